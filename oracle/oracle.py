@@ -1,0 +1,187 @@
+"""ctypes binding of the C oracle plus the oracle's own host-side derivations.
+
+TEST INFRASTRUCTURE ONLY: imported by tests, the smoke check and the
+benchmark's CPU-baseline leg; never by the product package.
+
+Every function follows the definitions of arXiv:2305.12161:
+  * update rule: T -> 0 Glauber acceptance (Methods, equation
+    equ:glauberAcceptance); one MCS = N proposals (Methods, rsf update);
+  * sweep order: checkerboard colour 0 then colour 1 every sweep (Methods,
+    "Checkerboard update"; Supplementary Methods I B, "01 cycle");
+  * C(r,t) = <s_i s_j> - <s_i><s_j> (Results, eq:correlation function),
+    here per lattice along the three axes, and ell from the intercept of C
+    with c = 0.5 (Results, dynamical-scaling paragraph).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i8p = ctypes.POINTER(ctypes.c_int8)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build_oracle
+        build_oracle.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.or_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+    lib.or_philox4x32_10.restype = None
+    lib.or_tie_bit.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint64]
+    lib.or_tie_bit.restype = ctypes.c_int
+    lib.or_init_bit.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.or_init_bit.restype = ctypes.c_int
+    lib.or_init.argtypes = [ctypes.c_int, ctypes.c_uint64, _i8p]
+    lib.or_init.restype = None
+    lib.or_half_sweep.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, _i8p]
+    lib.or_half_sweep.restype = ctypes.c_int64
+    lib.or_sweep.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, _i8p]
+    lib.or_sweep.restype = ctypes.c_int64
+    lib.or_bonds.argtypes = [ctypes.c_int, _i8p, _i64p]
+    lib.or_bonds.restype = None
+    lib.or_corr.argtypes = [ctypes.c_int, _i8p, _i64p, _i64p]
+    lib.or_corr.restype = None
+    lib.or_run.argtypes = [ctypes.c_int, ctypes.c_uint64, _i8p, ctypes.c_uint64, ctypes.c_uint64,
+                           ctypes.c_uint64, _i64p]
+    lib.or_run.restype = None
+    lib.or_window_advance.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_int, _i8p, ctypes.c_uint64,
+                                      ctypes.c_uint64]
+    lib.or_window_advance.restype = None
+    lib.or_set_threads.argtypes = [ctypes.c_int]
+    lib.or_set_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _i8(a):
+    assert a.dtype == np.int8 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_i8p)
+
+
+def _check_L(L):
+    if L < 4 or L % 2:
+        raise ValueError("the checkerboard needs an even L >= 4 under periodic boundaries")
+
+
+def set_threads(n: int = 0) -> int:
+    """Set the OpenMP thread count (0 keeps the current one); returns the count in use."""
+    return int(_load().or_set_threads(int(n)))
+
+
+def philox4x32_10(ctr, key):
+    """Raw Philox4x32-10 block: 4 counter words, 2 key words -> 4 output words."""
+    lib = _load()
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib.or_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def tie_bit(seed: int, t: int, p: int, j: int) -> int:
+    return int(_load().or_tie_bit(seed, t, p, j))
+
+
+def init_bit(seed: int, i: int) -> int:
+    return int(_load().or_init_bit(seed, i))
+
+
+def init(L: int, seed: int) -> np.ndarray:
+    """Infinite-temperature start: i.i.d. fair +-1 spins, shape (L, L, L) indexed [z, y, x]."""
+    _check_L(L)
+    s = np.empty((L, L, L), dtype=np.int8)
+    _load().or_init(L, seed, _i8(s))
+    return s
+
+
+def half_sweep(s: np.ndarray, seed: int, t: int, p: int) -> int:
+    """In-place half-sweep of colour p during sweep t; returns the number of flips."""
+    L = s.shape[0]
+    _check_L(L)
+    return int(_load().or_half_sweep(L, seed, t, p, _i8(s)))
+
+
+def sweep(s: np.ndarray, seed: int, t: int) -> int:
+    L = s.shape[0]
+    _check_L(L)
+    return int(_load().or_sweep(L, seed, t, _i8(s)))
+
+
+def bonds(s: np.ndarray) -> np.ndarray:
+    """Per-axis unsatisfied-bond counts [B_x, B_y, B_z]."""
+    L = s.shape[0]
+    B = np.zeros(3, dtype=np.int64)
+    _load().or_bonds(L, _i8(s), B.ctypes.data_as(_i64p))
+    return B
+
+
+def corr(s: np.ndarray):
+    """Axis correlation sums S[a, r] for r = 0..L/2 and magnetisation M."""
+    L = s.shape[0]
+    S = np.zeros((3, L // 2 + 1), dtype=np.int64)
+    M = np.zeros(1, dtype=np.int64)
+    _load().or_corr(L, _i8(s), S.ctypes.data_as(_i64p), M.ctypes.data_as(_i64p))
+    return S, int(M[0])
+
+
+def run(s: np.ndarray, seed: int, t0: int, n: int, every: int = 0) -> np.ndarray:
+    """Advance n sweeps in place from time t0; returns B(t0 + k*every) for k < n/every."""
+    L = s.shape[0]
+    _check_L(L)
+    if every > 0:
+        tr = np.zeros((n + every - 1) // every, dtype=np.int64)
+        ptr = tr.ctypes.data_as(_i64p)
+    else:
+        tr = np.zeros(0, dtype=np.int64)
+        ptr = None
+    _load().or_run(L, seed, _i8(s), t0, n, every, ptr)
+    return tr
+
+
+def window_advance(L: int, seed: int, origin, w: np.ndarray, t0: int, T: int) -> None:
+    """Advance a W^3 window (global corner `origin` = (ox, oy, oz)) by T sweeps in place.
+
+    Sites within local distance 2T of a face are not trustworthy afterwards.
+    """
+    W = w.shape[0]
+    ox, oy, oz = (int(v) for v in origin)
+    _load().or_window_advance(L, seed, ox, oy, oz, W, _i8(w), t0, T)
+
+
+# --------------------------------------------------------------------------
+# Host-side derivations (double precision), written for the oracle only.
+# --------------------------------------------------------------------------
+def ell_energy(B: int, N: int) -> float:
+    """Energy-excess length 3N/B (mean chord between walls along an axis); +inf if B = 0."""
+    return float("inf") if B == 0 else 3.0 * N / float(B)
+
+
+def connected_corr(S: np.ndarray, M: int, N: int) -> np.ndarray:
+    """C_a(r) = S_a(r)/N - (M/N)^2, shape (3, L/2+1)."""
+    m = M / float(N)
+    return S.astype(np.float64) / float(N) - m * m
+
+
+def ell_intercept(S: np.ndarray, M: int, N: int, c: float = 0.5) -> float:
+    """Linear-interpolated first crossing of the axis-averaged C(r) with c.
+
+    Returns nan when C(0) <= c (no length defined) and inf when C stays >= c
+    up to r = L/2 (saturated).
+    """
+    Cbar = connected_corr(S, M, N).mean(axis=0)
+    if not Cbar[0] > c:
+        return float("nan")
+    for r in range(1, Cbar.shape[0]):
+        if Cbar[r] < c:
+            return (r - 1) + (Cbar[r - 1] - c) / (Cbar[r - 1] - Cbar[r])
+    return float("inf")
