@@ -1,0 +1,152 @@
+/*
+ * quench.h -- C ABI of libquench, the MI355X (gfx950) library for the
+ * zero-temperature single-spin-flip quench of the d=3 nearest-neighbour Ising
+ * model with checkerboard updates (Gessert, Christiansen, Janke,
+ * arXiv:2305.12161).
+ *
+ * Model (Methods, "Spin updates"): spins s = +-1 on a periodic L^3 simple-cubic
+ * lattice, ferromagnetic coupling J = 1, k_B = 1.  A proposal to flip s_i with
+ * a anti-aligned neighbours changes the energy by dE = 12 - 4a and is accepted
+ * with the T -> 0 Glauber probability (Methods, equation
+ * equ:glauberAcceptance): always if dE < 0 (a >= 4), with probability 1/2 if
+ * dE = 0 (a == 3), never if dE > 0.
+ *
+ * Sweep (Methods, "Checkerboard update"; Supplementary Methods I B): all
+ * sites of colour 0, (x+y+z) even, are updated concurrently, then all sites of
+ * colour 1; the same "01 cycle" order every sweep.  One sweep is N = L^3
+ * proposals, one Monte Carlo sweep (MCS).
+ *
+ * Random bits (the paper names no generator; this is the library's contract):
+ * Philox4x32-10 (Salmon et al., SC'11) with key (seed mod 2^32, seed >> 32).
+ *   lattice index  i = x + L*(y + L*z);  colour index j = x/2 + (L/2)*(y + L*z)
+ *   tie bit of a colour-p site during 0-based sweep t:
+ *       counter (j/128, t, p, 0), bit (w[(j>>5)&3] >> (j&31)) & 1, flip iff 1
+ *   initial spin of site i (infinite-temperature start, Results):
+ *       counter (i/128, 0, 0, 1), bit (w[(i>>5)&3] >> (i&31)) & 1, +1 iff 1
+ * Results are therefore a pure function of (L, seed, t): they do not depend on
+ * the layout, tiling, batching or anything else running on the device.
+ *
+ * Measurements:
+ *   B(t)   unsigned count of unsatisfied bonds, B = sum over axes a of
+ *          #{i : s_i != s_{i+e_a}}; energy E = -(3N - 2B).  The paper measures
+ *          length through C(r,t); 3N/B (energy-excess length) is an addition.
+ *   S_a(r) = sum_i s_i s_{i + r e_a} for r = 0..L/2 and a = x, y, z, and
+ *   M      = sum_i s_i: the integer pieces of the two-point function
+ *          C(r,t) = <s_i s_j> - <s_i><s_j> (Results, eq:correlation function)
+ *          along the axes.  ell is where C crosses 1/2 (Results).
+ *
+ * Conventions for every entry point:
+ *   Memory   -- device memory is owned by the caller (e.g. a torch tensor) and
+ *               must outlive the handle; the library allocates no device
+ *               memory.  Host arrays are caller-allocated.
+ *   Streams  -- all device work is enqueued on the stream given at creation.
+ *               Calls that return host data synchronise that stream; the others
+ *               are asynchronous.
+ *   Errors   -- every call returns a qz_status; nothing is thrown across the
+ *               ABI.  qz_last_error() gives the text of the calling thread's
+ *               last failure.  After a QZ_EDEVICE failure the handle answers
+ *               QZ_ESTATE to everything but qz_destroy.
+ *   Threads  -- a handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef QUENCH_H
+#define QUENCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QZ_ABI_VERSION 1
+
+typedef enum {
+    QZ_OK = 0,
+    QZ_EINVAL = -1,       /* bad argument: L odd or < 4, null pointer, bad layout, ...   */
+    QZ_ENOMEM = -2,       /* caller's device buffer smaller than qz_state_bytes()        */
+    QZ_EDEVICE = -3,      /* a HIP call failed; text in qz_last_error()                  */
+    QZ_ESTATE = -4,       /* handle unusable after an earlier device failure             */
+    QZ_EUNSUPPORTED = -5  /* the layout cannot hold this L (see qz_layout)               */
+} qz_status;
+
+/* Spin storage.
+ *   QZ_LAYOUT_I8:  one int8 (+1/-1) per site, index i; any even L >= 4.
+ *   QZ_LAYOUT_BIT: one bit per site (1 = +1), colour-separated: plane c holds
+ *                  the colour-c sites as words [z][y][L/64] of 32 bits, bit b of
+ *                  word w = site x = 64w + 2b + ((c+y+z)&1).  Needs L % 64 == 0.
+ *                  Two copies (read / write) are kept so that both colours of a
+ *                  sweep are updated in one pass over memory. */
+typedef enum { QZ_LAYOUT_I8 = 0, QZ_LAYOUT_BIT = 1 } qz_layout;
+
+typedef struct qz_lattice qz_lattice; /* opaque, library-owned host object */
+
+/* ABI version of the loaded library (QZ_ABI_VERSION when it matches this header). */
+int qz_abi_version(void);
+
+/* Device bytes a lattice of side L needs in `layout`, spins plus counters and
+ * staging space; 0 if L or layout is invalid for the layout. */
+size_t qz_state_bytes(uint32_t L, int layout);
+
+/* Create a lattice of side L in caller memory dev_mem (dev_bytes >=
+ * qz_state_bytes) and draw the infinite-temperature start from `seed`
+ * (Results: random configurations, m close to 0); t := 0.  hip_stream is a
+ * hipStream_t (NULL = the default stream).  Errors: QZ_EINVAL, QZ_ENOMEM,
+ * QZ_EUNSUPPORTED, QZ_EDEVICE. */
+int qz_create(uint32_t L, uint64_t seed, int layout, void *dev_mem, size_t dev_bytes,
+              void *hip_stream, qz_lattice **out);
+
+/* Release the host object (the caller's device memory is left alone). */
+int qz_destroy(qz_lattice *q);
+
+/* Advance n_sweeps MCS from the current time t0.  If trace_every > 0 (and
+ * n_sweeps % trace_every == 0), host_trace receives n_sweeps/trace_every
+ * values B(t0 + k*trace_every), each the bond count of the state at the start
+ * of that sweep, computed inside the sweep itself; this call then synchronises.
+ * With trace_every == 0 it is asynchronous.  Errors: QZ_EINVAL, QZ_ESTATE,
+ * QZ_EDEVICE. */
+int qz_run(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64_t *host_trace);
+
+/* As qz_run, but the trace goes to caller device memory dev_trace
+ * (n_sweeps/trace_every uint64 values, zeroed by the library) and the call
+ * never synchronises. */
+int qz_run_device(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64_t *dev_trace);
+
+/* Per-axis unsatisfied-bond counts [B_x, B_y, B_z] of the current state. */
+int qz_bonds(qz_lattice *q, uint64_t out_B_axes[3]);
+
+/* Axis correlation sums of the current state: out_S[a*(L/2+1) + r] = S_a(r)
+ * for a = 0 (x), 1 (y), 2 (z) and r = 0..L/2, and *out_M = M. */
+int qz_corr(qz_lattice *q, int64_t *out_S, int64_t *out_M);
+
+/* Current time t (completed sweeps). */
+int qz_time(const qz_lattice *q, uint64_t *t);
+
+/* Copy the whole lattice to host as int8 +-1, index i (N = L^3 bytes). */
+int qz_download_spins(qz_lattice *q, int8_t *host);
+
+/* Replace the lattice by host int8 values (each must be +1 or -1, else
+ * QZ_EINVAL and the state is unspecified) and set the time to t (used for
+ * special initial states and for resuming from a checkpoint). */
+int qz_upload_spins(qz_lattice *q, const int8_t *host, uint64_t t);
+
+/* Copy a W^3 cube whose corner is at global origin[0..2] = (x, y, z), taken
+ * periodically, to host as int8, local x fastest.  1 <= W <= L. */
+int qz_download_window(qz_lattice *q, const uint32_t origin[3], uint32_t W, int8_t *host);
+
+/* Tuning of the fused one-pass sweep of the bit layout: V 32-bit words per
+ * lane along x (1, 2 or 4, dividing L/64), Ty rows of y per tile (Ty == L
+ * means whole planes with no halo rows) and Tz planes of z per tile.  Results
+ * never depend on the tuning.  QZ_EINVAL if the triple does not fit this L
+ * (at most 1024 threads and 64 KiB of LDS per workgroup); QZ_EUNSUPPORTED for
+ * the int8 layout, which has no tuning. */
+int qz_set_tuning(qz_lattice *q, int V, int Ty, int Tz);
+int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
+
+/* Text for a status code, and the calling thread's last error message. */
+const char *qz_status_string(int status);
+const char *qz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QUENCH_H */

@@ -57,6 +57,9 @@ def _load():
                                       ctypes.c_int, ctypes.c_int, _i8p, ctypes.c_uint64,
                                       ctypes.c_uint64]
     lib.or_window_advance.restype = None
+    lib.or_init_window.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, _i8p]
+    lib.or_init_window.restype = None
     lib.or_set_threads.argtypes = [ctypes.c_int]
     lib.or_set_threads.restype = ctypes.c_int
     _lib = lib
@@ -102,6 +105,15 @@ def init(L: int, seed: int) -> np.ndarray:
     s = np.empty((L, L, L), dtype=np.int8)
     _load().or_init(L, seed, _i8(s))
     return s
+
+
+def init_window(L: int, seed: int, origin, W: int) -> np.ndarray:
+    """The infinite-temperature start of the L^3 lattice restricted to a W^3 window."""
+    _check_L(L)
+    w = np.empty((W, W, W), dtype=np.int8)
+    ox, oy, oz = (int(v) % L for v in origin)
+    _load().or_init_window(L, seed, ox, oy, oz, W, _i8(w))
+    return w
 
 
 def half_sweep(s: np.ndarray, seed: int, t: int, p: int) -> int:

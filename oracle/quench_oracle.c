@@ -125,6 +125,20 @@ void or_init(int L, uint64_t seed, int8_t *s)
         s[i] = or_init_bit(seed, (uint64_t)i) ? (int8_t)1 : (int8_t)-1;
 }
 
+/* The same start restricted to a W^3 window with global corner (ox, oy, oz),
+ * taken periodically; w is indexed like a lattice of side W. */
+void or_init_window(int L, uint64_t seed, int ox, int oy, int oz, int W, int8_t *w)
+{
+#pragma omp parallel for schedule(static)
+    for (int lz = 0; lz < W; ++lz)
+        for (int ly = 0; ly < W; ++ly)
+            for (int lx = 0; lx < W; ++lx) {
+                int gx = (ox + lx) % L, gy = (oy + ly) % L, gz = (oz + lz) % L;
+                w[or_idx(W, lx, ly, lz)] =
+                    or_init_bit(seed, (uint64_t)or_idx(L, gx, gy, gz)) ? (int8_t)1 : (int8_t)-1;
+            }
+}
+
 /* ------------------------------------------------------------------------ */
 /* One half-sweep over colour p (Methods, "Checkerboard update"), each       */
 /* proposal accepted by the T -> 0 limit of the Glauber probability          */

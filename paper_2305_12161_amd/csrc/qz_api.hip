@@ -1,0 +1,468 @@
+// qz_api.hip -- the C ABI declared in include/quench.h.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "../../include/quench.h"
+#include "qz_internal.hpp"
+
+#define QZ_EXPORT extern "C" __attribute__((visibility("default")))
+
+struct qz_lattice {
+    uint32_t L;
+    uint64_t seed;
+    int layout;
+    uint64_t t;
+    uint8_t *base;
+    size_t bytes;
+    hipStream_t st;
+    qz::StateMap map;
+    int cur;                 // bit layout: which copy holds the current state
+    qz::BitTuning tune;
+    bool failed;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string &msg)
+{
+    g_last_error = msg;
+    return status;
+}
+
+int device_fail(qz_lattice *q, hipError_t e, const char *where)
+{
+    if (q)
+        q->failed = true;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+    return fail(QZ_EDEVICE, buf);
+}
+
+#define QZ_HIP(q, call)                                   \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess)                             \
+            return device_fail((q), e_, #call);           \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool layout_ok(uint32_t L, int layout)
+{
+    if (L < 4 || (L & 1u))
+        return false;
+    if (layout == QZ_LAYOUT_I8)
+        return L <= 4096;
+    if (layout == QZ_LAYOUT_BIT)
+        return L % 64 == 0 && L <= 4096;
+    return false;
+}
+
+uint64_t n_sites(uint32_t L) { return (uint64_t)L * L * L; }
+
+int8_t *i8_spins(qz_lattice *q) { return reinterpret_cast<int8_t *>(q->base + q->map.spins_off); }
+
+uint32_t *bit_plane(qz_lattice *q, int copy, int colour)
+{
+    const size_t plane_bytes = n_sites(q->L) / 16;
+    return reinterpret_cast<uint32_t *>(q->base + q->map.spins_off +
+                                        (size_t)copy * 2 * plane_bytes +
+                                        (size_t)colour * plane_bytes);
+}
+
+unsigned long long *counters(qz_lattice *q)
+{
+    return reinterpret_cast<unsigned long long *>(q->base + q->map.counter_off);
+}
+
+int check_handle(qz_lattice *q)
+{
+    if (!q)
+        return fail(QZ_EINVAL, "null handle");
+    if (q->failed)
+        return fail(QZ_ESTATE, "handle unusable after an earlier device failure");
+    return QZ_OK;
+}
+
+// One sweep of the current state; bond_acc (device, may be null) receives the
+// bond count of the state entering the sweep.
+int sweep_once(qz_lattice *q, unsigned long long *bond_acc)
+{
+    const uint32_t t = (uint32_t)q->t;
+    if (q->layout == QZ_LAYOUT_I8) {
+        QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 0, i8_spins(q), bond_acc));
+        QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 1, i8_spins(q), nullptr));
+    } else {
+        const int a = q->cur, b = 1 - q->cur;
+        QZ_HIP(q, qz::bit_sweep(q->st, q->L, q->seed, t, q->tune, bit_plane(q, a, 0),
+                                bit_plane(q, a, 1), bit_plane(q, b, 0), bit_plane(q, b, 1),
+                                bond_acc));
+        q->cur = b;
+    }
+    q->t += 1;
+    return QZ_OK;
+}
+
+int run_impl(qz_lattice *q, uint64_t n, uint64_t every, unsigned long long *dev_trace)
+{
+    for (uint64_t k = 0; k < n; ++k) {
+        unsigned long long *acc = nullptr;
+        if (every > 0 && dev_trace != nullptr && k % every == 0)
+            acc = dev_trace + k / every;
+        int rc = sweep_once(q, acc);
+        if (rc != QZ_OK)
+            return rc;
+    }
+    return QZ_OK;
+}
+
+}  // namespace
+
+namespace qz {
+bool state_map(uint32_t L, int layout, StateMap *m)
+{
+    if (!layout_ok(L, layout))
+        return false;
+    const uint64_t N = n_sites(L);
+    size_t off = 0;
+    m->spins_off = off;
+    m->spins_bytes = (layout == QZ_LAYOUT_I8) ? (size_t)N : (size_t)(N / 8) * 2;
+    off = align256(off + m->spins_bytes);
+    m->counter_off = off;
+    off = align256(off + 64 * 8);
+    m->corr_off = off;
+    off = align256(off + (size_t)(3 * (L / 2 + 1) + 1) * 8);
+    m->trace_off = off;
+    off = align256(off + kTraceCap * 8);
+    m->stage_off = off;
+    m->stage_bytes = std::min<size_t>((size_t)N, kStageMax);
+    m->stage_bytes = std::max<size_t>(m->stage_bytes, (size_t)L * L);
+    off = align256(off + m->stage_bytes);
+    m->total = off;
+    return true;
+}
+}  // namespace qz
+
+QZ_EXPORT int qz_abi_version(void) { return QZ_ABI_VERSION; }
+
+QZ_EXPORT size_t qz_state_bytes(uint32_t L, int layout)
+{
+    qz::StateMap m;
+    return qz::state_map(L, layout, &m) ? m.total : 0;
+}
+
+QZ_EXPORT int qz_create(uint32_t L, uint64_t seed, int layout, void *dev_mem, size_t dev_bytes,
+                        void *hip_stream, qz_lattice **out)
+{
+    if (!out)
+        return fail(QZ_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (layout != QZ_LAYOUT_I8 && layout != QZ_LAYOUT_BIT)
+        return fail(QZ_EINVAL, "unknown layout");
+    if (L < 4 || (L & 1u))
+        return fail(QZ_EINVAL, "L must be even and >= 4");
+    if (!layout_ok(L, layout))
+        return fail(QZ_EUNSUPPORTED, "the bit layout needs L % 64 == 0 (and L <= 4096)");
+    if (!dev_mem)
+        return fail(QZ_EINVAL, "null device buffer");
+    if ((reinterpret_cast<uintptr_t>(dev_mem) & 255u) != 0)
+        return fail(QZ_EINVAL, "device buffer must be 256-byte aligned");
+    qz::StateMap m;
+    qz::state_map(L, layout, &m);
+    if (dev_bytes < m.total)
+        return fail(QZ_ENOMEM, "device buffer smaller than qz_state_bytes()");
+    qz_lattice *q = new (std::nothrow) qz_lattice();
+    if (!q)
+        return fail(QZ_ENOMEM, "host allocation failed");
+    q->L = L;
+    q->seed = seed;
+    q->layout = layout;
+    q->t = 0;
+    q->base = reinterpret_cast<uint8_t *>(dev_mem);
+    q->bytes = dev_bytes;
+    q->st = reinterpret_cast<hipStream_t>(hip_stream);
+    q->map = m;
+    q->cur = 0;
+    q->failed = false;
+    if (layout == QZ_LAYOUT_BIT)
+        q->tune = qz::bit_tuning_default(L);
+    hipError_t e;
+    if (layout == QZ_LAYOUT_I8)
+        e = qz::i8_init(q->st, L, seed, i8_spins(q));
+    else
+        e = qz::bit_init(q->st, L, seed, bit_plane(q, 0, 0), bit_plane(q, 0, 1));
+    if (e != hipSuccess) {
+        int rc = device_fail(nullptr, e, "init kernel");
+        delete q;
+        return rc;
+    }
+    *out = q;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_destroy(qz_lattice *q)
+{
+    if (!q)
+        return fail(QZ_EINVAL, "null handle");
+    delete q;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_run(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64_t *host_trace)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if (trace_every == 0)
+        return run_impl(q, n_sweeps, 0, nullptr);
+    if (!host_trace)
+        return fail(QZ_EINVAL, "null trace buffer");
+    if (n_sweeps % trace_every)
+        return fail(QZ_EINVAL, "n_sweeps must be a multiple of trace_every");
+    unsigned long long *slots =
+        reinterpret_cast<unsigned long long *>(q->base + q->map.trace_off);
+    const uint64_t points = n_sweeps / trace_every;
+    uint64_t done = 0;
+    while (done < points) {
+        const uint64_t chunk = std::min<uint64_t>(points - done, qz::kTraceCap);
+        QZ_HIP(q, qz::fill_u64(q->st, slots, chunk, 0ull));
+        rc = run_impl(q, chunk * trace_every, trace_every, slots);
+        if (rc != QZ_OK)
+            return rc;
+        QZ_HIP(q, hipMemcpyAsync(host_trace + done, slots, chunk * 8, hipMemcpyDeviceToHost,
+                                 q->st));
+        QZ_HIP(q, hipStreamSynchronize(q->st));
+        done += chunk;
+    }
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_run_device(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every,
+                            uint64_t *dev_trace)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if (trace_every == 0)
+        return run_impl(q, n_sweeps, 0, nullptr);
+    if (!dev_trace)
+        return fail(QZ_EINVAL, "null trace buffer");
+    if (n_sweeps % trace_every)
+        return fail(QZ_EINVAL, "n_sweeps must be a multiple of trace_every");
+    unsigned long long *slots = reinterpret_cast<unsigned long long *>(dev_trace);
+    QZ_HIP(q, qz::fill_u64(q->st, slots, n_sweeps / trace_every, 0ull));
+    return run_impl(q, n_sweeps, trace_every, slots);
+}
+
+QZ_EXPORT int qz_bonds(qz_lattice *q, uint64_t out_B_axes[3])
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if (!out_B_axes)
+        return fail(QZ_EINVAL, "null output");
+    unsigned long long *c = counters(q);
+    QZ_HIP(q, qz::fill_u64(q->st, c, 3, 0ull));
+    if (q->layout == QZ_LAYOUT_I8)
+        QZ_HIP(q, qz::i8_bonds(q->st, q->L, i8_spins(q), c));
+    else
+        QZ_HIP(q, qz::bit_bonds(q->st, q->L, bit_plane(q, q->cur, 0), bit_plane(q, q->cur, 1), c));
+    unsigned long long h[3];
+    QZ_HIP(q, hipMemcpyAsync(h, c, sizeof h, hipMemcpyDeviceToHost, q->st));
+    QZ_HIP(q, hipStreamSynchronize(q->st));
+    for (int a = 0; a < 3; ++a)
+        out_B_axes[a] = h[a];
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_corr(qz_lattice *q, int64_t *out_S, int64_t *out_M)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if (!out_S || !out_M)
+        return fail(QZ_EINVAL, "null output");
+    const uint32_t R = q->L / 2 + 1;
+    const size_t nvals = 3 * (size_t)R + 1;
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(q->base + q->map.corr_off);
+    QZ_HIP(q, qz::fill_u64(q->st, acc, nvals, 0ull));
+    if (q->layout == QZ_LAYOUT_I8)
+        QZ_HIP(q, qz::i8_corr(q->st, q->L, i8_spins(q), reinterpret_cast<long long *>(acc),
+                              reinterpret_cast<long long *>(acc + 3 * R)));
+    else
+        QZ_HIP(q, qz::bit_corr(q->st, q->L, bit_plane(q, q->cur, 0), bit_plane(q, q->cur, 1), acc,
+                               acc + 3 * R));
+    unsigned long long *h = new (std::nothrow) unsigned long long[nvals];
+    if (!h)
+        return fail(QZ_ENOMEM, "host allocation failed");
+    hipError_t e = hipMemcpyAsync(h, acc, nvals * 8, hipMemcpyDeviceToHost, q->st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(q->st);
+    if (e != hipSuccess) {
+        delete[] h;
+        return device_fail(q, e, "qz_corr copy");
+    }
+    const int64_t N = (int64_t)n_sites(q->L);
+    if (q->layout == QZ_LAYOUT_I8) {
+        for (size_t k = 0; k < 3 * (size_t)R; ++k)
+            out_S[k] = (int64_t)h[k];
+        *out_M = (int64_t)h[3 * R];
+    } else {
+        // anti-aligned pair counts -> S = N - 2*anti; up-spin count -> M = 2*ones - N
+        for (size_t k = 0; k < 3 * (size_t)R; ++k)
+            out_S[k] = N - 2 * (int64_t)h[k];
+        *out_M = 2 * (int64_t)h[3 * R] - N;
+    }
+    delete[] h;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_time(const qz_lattice *q, uint64_t *t)
+{
+    if (!q || !t)
+        return fail(QZ_EINVAL, "null argument");
+    *t = q->t;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_download_spins(qz_lattice *q, int8_t *host)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if (!host)
+        return fail(QZ_EINVAL, "null output");
+    const uint32_t L = q->L;
+    const uint64_t N = n_sites(L);
+    if (q->layout == QZ_LAYOUT_I8) {
+        QZ_HIP(q, hipMemcpyAsync(host, i8_spins(q), N, hipMemcpyDeviceToHost, q->st));
+        QZ_HIP(q, hipStreamSynchronize(q->st));
+        return QZ_OK;
+    }
+    int8_t *stage = reinterpret_cast<int8_t *>(q->base + q->map.stage_off);
+    const uint64_t plane = (uint64_t)L * L;
+    const uint32_t nzc = (uint32_t)std::max<uint64_t>(1, q->map.stage_bytes / plane);
+    for (uint32_t z0 = 0; z0 < L; z0 += nzc) {
+        const uint32_t nz = std::min<uint32_t>(nzc, L - z0);
+        QZ_HIP(q, qz::bit_unpack(q->st, L, bit_plane(q, q->cur, 0), bit_plane(q, q->cur, 1), z0,
+                                 nz, stage));
+        QZ_HIP(q, hipMemcpyAsync(host + (uint64_t)z0 * plane, stage, (size_t)nz * plane,
+                                 hipMemcpyDeviceToHost, q->st));
+        QZ_HIP(q, hipStreamSynchronize(q->st));
+    }
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_upload_spins(qz_lattice *q, const int8_t *host, uint64_t t)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if (!host)
+        return fail(QZ_EINVAL, "null input");
+    const uint32_t L = q->L;
+    const uint64_t N = n_sites(L);
+    unsigned long long *bad = counters(q) + 3;
+    QZ_HIP(q, qz::fill_u64(q->st, bad, 1, 0ull));
+    if (q->layout == QZ_LAYOUT_I8) {
+        QZ_HIP(q, hipMemcpyAsync(i8_spins(q), host, N, hipMemcpyHostToDevice, q->st));
+        QZ_HIP(q, qz::i8_check_pm1(q->st, N, i8_spins(q), bad));
+    } else {
+        int8_t *stage = reinterpret_cast<int8_t *>(q->base + q->map.stage_off);
+        const uint64_t plane = (uint64_t)L * L;
+        const uint32_t nzc = (uint32_t)std::max<uint64_t>(1, q->map.stage_bytes / plane);
+        for (uint32_t z0 = 0; z0 < L; z0 += nzc) {
+            const uint32_t nz = std::min<uint32_t>(nzc, L - z0);
+            QZ_HIP(q, hipMemcpyAsync(stage, host + (uint64_t)z0 * plane, (size_t)nz * plane,
+                                     hipMemcpyHostToDevice, q->st));
+            QZ_HIP(q, qz::bit_pack(q->st, L, bit_plane(q, q->cur, 0), bit_plane(q, q->cur, 1), z0,
+                                   nz, stage, bad));
+            // the stage is reused by the next chunk: wait for this pack to finish
+            QZ_HIP(q, hipStreamSynchronize(q->st));
+        }
+    }
+    unsigned long long nbad = 0;
+    QZ_HIP(q, hipMemcpyAsync(&nbad, bad, 8, hipMemcpyDeviceToHost, q->st));
+    QZ_HIP(q, hipStreamSynchronize(q->st));
+    q->t = t;
+    if (nbad)
+        return fail(QZ_EINVAL, "uploaded spins must all be +1 or -1");
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_download_window(qz_lattice *q, const uint32_t origin[3], uint32_t W, int8_t *host)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if (!origin || !host)
+        return fail(QZ_EINVAL, "null argument");
+    const uint32_t L = q->L;
+    if (W < 1 || W > L)
+        return fail(QZ_EINVAL, "window side must be in [1, L]");
+    const uint32_t ox = origin[0] % L, oy = origin[1] % L, oz = origin[2] % L;
+    int8_t *stage = reinterpret_cast<int8_t *>(q->base + q->map.stage_off);
+    const uint64_t plane = (uint64_t)W * W;
+    const uint32_t nzc = (uint32_t)std::max<uint64_t>(1, q->map.stage_bytes / plane);
+    for (uint32_t lz0 = 0; lz0 < W; lz0 += nzc) {
+        const uint32_t nz = std::min<uint32_t>(nzc, W - lz0);
+        if (q->layout == QZ_LAYOUT_I8)
+            QZ_HIP(q, qz::i8_window(q->st, L, i8_spins(q), ox, oy, oz, W, lz0, nz, stage));
+        else
+            QZ_HIP(q, qz::bit_window(q->st, L, bit_plane(q, q->cur, 0), bit_plane(q, q->cur, 1),
+                                     ox, oy, oz, W, lz0, nz, stage));
+        QZ_HIP(q, hipMemcpyAsync(host + (uint64_t)lz0 * plane, stage, (size_t)nz * plane,
+                                 hipMemcpyDeviceToHost, q->st));
+        QZ_HIP(q, hipStreamSynchronize(q->st));
+    }
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_set_tuning(qz_lattice *q, int V, int Ty, int Tz)
+{
+    if (!q)
+        return fail(QZ_EINVAL, "null handle");
+    if (q->layout != QZ_LAYOUT_BIT)
+        return fail(QZ_EUNSUPPORTED, "only the bit layout has a tuning");
+    qz::BitTuning t;
+    t.V = V;
+    t.Ty = Ty;
+    t.Tz = Tz;
+    if (!qz::bit_tuning_valid(q->L, t))
+        return fail(QZ_EINVAL, "tuning does not fit this lattice size");
+    q->tune = t;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3])
+{
+    if (!q || !out_V_Ty_Tz)
+        return fail(QZ_EINVAL, "null argument");
+    if (q->layout != QZ_LAYOUT_BIT)
+        return fail(QZ_EUNSUPPORTED, "only the bit layout has a tuning");
+    out_V_Ty_Tz[0] = q->tune.V;
+    out_V_Ty_Tz[1] = q->tune.Ty;
+    out_V_Ty_Tz[2] = q->tune.Tz;
+    return QZ_OK;
+}
+
+QZ_EXPORT const char *qz_status_string(int status)
+{
+    switch (status) {
+    case QZ_OK: return "ok";
+    case QZ_EINVAL: return "invalid argument";
+    case QZ_ENOMEM: return "device buffer too small";
+    case QZ_EDEVICE: return "device error";
+    case QZ_ESTATE: return "handle unusable after an earlier device failure";
+    case QZ_EUNSUPPORTED: return "layout cannot hold this lattice size";
+    default: return "unknown status";
+    }
+}
+
+QZ_EXPORT const char *qz_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,740 @@
+// qz_bit.hip -- kernels for the 1-bit, colour-separated layout.
+//
+// Plane c (c = 0, 1) holds the colour-c sites as 32-bit words
+//   P_c[(z*L + y)*W + w],  W = L/64,
+// bit b of word w being the site x = 64w + 2b + pi with pi = (c + y + z) & 1
+// (all colour-c sites of one row share the parity of x).  A colour-c site at
+// x = 2k + pi has its two x-neighbours at colour indices k and k-1 (pi = 0) or
+// k and k+1 (pi = 1) of the other colour's same row; its y- and z-neighbours
+// are bit k of the other colour's rows (y+-1, z) and (y, z+-1).  The word index
+// g = (z*L + y)*W + w equals j/32 for the colour index j of the contract, so the
+// tie bits of word g are word (g & 3) of the Philox block g >> 2.
+//
+// The sweep (colour 0 then colour 1, Methods "Checkerboard update") is fused
+// into ONE pass over memory that reads copy A and writes copy B: a workgroup
+// owns a tile of Ty rows x all of x x Tz planes and streams it along z.  At
+// plane step q it updates colour 0 of plane q (from old colour 1 of planes
+// q-1, q, q+1) and then colour 1 of plane q-1 (from the new colour 0 of planes
+// q-2, q-1, q), so each word is read once and written once per sweep.  The
+// new colour 0 is recomputed for one halo row on each side and one halo plane
+// at each end of the tile (from copy A, so tiles never race).  Rows are
+// exchanged through LDS, one barrier per plane step.
+#include "qz_device.hpp"
+#include "qz_internal.hpp"
+
+namespace qz {
+namespace {
+
+// --------------------------------------------------------------------------
+// vector load/store of V consecutive words
+// --------------------------------------------------------------------------
+template <int V> struct VecT;
+template <> struct VecT<1> { using T = uint32_t; };
+template <> struct VecT<2> { using T = uint2; };
+template <> struct VecT<4> { using T = uint4; };
+
+template <int V>
+__device__ __forceinline__ void load_words(const uint32_t *p, uint32_t (&r)[V])
+{
+    if constexpr (V == 4) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+    } else if constexpr (V == 2) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p);
+        r[0] = v.x; r[1] = v.y;
+    } else {
+        r[0] = *p;
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void store_words(uint32_t *p, const uint32_t (&r)[V])
+{
+    if constexpr (V == 4) {
+        *reinterpret_cast<uint4 *>(p) = make_uint4(r[0], r[1], r[2], r[3]);
+    } else if constexpr (V == 2) {
+        *reinterpret_cast<uint2 *>(p) = make_uint2(r[0], r[1]);
+    } else {
+        *p = r[0];
+    }
+}
+
+struct SweepArgs {
+    const uint32_t *S0, *S1;   // read copy, colour planes 0 and 1
+    uint32_t *D0, *D1;         // write copy
+    unsigned long long *bond_acc;
+    uint32_t L, W, R;          // R = W / V lanes per row
+    uint32_t Ty, E, Tz, nty;   // E = rows held per tile (Ty + 4, or L for whole planes)
+    uint32_t whole;            // 1 when a tile is a whole plane (no y halo)
+    uint32_t k0, k1, t;
+};
+
+// Update V words of one colour.  own = the words being updated; same = the
+// other colour's same-row words (x-neighbour at the same index); adj = the
+// word just outside the lane's range on the side given by pi; ym/yp/zm/zp the
+// other colour's rows y-1, y+1 and planes z-1, z+1.
+template <int V>
+__device__ __forceinline__ void update_words(const uint32_t (&own)[V], const uint32_t (&same)[V],
+                                             uint32_t adj, uint32_t pi, const uint32_t (&ym)[V],
+                                             const uint32_t (&yp)[V], const uint32_t (&zm)[V],
+                                             const uint32_t (&zp)[V], uint32_t k0, uint32_t k1,
+                                             uint32_t ctr0, uint32_t sub, uint32_t t, uint32_t p,
+                                             uint32_t (&out)[V], uint32_t &cnt0, uint32_t &cnt1,
+                                             uint32_t &cnt2)
+{
+    Counts c[V];
+    uint32_t ties = 0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        uint32_t shifted;
+        if (pi == 0u) {
+            // neighbour at k-1: bits move up by one, bit 0 from the word below
+            const uint32_t lo = (v > 0) ? same[v > 0 ? v - 1 : 0] : adj;
+            shifted = funnel(same[v], lo, 31);
+        } else {
+            // neighbour at k+1: bits move down by one, bit 31 from the word above
+            const uint32_t hi = (v < V - 1) ? same[v < V - 1 ? v + 1 : 0] : adj;
+            shifted = funnel(hi, same[v], 1);
+        }
+        c[v] = count_antialigned(own[v], same[v], shifted, ym[v], yp[v], zm[v], zp[v]);
+        ties |= tie_mask(c[v]);
+    }
+    uint32_t r[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        r[v] = 0u;
+    if (ties != 0u) {
+        const Words4 rb = philox10(ctr0 >> 2, t, p, 0u, k0, k1);
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            r[v] = rb.w[(sub + v) & 3];
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        out[v] = apply_rule(own[v], c[v], r[v]);
+        cnt0 += __builtin_popcount(c[v].a0);
+        cnt1 += __builtin_popcount(c[v].a1);
+        cnt2 += __builtin_popcount(c[v].a2);
+    }
+}
+
+template <int V>
+__global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
+{
+    extern __shared__ uint32_t lds[];
+    const uint32_t L = A.L, W = A.W, E = A.E;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t e = tid / A.R;               // held row
+    const uint32_t w0 = (tid % A.R) * V;        // first word of this lane
+
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t ty = tile % A.nty, tz = tile / A.nty;
+    const uint32_t y0 = ty * A.Ty, z0 = tz * A.Tz;
+    const uint32_t Tya = min(A.Ty, L - y0), Tza = min(A.Tz, L - z0);
+    const uint32_t Ea = A.whole ? L : Tya + 4;
+
+    const bool held = e < Ea;
+    bool c0_row, owned;
+    uint32_t y, em, ep;
+    if (A.whole) {
+        y = e;
+        c0_row = held;
+        owned = held;
+        em = (e == 0) ? L - 1 : e - 1;
+        ep = (e + 1 == L) ? 0 : e + 1;
+    } else {
+        y = (y0 + L - 2 + e) % L;
+        c0_row = held && e >= 1 && e + 2 <= Ea;
+        owned = held && e >= 2 && e + 3 <= Ea;
+        em = e - 1;
+        ep = e + 1;
+    }
+    const uint32_t wprev = (w0 + W - 1) % W, wnext = (w0 + V) % W;
+    const size_t row_words = (size_t)W;
+    const size_t plane_words = (size_t)L * W;
+
+    uint32_t c1m[V], c1c[V], c1p[V], c0o[V], n0m2[V], n0m1[V], n0c[V], c1n[V];
+    uint32_t pf1[V], pf0[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        c1m[v] = c1c[v] = c1p[v] = c0o[v] = n0m2[v] = n0m1[v] = n0c[v] = c1n[v] = 0u;
+        pf1[v] = pf0[v] = 0u;
+    }
+    auto off = [&](uint32_t z) -> size_t { return (size_t)z * plane_words + (size_t)y * row_words + w0; };
+
+    if (held) {
+        load_words<V>(A.S1 + off((z0 + L - 2) % L), c1m);
+        load_words<V>(A.S1 + off((z0 + L - 1) % L), c1c);
+        load_words<V>(A.S1 + off(z0 % L), c1p);
+    }
+    if (c0_row)
+        load_words<V>(A.S0 + off((z0 + L - 1) % L), c0o);
+
+    uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0;
+    const bool counting = A.bond_acc != nullptr;
+
+    for (int qi = -1; qi <= (int)Tza; ++qi) {
+        const uint32_t zq = (z0 + L + qi) % L;            // plane of this step
+        const uint32_t zm = (zq + L - 1) % L;             // plane of the colour-1 update
+        // prefetch the next step's words
+        if (qi < (int)Tza) {
+            if (held)
+                load_words<V>(A.S1 + off((zq + 2) % L), pf1);
+            if (c0_row)
+                load_words<V>(A.S0 + off((zq + 1) % L), pf0);
+        }
+        uint32_t *X1 = lds + (size_t)(qi & 1) * 2 * E * W;   // old colour 1 of plane q
+        uint32_t *X0 = X1 + (size_t)E * W;                  // new colour 0 of plane q-1
+        if (held) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                X1[e * W + w0 + v] = c1c[v];
+                X0[e * W + w0 + v] = n0m1[v];
+            }
+        }
+        __syncthreads();
+
+        const uint32_t pi = (y + zq) & 1u;   // x parity of colour 0 at (y, zq), colour 1 at (y, zm)
+        if (c0_row) {
+            uint32_t ym[V], yp[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                ym[v] = X1[em * W + w0 + v];
+                yp[v] = X1[ep * W + w0 + v];
+            }
+            const uint32_t adj = X1[e * W + (pi == 0u ? wprev : wnext)];
+            const uint32_t g0 = (uint32_t)(((size_t)zq * L + y) * W + w0);
+            uint32_t a0 = 0, a1 = 0, a2 = 0;
+            update_words<V>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, A.k0, A.k1, g0, g0 & 3u, A.t,
+                            0u, n0c, a0, a1, a2);
+            if (counting && owned && qi >= 0 && qi < (int)Tza) {
+                cnt0 += a0;
+                cnt1 += a1;
+                cnt2 += a2;
+            }
+            if (owned && qi >= 0 && qi < (int)Tza)
+                store_words<V>(A.D0 + off(zq), n0c);
+        }
+        if (owned && qi >= 1) {
+            uint32_t ym[V], yp[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                ym[v] = X0[em * W + w0 + v];
+                yp[v] = X0[ep * W + w0 + v];
+            }
+            const uint32_t adj = X0[e * W + (pi == 0u ? wprev : wnext)];
+            const uint32_t g1 = (uint32_t)(((size_t)zm * L + y) * W + w0);
+            uint32_t d0 = 0, d1 = 0, d2 = 0;
+            update_words<V>(c1m, n0m1, adj, pi, ym, yp, n0m2, n0c, A.k0, A.k1, g1, g1 & 3u, A.t,
+                            1u, c1n, d0, d1, d2);
+            store_words<V>(A.D1 + off(zm), c1n);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            c1m[v] = c1c[v];
+            c1c[v] = c1p[v];
+            c1p[v] = pf1[v];
+            c0o[v] = pf0[v];
+            n0m2[v] = n0m1[v];
+            n0m1[v] = n0c[v];
+        }
+    }
+
+    if (counting) {
+        __shared__ unsigned long long part[16];
+        const unsigned long long mine =
+            (unsigned long long)cnt0 + 2ull * cnt1 + 4ull * cnt2;
+        const unsigned long long ws = wave_sum_u64(mine);
+        const uint32_t nw = (blockDim.x + 63) / 64;
+        if ((tid & 63) == 0)
+            part[tid >> 6] = ws;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long tot = 0;
+            for (uint32_t k = 0; k < nw; ++k)
+                tot += part[k];
+            atomicAdd(A.bond_acc, tot);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// initial state: thread h covers lattice sites i = 64h .. 64h+63 (one row
+// segment), i.e. one word of each colour.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t even_bits(uint64_t v)
+{
+    v &= 0x5555555555555555ull;
+    v = (v | (v >> 1)) & 0x3333333333333333ull;
+    v = (v | (v >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    v = (v | (v >> 4)) & 0x00FF00FF00FF00FFull;
+    v = (v | (v >> 8)) & 0x0000FFFF0000FFFFull;
+    v = (v | (v >> 16)) & 0x00000000FFFFFFFFull;
+    return (uint32_t)v;
+}
+
+__global__ void __launch_bounds__(256) k_bit_init(uint32_t L, uint32_t W, uint64_t nh, uint32_t k0,
+                                                  uint32_t k1, uint32_t *P0, uint32_t *P1)
+{
+    const uint64_t h = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (h >= nh)
+        return;
+    const Words4 r = philox10((uint32_t)(h >> 1), 0u, 0u, 1u, k0, k1);
+    const uint32_t q = (uint32_t)(h & 1u) * 2u;
+    const uint64_t v = (uint64_t)r.w[q] | ((uint64_t)r.w[q + 1] << 32);
+    const uint64_t row = h / W;
+    const uint32_t y = (uint32_t)(row % L), z = (uint32_t)(row / L);
+    const uint32_t ce = (y + z) & 1u;   // colour of the even-x sites of this row
+    uint32_t *Pe = ce ? P1 : P0, *Po = ce ? P0 : P1;
+    Pe[h] = even_bits(v);
+    Po[h] = even_bits(v >> 1);
+}
+
+// --------------------------------------------------------------------------
+// per-axis bond counts from the colour-0 sites (every bond has exactly one
+// colour-0 end): thread per colour-0 word.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_bit_bonds(uint32_t L, uint32_t W, uint64_t nwords,
+                                                   const uint32_t *P0, const uint32_t *P1,
+                                                   unsigned long long *acc3)
+{
+    unsigned long long bx = 0, by = 0, bz = 0;
+    const size_t plane = (size_t)L * W;
+    for (uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x; g < nwords;
+         g += (uint64_t)gridDim.x * 256) {
+        const uint32_t w = (uint32_t)(g % W);
+        const uint64_t row = g / W;
+        const uint32_t y = (uint32_t)(row % L), z = (uint32_t)(row / L);
+        const uint32_t s = P0[g];
+        const uint32_t same = P1[g];
+        const uint32_t pi = (y + z) & 1u;
+        const size_t rb = (size_t)row * W;
+        uint32_t shifted;
+        if (pi == 0u)
+            shifted = funnel(same, P1[rb + (w + W - 1) % W], 31);
+        else
+            shifted = funnel(P1[rb + (w + 1) % W], same, 1);
+        const size_t zb = (size_t)z * plane;
+        const uint32_t ym = P1[zb + (size_t)((y + L - 1) % L) * W + w];
+        const uint32_t yp = P1[zb + (size_t)((y + 1) % L) * W + w];
+        const uint32_t zm = P1[(size_t)((z + L - 1) % L) * plane + (size_t)y * W + w];
+        const uint32_t zp = P1[(size_t)((z + 1) % L) * plane + (size_t)y * W + w];
+        bx += __builtin_popcount(s ^ same) + __builtin_popcount(s ^ shifted);
+        by += __builtin_popcount(s ^ ym) + __builtin_popcount(s ^ yp);
+        bz += __builtin_popcount(s ^ zm) + __builtin_popcount(s ^ zp);
+    }
+    __shared__ unsigned long long part[3][4];
+    bx = wave_sum_u64(bx);
+    by = wave_sum_u64(by);
+    bz = wave_sum_u64(bz);
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = bx;
+        part[1][threadIdx.x >> 6] = by;
+        part[2][threadIdx.x >> 6] = bz;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long tot = 0;
+        for (int k = 0; k < 4; ++k)
+            tot += part[threadIdx.x][k];
+        atomicAdd(acc3 + threadIdx.x, tot);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Correlation along y (AX = 1) or z (AX = 2).  For a fixed x-parity pi, word
+// column w and other coordinate o (z for AX = 1, y for AX = 2), the words
+// line[u] = P_{(pi+u+o)&1}[...] for u = 0..L-1 hold 32 parallel lines of sites
+// along the axis.  anti(r) = sum_u popc(line[u] ^ line[(u+r) mod L]) counts the
+// anti-aligned pairs at separation r; S(r) = N - 2 * sum anti(r).
+// A tile is (o, K consecutive words); both parities are held in LDS.
+// --------------------------------------------------------------------------
+constexpr int kCorrG = 8;    // separations per work item
+
+template <int AX, int kCorrK>
+__global__ void __launch_bounds__(256) k_bit_corr_lines(uint32_t L, uint32_t W, const uint32_t *P0,
+                                                        const uint32_t *P1, unsigned long long *anti)
+{
+    extern __shared__ uint32_t sm[];
+    const uint32_t R = L / 2 + 1;
+    uint32_t *lines = sm;                                            // [2][K][L]
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(sm + 2 * kCorrK * L);  // [R]
+    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x)
+        acc[r] = 0ull;
+    const uint32_t wt = W / kCorrK;
+    const uint32_t ntiles = L * wt;
+    const uint32_t ngroups = (R + kCorrG - 1) / kCorrG;
+    const uint32_t nitems = 2 * kCorrK * ngroups;
+    const size_t plane = (size_t)L * W;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t o = tile / wt, wb = (tile % wt) * kCorrK;
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < 2 * kCorrK * L; k += blockDim.x) {
+            const uint32_t kk = k % kCorrK, u = (k / kCorrK) % L, pi = k / (kCorrK * L);
+            const uint32_t c = (pi + u + o) & 1u;
+            const uint32_t *P = c ? P1 : P0;
+            const size_t addr = (AX == 1) ? (size_t)o * plane + (size_t)u * W + wb + kk
+                                          : (size_t)u * plane + (size_t)o * W + wb + kk;
+            lines[(pi * kCorrK + kk) * L + u] = P[addr];
+        }
+        __syncthreads();
+        for (uint32_t it = threadIdx.x; it < nitems; it += blockDim.x) {
+            const uint32_t g = it % ngroups, line = it / ngroups;
+            const uint32_t *ln = lines + line * L;
+            const uint32_t r0 = g * kCorrG;
+            uint32_t a[kCorrG];
+#pragma unroll
+            for (int d = 0; d < kCorrG; ++d)
+                a[d] = 0u;
+            uint32_t ywin[2 * kCorrG];
+#pragma unroll
+            for (int d = 0; d < kCorrG; ++d)
+                ywin[d] = ln[(r0 + d) % L];
+            for (uint32_t u = 0; u < L; u += kCorrG) {
+                uint32_t xw[kCorrG];
+#pragma unroll
+                for (int d = 0; d < kCorrG; ++d) {
+                    xw[d] = ln[u + d];
+                    ywin[kCorrG + d] = ln[(u + r0 + kCorrG + d) % L];
+                }
+#pragma unroll
+                for (int i = 0; i < kCorrG; ++i)
+#pragma unroll
+                    for (int d = 0; d < kCorrG; ++d)
+                        a[d] += __builtin_popcount(xw[i] ^ ywin[i + d]);
+#pragma unroll
+                for (int d = 0; d < kCorrG; ++d)
+                    ywin[d] = ywin[kCorrG + d];
+            }
+#pragma unroll
+            for (int d = 0; d < kCorrG; ++d)
+                if (r0 + d < R)
+                    atomicAdd(acc + r0 + d, (unsigned long long)a[d]);
+        }
+    }
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x)
+        if (acc[r])
+            atomicAdd(anti + r, acc[r]);
+}
+
+// Correlation along x, plus the count of up spins.  For row (y, z) let E / O
+// be the rows of even-x / odd-x sites (colour planes (y+z)&1 and its
+// complement).  With rot(X, m)[k] = X[(k+m) mod L/2]:
+//   r = 2m    pairs E[k]-E[k+m] and O[k]-O[k+m]
+//   r = 2m+1  pairs E[k]-O[k+m] and O[k]-E[k+m+1].
+// A work item is (row, q): the 32 shifts m = 32q .. 32q+31.
+__global__ void __launch_bounds__(256) k_bit_corr_x(uint32_t L, uint32_t W, const uint32_t *P0,
+                                                    const uint32_t *P1, unsigned long long *anti,
+                                                    unsigned long long *ones)
+{
+    extern __shared__ uint32_t sm[];
+    const uint32_t R = L / 2 + 1;
+    constexpr uint32_t kRows = 16;
+    uint32_t *rows = sm;                                             // [kRows][2][W]
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(sm + kRows * 2 * W);
+    __shared__ unsigned long long ones_acc;
+    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x)
+        acc[r] = 0ull;
+    if (threadIdx.x == 0)
+        ones_acc = 0ull;
+    const uint32_t nq = W / 2 + 1;   // m = 0 .. L/4
+    const uint64_t nrows = (uint64_t)L * L;
+    const uint32_t ntiles = (uint32_t)(nrows / kRows);
+    uint32_t my_ones = 0;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < kRows * 2 * W; k += blockDim.x) {
+            const uint32_t w = k % W, side = (k / W) & 1u, rr = k / (2 * W);
+            const uint64_t row = (uint64_t)tile * kRows + rr;
+            const uint32_t y = (uint32_t)(row % L), z = (uint32_t)(row / L);
+            const uint32_t ce = (y + z) & 1u;
+            const uint32_t c = side ? 1u - ce : ce;           // side 0 = even x, 1 = odd x
+            rows[k] = (c ? P1 : P0)[(size_t)row * W + w];
+        }
+        __syncthreads();
+        for (uint32_t it = threadIdx.x; it < kRows * nq; it += blockDim.x) {
+            const uint32_t q = it % nq, rr = it / nq;
+            const uint32_t *Ev = rows + rr * 2 * W, *Ov = Ev + W;
+            uint32_t ae[32], ao[32];
+#pragma unroll
+            for (int s = 0; s < 32; ++s)
+                ae[s] = ao[s] = 0u;
+            for (uint32_t w = 0; w < W; ++w) {
+                const uint32_t e0 = Ev[w], o0 = Ov[w];
+                if (q == 0)
+                    my_ones += __builtin_popcount(e0) + __builtin_popcount(o0);
+                const uint32_t ea = Ev[(w + q) % W], eb = Ev[(w + q + 1) % W],
+                               ec = Ev[(w + q + 2) % W];
+                const uint32_t oa = Ov[(w + q) % W], ob = Ov[(w + q + 1) % W];
+#pragma unroll
+                for (int s = 0; s < 32; ++s) {
+                    const uint32_t re = funnel(eb, ea, s);                           // rotE(32q+s)
+                    const uint32_t re1 = (s < 31) ? funnel(eb, ea, s + 1) : funnel(ec, eb, 0);  // rotE(+1)
+                    const uint32_t ro = funnel(ob, oa, s);                           // rotO(32q+s)
+                    ae[s] += __builtin_popcount(e0 ^ re) + __builtin_popcount(o0 ^ ro);
+                    ao[s] += __builtin_popcount(e0 ^ ro) + __builtin_popcount(o0 ^ re1);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 32; ++s) {
+                const uint32_t m = 32 * q + s;
+                if (2 * m < R)
+                    atomicAdd(acc + 2 * m, (unsigned long long)ae[s]);
+                if (2 * m + 1 < R)
+                    atomicAdd(acc + 2 * m + 1, (unsigned long long)ao[s]);
+            }
+        }
+    }
+    if (my_ones)
+        atomicAdd(&ones_acc, (unsigned long long)my_ones);
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x)
+        if (acc[r])
+            atomicAdd(anti + r, acc[r]);
+    if (threadIdx.x == 0 && ones_acc)
+        atomicAdd(ones, ones_acc);
+}
+
+// --------------------------------------------------------------------------
+// unpack / pack / window (checkpoint and test copies)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int8_t site_of(uint32_t L, uint32_t W, const uint32_t *P0,
+                                          const uint32_t *P1, uint32_t x, uint32_t y, uint32_t z)
+{
+    const uint32_t c = (x + y + z) & 1u;
+    const uint32_t word = (c ? P1 : P0)[((size_t)z * L + y) * W + (x >> 6)];
+    return ((word >> ((x >> 1) & 31u)) & 1u) ? (int8_t)1 : (int8_t)-1;
+}
+
+__global__ void __launch_bounds__(256) k_bit_unpack(uint32_t L, uint32_t W, const uint32_t *P0,
+                                                    const uint32_t *P1, uint32_t z0, uint64_t n,
+                                                    int8_t *out)
+{
+    const uint64_t LL = (uint64_t)L * L;
+    for (uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x; k < n;
+         k += (uint64_t)gridDim.x * 256) {
+        const uint32_t x = (uint32_t)(k % L), y = (uint32_t)((k / L) % L);
+        const uint32_t z = z0 + (uint32_t)(k / LL);
+        out[k] = site_of(L, W, P0, P1, x, y, z);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bit_pack(uint32_t L, uint32_t W, uint32_t *P0,
+                                                  uint32_t *P1, uint32_t z0, uint64_t nw,
+                                                  const int8_t *in, unsigned long long *bad)
+{
+    // thread per (colour, word) of planes z0 .. z0+nz-1
+    const uint64_t LL = (uint64_t)L * L;
+    unsigned long long b = 0;
+    for (uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x; k < nw;
+         k += (uint64_t)gridDim.x * 256) {
+        const uint32_t c = (uint32_t)(k & 1u);
+        const uint64_t g = k >> 1;                  // word index relative to plane z0
+        const uint32_t w = (uint32_t)(g % W);
+        const uint64_t row = g / W;
+        const uint32_t y = (uint32_t)(row % L), zl = (uint32_t)(row / L);
+        const uint32_t pi = (c + y + z0 + zl) & 1u;
+        const int8_t *src = in + (uint64_t)zl * LL + (uint64_t)y * L + 64u * w + pi;
+        uint32_t word = 0;
+        for (int bit = 0; bit < 32; ++bit) {
+            const int8_t v = src[2 * bit];
+            b += (v != 1 && v != -1);
+            word |= (v == 1 ? 1u : 0u) << bit;
+        }
+        (c ? P1 : P0)[(size_t)z0 * L * W + g] = word;
+    }
+    __shared__ unsigned long long part[4];
+    b = wave_sum_u64(b);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long tot = part[0] + part[1] + part[2] + part[3];
+        if (tot)
+            atomicAdd(bad, tot);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bit_window(uint32_t L, uint32_t W, const uint32_t *P0,
+                                                    const uint32_t *P1, uint32_t ox, uint32_t oy,
+                                                    uint32_t oz, uint32_t Wn, uint32_t lz0,
+                                                    uint64_t n, int8_t *out)
+{
+    const uint64_t WW = (uint64_t)Wn * Wn;
+    for (uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x; k < n;
+         k += (uint64_t)gridDim.x * 256) {
+        const uint32_t lx = (uint32_t)(k % Wn), ly = (uint32_t)((k / Wn) % Wn);
+        const uint32_t lz = lz0 + (uint32_t)(k / WW);
+        out[k] = site_of(L, W, P0, P1, (ox + lx) % L, (oy + ly) % L, (oz + lz) % L);
+    }
+}
+
+uint32_t grid_cap(uint64_t work, uint32_t cap)
+{
+    uint64_t g = (work + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// tuning rules
+// --------------------------------------------------------------------------
+bool bit_tuning_valid(uint32_t L, const BitTuning &t)
+{
+    if (L < 64 || L % 64)
+        return false;
+    const uint32_t W = L / 64;
+    if (t.V != 1 && t.V != 2 && t.V != 4)
+        return false;
+    if (W % (uint32_t)t.V)
+        return false;
+    if (t.Tz < 1 || (uint32_t)t.Tz > L || t.Ty < 1 || (uint32_t)t.Ty > L)
+        return false;
+    const uint32_t R = W / t.V;
+    const uint32_t E = ((uint32_t)t.Ty == L) ? L : (uint32_t)t.Ty + 4;
+    const uint32_t threads = ((E * R + 63) / 64) * 64;
+    if (threads > 1024)
+        return false;
+    const size_t lds = (size_t)2 * 2 * E * W * 4;
+    return lds <= 60 * 1024;   // stays inside the default dynamic LDS limit with the static part
+}
+
+BitTuning bit_tuning_default(uint32_t L)
+{
+    const uint32_t W = L / 64;
+    BitTuning t;
+    t.V = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
+    const uint32_t R = W / t.V;
+    if (L * R <= 256 || (L * R <= 1024 && L <= 512)) {
+        t.Ty = (int)L;   // whole planes
+        t.Tz = (int)((L <= 128) ? 8 : 16);
+    } else {
+        uint32_t E = 8;
+        while (E * 2 * R <= 256 && E * 2 <= L)
+            E *= 2;
+        t.Ty = (int)(E - 4);
+        t.Tz = 64;
+    }
+    if ((uint32_t)t.Tz > L)
+        t.Tz = (int)L;
+    return t;
+}
+
+hipError_t bit_init(hipStream_t st, uint32_t L, uint64_t seed, uint32_t *P0, uint32_t *P1)
+{
+    const uint32_t W = L / 64;
+    const uint64_t nh = (uint64_t)L * L * W;
+    hipLaunchKernelGGL(k_bit_init, dim3((uint32_t)((nh + 255) / 256)), dim3(256), 0, st, L, W, nh,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), P0, P1);
+    return hipGetLastError();
+}
+
+hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
+                     const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
+                     unsigned long long *bond_acc)
+{
+    if (!bit_tuning_valid(L, tu))
+        return hipErrorInvalidValue;
+    SweepArgs a;
+    a.S0 = S0; a.S1 = S1; a.D0 = D0; a.D1 = D1;
+    a.bond_acc = bond_acc;
+    a.L = L;
+    a.W = L / 64;
+    a.R = a.W / tu.V;
+    a.whole = ((uint32_t)tu.Ty == L) ? 1u : 0u;
+    a.Ty = (uint32_t)tu.Ty;
+    a.E = a.whole ? L : a.Ty + 4;
+    a.Tz = (uint32_t)tu.Tz;
+    a.nty = (L + a.Ty - 1) / a.Ty;
+    const uint32_t ntz = (L + a.Tz - 1) / a.Tz;
+    a.k0 = (uint32_t)seed;
+    a.k1 = (uint32_t)(seed >> 32);
+    a.t = t;
+    const uint32_t threads = ((a.E * a.R + 63) / 64) * 64;
+    const size_t lds = (size_t)2 * 2 * a.E * a.W * 4;
+    const dim3 grid(a.nty * ntz), block(threads);
+    switch (tu.V) {
+    case 4: hipLaunchKernelGGL(k_bit_sweep<4>, grid, block, lds, st, a); break;
+    case 2: hipLaunchKernelGGL(k_bit_sweep<2>, grid, block, lds, st, a); break;
+    default: hipLaunchKernelGGL(k_bit_sweep<1>, grid, block, lds, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t bit_bonds(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
+                     unsigned long long *acc3)
+{
+    const uint32_t W = L / 64;
+    const uint64_t nw = (uint64_t)L * L * W;
+    hipLaunchKernelGGL(k_bit_bonds, dim3(grid_cap(nw, 4096)), dim3(256), 0, st, L, W, nw, P0, P1,
+                       acc3);
+    return hipGetLastError();
+}
+
+hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
+                    unsigned long long *anti, unsigned long long *ones)
+{
+    const uint32_t W = L / 64;
+    const uint32_t R = L / 2 + 1;
+    // words per line tile: 4, else 2, else 1 (W need not be a multiple of 4)
+    const int K = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
+    const size_t lds_lines = (size_t)2 * K * L * 4 + (size_t)R * 8;
+    const uint32_t ntiles_lines = L * (W / K);
+    const uint32_t g_lines = ntiles_lines < 2048 ? ntiles_lines : 2048;
+    if (K == 4) {
+        hipLaunchKernelGGL((k_bit_corr_lines<1, 4>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
+                           P0, P1, anti + 1 * R);
+        hipLaunchKernelGGL((k_bit_corr_lines<2, 4>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
+                           P0, P1, anti + 2 * R);
+    } else if (K == 2) {
+        hipLaunchKernelGGL((k_bit_corr_lines<1, 2>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
+                           P0, P1, anti + 1 * R);
+        hipLaunchKernelGGL((k_bit_corr_lines<2, 2>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
+                           P0, P1, anti + 2 * R);
+    } else {
+        hipLaunchKernelGGL((k_bit_corr_lines<1, 1>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
+                           P0, P1, anti + 1 * R);
+        hipLaunchKernelGGL((k_bit_corr_lines<2, 1>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
+                           P0, P1, anti + 2 * R);
+    }
+    const size_t lds_x = (size_t)16 * 2 * W * 4 + (size_t)R * 8;
+    const uint32_t ntiles_x = (uint32_t)((uint64_t)L * L / 16);
+    const uint32_t g_x = ntiles_x < 2048 ? ntiles_x : 2048;
+    hipLaunchKernelGGL(k_bit_corr_x, dim3(g_x), dim3(256), lds_x, st, L, W, P0, P1, anti, ones);
+    return hipGetLastError();
+}
+
+hipError_t bit_unpack(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
+                      uint32_t z0, uint32_t nz, int8_t *out)
+{
+    const uint64_t n = (uint64_t)L * L * nz;
+    hipLaunchKernelGGL(k_bit_unpack, dim3(grid_cap(n, 8192)), dim3(256), 0, st, L, L / 64, P0, P1,
+                       z0, n, out);
+    return hipGetLastError();
+}
+
+hipError_t bit_pack(hipStream_t st, uint32_t L, uint32_t *P0, uint32_t *P1, uint32_t z0,
+                    uint32_t nz, const int8_t *in, unsigned long long *bad)
+{
+    const uint32_t W = L / 64;
+    const uint64_t nw = (uint64_t)L * W * nz * 2;
+    hipLaunchKernelGGL(k_bit_pack, dim3(grid_cap(nw, 8192)), dim3(256), 0, st, L, W, P0, P1, z0,
+                       nw, in, bad);
+    return hipGetLastError();
+}
+
+hipError_t bit_window(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
+                      uint32_t ox, uint32_t oy, uint32_t oz, uint32_t Wn, uint32_t lz0,
+                      uint32_t nz, int8_t *out)
+{
+    const uint64_t n = (uint64_t)Wn * Wn * nz;
+    hipLaunchKernelGGL(k_bit_window, dim3(grid_cap(n, 8192)), dim3(256), 0, st, L, L / 64, P0, P1,
+                       ox, oy, oz, Wn, lz0, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace qz

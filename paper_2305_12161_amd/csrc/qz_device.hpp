@@ -1,0 +1,134 @@
+// qz_device.hpp -- device-side building blocks shared by the quench kernels:
+// the counter-based generator, three-input bitwise helpers and wavefront
+// reductions.  gfx950 only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qz {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round multiplies
+// counter words 0 and 2 by the two round multipliers (full 64-bit products),
+// then mixes: (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0)).
+// The key advances by the two Weyl increments between rounds.  Ten rounds.
+// ---------------------------------------------------------------------------
+struct Words4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                           uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    Words4 r;
+    r.w[0] = c0; r.w[1] = c1; r.w[2] = c2; r.w[3] = c3;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric three-input bitwise functions as single gfx950 v_bitop3_b32
+// instructions.  The truth tables below are symmetric in their three inputs,
+// so they do not depend on how the hardware orders the inputs in the index.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+__device__ __forceinline__ uint32_t and3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x80);
+}
+
+// Funnel shift: the low 32 bits of ((hi:lo) >> s), 0 <= s < 32.
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
+{
+    return __builtin_amdgcn_alignbit(hi, lo, s);
+}
+
+// ---------------------------------------------------------------------------
+// The zero-temperature rule on 32 sites at once.  s holds 32 spins of one
+// colour, n[0..5] the matching bits of their six neighbours.  The number of
+// anti-aligned neighbours a = sum_k (s ^ n_k) is formed as three bit planes
+// (a = 4*a2 + 2*a1 + a0) by two full adders over the neighbour triples; the
+// spin flips where a >= 4 (energy falls) or a == 3 (energy unchanged) and the
+// tie bit r is set.
+// ---------------------------------------------------------------------------
+struct Counts {
+    uint32_t a0, a1, a2;
+};
+
+__device__ __forceinline__ Counts count_antialigned(uint32_t s, uint32_t n0, uint32_t n1,
+                                                    uint32_t n2, uint32_t n3, uint32_t n4,
+                                                    uint32_t n5)
+{
+    // Adder over (s^n0, s^n1, s^n2): sum = s ^ xor3(n), carry = s ^ maj3(n).
+    const uint32_t xa = xor3(n0, n1, n2), ma = maj3(n0, n1, n2);
+    const uint32_t xb = xor3(n3, n4, n5), mb = maj3(n3, n4, n5);
+    const uint32_t sa = s ^ xa, sb = s ^ xb;
+    const uint32_t ca = s ^ ma, cb = s ^ mb;
+    Counts c;
+    c.a0 = xa ^ xb;           // sa ^ sb
+    const uint32_t k = sa & sb;
+    c.a1 = xor3(ca, cb, k);
+    c.a2 = maj3(ca, cb, k);
+    return c;
+}
+
+__device__ __forceinline__ uint32_t tie_mask(const Counts &c)
+{
+    return c.a1 & c.a0 & ~c.a2;   // a == 3
+}
+
+__device__ __forceinline__ uint32_t apply_rule(uint32_t s, const Counts &c, uint32_t r)
+{
+    return s ^ (c.a2 | and3(c.a1, c.a0, r));
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront (64-lane) sum of a 64-bit value; lane 0 ends with the total.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Map a linear block id to a tile so that consecutive tiles stay on one XCD.
+// Workgroups are dealt round-robin over the 8 XCDs; tile = xcd*(n/8) + k.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nblocks)
+{
+    if ((nblocks & 7u) != 0u)
+        return bid;
+    return (bid & 7u) * (nblocks >> 3) + (bid >> 3);
+}
+
+}  // namespace qz

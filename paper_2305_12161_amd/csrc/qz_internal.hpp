@@ -1,0 +1,70 @@
+// qz_internal.hpp -- host-side declarations shared by the library's
+// translation units: the lattice object, tuning knobs and kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace qz {
+
+// Device-memory map of one lattice inside the caller's buffer.  Offsets are
+// 256-byte aligned.
+struct StateMap {
+    size_t spins_off;     // I8: N bytes.  BIT: two copies of [plane0 | plane1]
+    size_t spins_bytes;   //   each plane N/16 bytes (N/8 per copy)
+    size_t counter_off;   // 64 uint64 counters for measurements
+    size_t corr_off;      // 3*(L/2+1) + 1 int64 correlation accumulators
+    size_t trace_off;     // kTraceCap uint64 trace slots for host-trace runs
+    size_t stage_off;     // staging bytes for host copies
+    size_t stage_bytes;
+    size_t total;
+};
+
+constexpr size_t kTraceCap = 4096;
+constexpr size_t kStageMax = size_t(32) << 20;
+
+bool state_map(uint32_t L, int layout, StateMap *m);
+
+// Tuning of the fused bit-sweep kernel (see qz_bit.hip).
+struct BitTuning {
+    int V;    // 32-bit words per lane along x: 1, 2 or 4
+    int Ty;   // rows (y) owned per tile; Ty == L means whole planes, no y halo
+    int Tz;   // planes (z) per tile
+};
+bool bit_tuning_valid(uint32_t L, const BitTuning &t);
+BitTuning bit_tuning_default(uint32_t L);
+
+// ----- int8 layout -----
+hipError_t i8_init(hipStream_t st, uint32_t L, uint64_t seed, int8_t *s);
+hipError_t i8_half_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, int p, int8_t *s,
+                         unsigned long long *bond_acc);
+hipError_t i8_bonds(hipStream_t st, uint32_t L, const int8_t *s, unsigned long long *acc3);
+hipError_t i8_corr(hipStream_t st, uint32_t L, const int8_t *s, long long *S, long long *M);
+hipError_t i8_check_pm1(hipStream_t st, size_t n, const int8_t *s, unsigned long long *bad);
+
+// ----- bit layout -----
+// planes: copy k (0/1) at base + k*N/8 bytes, colour c at + c*N/16.
+hipError_t bit_init(hipStream_t st, uint32_t L, uint64_t seed, uint32_t *P0, uint32_t *P1);
+hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
+                     const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
+                     unsigned long long *bond_acc);
+hipError_t bit_bonds(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
+                     unsigned long long *acc3);
+hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
+                    unsigned long long *anti /* 3*(L/2+1) */, unsigned long long *ones);
+// Unpack planes z in [z0, z0+nz) to int8 (index (z-z0)*L*L + y*L + x).
+hipError_t bit_unpack(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
+                      uint32_t z0, uint32_t nz, int8_t *out);
+// Pack planes z in [z0, z0+nz) from int8; counts entries that are not +-1.
+hipError_t bit_pack(hipStream_t st, uint32_t L, uint32_t *P0, uint32_t *P1, uint32_t z0,
+                    uint32_t nz, const int8_t *in, unsigned long long *bad);
+// Extract window planes lz in [lz0, lz0+nz) of a W^3 window at origin o.
+hipError_t bit_window(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
+                      uint32_t ox, uint32_t oy, uint32_t oz, uint32_t W, uint32_t lz0,
+                      uint32_t nz, int8_t *out);
+hipError_t i8_window(hipStream_t st, uint32_t L, const int8_t *s, uint32_t ox, uint32_t oy,
+                     uint32_t oz, uint32_t W, uint32_t lz0, uint32_t nz, int8_t *out);
+
+hipError_t fill_u64(hipStream_t st, unsigned long long *p, size_t n, unsigned long long v);
+
+}  // namespace qz

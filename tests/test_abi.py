@@ -1,0 +1,84 @@
+"""Host-only checks of the C ABI: the built library loads, exports every entry
+point the header declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "quench.h")
+LIB = os.path.join(ROOT, "paper_2305_12161_amd", "libquench.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qz_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import __graft_entry__
+        __graft_entry__.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_expected_calls():
+    names = declared_functions()
+    for need in ("qz_create", "qz_run", "qz_bonds", "qz_corr", "qz_destroy", "qz_state_bytes",
+                 "qz_download_spins", "qz_upload_spins", "qz_download_window", "qz_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_abi_version_and_sizes(lib):
+    lib.qz_abi_version.restype = ctypes.c_int
+    assert lib.qz_abi_version() == 1
+    lib.qz_state_bytes.restype = ctypes.c_size_t
+    lib.qz_state_bytes.argtypes = [ctypes.c_uint32, ctypes.c_int]
+    # int8: N bytes of spins; bit: two copies of N/8 bytes
+    assert lib.qz_state_bytes(32, 0) >= 32 ** 3
+    assert lib.qz_state_bytes(2048, 1) >= 2 * 2048 ** 3 // 8
+    assert lib.qz_state_bytes(2048, 1) < 2 * 2048 ** 3 // 8 + (64 << 20)
+    assert lib.qz_state_bytes(7, 0) == 0          # odd L
+    assert lib.qz_state_bytes(2, 0) == 0          # L < 4
+    assert lib.qz_state_bytes(96, 1) == 0         # bit layout needs L % 64 == 0
+    assert lib.qz_state_bytes(96, 0) > 0
+    assert lib.qz_state_bytes(64, 5) == 0         # unknown layout
+
+
+def test_create_rejects_bad_arguments_without_device(lib):
+    lib.qz_create.restype = ctypes.c_int
+    lib.qz_create.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.qz_last_error.restype = ctypes.c_char_p
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: every call below fails first
+    assert lib.qz_create(7, 1, 0, fake, 1 << 30, None, ctypes.byref(h)) == -1
+    assert lib.qz_create(96, 1, 1, fake, 1 << 30, None, ctypes.byref(h)) == -5
+    assert lib.qz_create(64, 1, 3, fake, 1 << 30, None, ctypes.byref(h)) == -1
+    assert lib.qz_create(64, 1, 1, None, 1 << 30, None, ctypes.byref(h)) == -1
+    assert lib.qz_create(64, 1, 1, fake, 16, None, ctypes.byref(h)) == -2
+    assert lib.qz_create(64, 1, 1, fake, 1 << 30, None, None) == -1
+    assert b"" != lib.qz_last_error()
+
+
+def test_status_strings(lib):
+    lib.qz_status_string.restype = ctypes.c_char_p
+    lib.qz_status_string.argtypes = [ctypes.c_int]
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.qz_status_string(code)
+    assert lib.qz_status_string(-99) == b"unknown status"
+
+
+def test_null_handle_calls(lib):
+    lib.qz_run.restype = ctypes.c_int
+    lib.qz_run.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
+    assert lib.qz_run(None, 1, 0, None) == -1
+    assert lib.qz_destroy(None) == -1

@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+The dynamics are exact integer work, so every comparison is bit-exact:
+lattices, bond traces, per-axis bond counts and correlation sums.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2305_12161_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qz():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_12161_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _threads(orc):
+    orc.set_threads(min(16, os.cpu_count() or 1))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_run(orc, L, seed, n, every=0, s=None, t0=0):
+    if s is None:
+        s = orc.init(L, seed)
+    tr = orc.run(s, seed, t0, n, every)
+    return s, tr
+
+
+# --------------------------------------------------------------------------
+# initial state
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("layout,L", [("i8", 4), ("i8", 6), ("i8", 10), ("i8", 32),
+                                      ("bit", 64), ("bit", 128), ("bit", 192), ("bit", 256)])
+def test_init_matches_oracle(qz, orc, layout, L):
+    say("init", layout, L)
+    for seed in (1, 2**63 + 12345):
+        lat = qz.Lattice(L, seed, layout)
+        assert np.array_equal(lat.download(), orc.init(L, seed))
+
+
+# --------------------------------------------------------------------------
+# dynamics: config 1 in full, small and ragged sizes, both layouts
+# --------------------------------------------------------------------------
+def test_config1_full_run(qz, orc):
+    c = wl.CONFIG1
+    say("config1", c)
+    lat = qz.Lattice(c.L, c.seed, "i8")
+    tr = lat.run(c.t_max, c.trace_every)
+    s, want = oracle_run(orc, c.L, c.seed, c.t_max, c.trace_every)
+    assert np.array_equal(tr.astype(np.int64), want)
+    assert np.array_equal(lat.download(), s)
+    assert np.array_equal(lat.bonds(), orc.bonds(s))
+    assert lat.t == c.t_max
+
+
+@pytest.mark.parametrize("L", [4, 6, 8, 10, 16, 18])
+def test_i8_small_sizes(qz, orc, L):
+    for seed in (3, 2**40 + 7):
+        say("i8 small", L, seed)
+        lat = qz.Lattice(L, seed, "i8")
+        s = orc.init(L, seed)
+        for chunk in (1, 4, 15):
+            tr = lat.run(chunk, 1)
+            want = orc.run(s, seed, lat.t - chunk, chunk, 1)
+            assert np.array_equal(tr.astype(np.int64), want)
+            assert np.array_equal(lat.download(), s)
+
+
+@pytest.mark.parametrize("L", [64, 128, 192, 256])
+def test_bit_default_tuning(qz, orc, L):
+    seed = 1000 + L
+    say("bit default", L)
+    lat = qz.Lattice(L, seed, "bit")
+    n = 20 if L <= 128 else 8
+    tr = lat.run(n, 2)
+    s, want = oracle_run(orc, L, seed, n, 2)
+    assert np.array_equal(tr.astype(np.int64), want)
+    assert np.array_equal(lat.download(), s)
+
+
+# (V, Ty, Tz) triples covering whole planes, halo tiles, ragged y and z tiles
+TUNINGS = {
+    64: [(1, 64, 64), (1, 64, 5), (1, 28, 7), (1, 12, 64), (1, 60, 3)],
+    128: [(2, 128, 8), (1, 128, 13), (2, 28, 11), (1, 60, 128), (2, 124, 6)],
+    192: [(1, 192, 16), (1, 28, 20), (1, 60, 7)],
+    256: [(4, 256, 16), (2, 60, 32), (4, 28, 10), (1, 28, 256), (4, 124, 9)],
+}
+
+
+@pytest.mark.parametrize("L", sorted(TUNINGS))
+def test_bit_tunings_match_oracle(qz, orc, L):
+    seed = 77 + L
+    n = 6
+    s, want = oracle_run(orc, L, seed, n, 1)
+    for V, Ty, Tz in TUNINGS[L]:
+        say("bit tuning", L, (V, Ty, Tz))
+        lat = qz.Lattice(L, seed, "bit")
+        lat.set_tuning(V, Ty, Tz)
+        tr = lat.run(n, 1)
+        assert np.array_equal(tr.astype(np.int64), want), (V, Ty, Tz)
+        assert np.array_equal(lat.download(), s), (V, Ty, Tz)
+
+
+@pytest.mark.parametrize("L", [64, 128])
+def test_bit_equals_i8(qz, L):
+    seed = 5 + L
+    say("bit==i8", L)
+    a = qz.Lattice(L, seed, "i8")
+    b = qz.Lattice(L, seed, "bit")
+    ta = a.run(60, 3)
+    tb = b.run(60, 3)
+    assert np.array_equal(ta, tb)
+    assert np.array_equal(a.download(), b.download())
+    assert np.array_equal(a.bonds(), b.bonds())
+    Sa, Ma = a.corr()
+    Sb, Mb = b.corr()
+    assert np.array_equal(Sa, Sb) and Ma == Mb
+
+
+# --------------------------------------------------------------------------
+# measurements
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("layout,L", [("i8", 6), ("i8", 16), ("i8", 34), ("bit", 64),
+                                      ("bit", 128), ("bit", 192), ("bit", 256)])
+def test_bonds_and_corr_match_oracle(qz, orc, layout, L):
+    seed = 11 + L
+    say("measure", layout, L)
+    lat = qz.Lattice(L, seed, layout)
+    s = orc.init(L, seed)
+    for n in (0, 3, 10):
+        if n:
+            lat.run(n)
+            orc.run(s, seed, lat.t - n, n)
+        assert np.array_equal(lat.download(), s)
+        assert np.array_equal(lat.bonds(), orc.bonds(s))
+        S, M = lat.corr()
+        So, Mo = orc.corr(s)
+        assert M == Mo
+        assert np.array_equal(S, So)
+
+
+# --------------------------------------------------------------------------
+# special states, upload/download, windows
+# --------------------------------------------------------------------------
+SPECIAL = {
+    "uniform_up": lambda L: wl.uniform_state(L, 1),
+    "uniform_down": lambda L: wl.uniform_state(L, -1),
+    "isolated": lambda L: wl.isolated_flip(L, (5, 3, 1)),
+    "slab_z": lambda L: wl.slab(L, 2),
+    "slab_x": lambda L: wl.slab(L, 0),
+    "plane": lambda L: wl.flipped_plane(L, 1, 2),
+    "line": lambda L: wl.flipped_line_x(L, 2, 3),
+    "neel": lambda L: wl.neel(L),
+    "cube": lambda L: wl.flipped_cube(L, (L - 1, 0, 7)),
+    "random": lambda L: wl.random_state(L, 3, 0.3),
+}
+
+
+@pytest.mark.parametrize("layout,L", [("i8", 8), ("i8", 64), ("bit", 64), ("bit", 128)])
+@pytest.mark.parametrize("name", sorted(SPECIAL))
+def test_special_states(qz, orc, layout, L, name):
+    say("special", name, layout, L)
+    s = SPECIAL[name](L)
+    lat = qz.Lattice(L, 9, layout)
+    lat.upload(s, 40)
+    assert lat.t == 40
+    assert np.array_equal(lat.download(), s)
+    tr = lat.run(4, 1)
+    want = orc.run(s, 9, 40, 4, 1)
+    assert np.array_equal(tr.astype(np.int64), want)
+    assert np.array_equal(lat.download(), s)
+
+
+def test_upload_rejects_non_spin_values(qz):
+    for layout, L in (("i8", 8), ("bit", 64)):
+        lat = qz.Lattice(L, 1, layout)
+        bad = np.ones((L, L, L), dtype=np.int8)
+        bad[1, 2, 3] = 0
+        with pytest.raises(qz.QuenchError) as ei:
+            lat.upload(bad, 0)
+        assert ei.value.status == qz.QZ_EINVAL
+
+
+@pytest.mark.parametrize("layout,L", [("i8", 16), ("bit", 64), ("bit", 128)])
+def test_window_download(qz, layout, L):
+    lat = qz.Lattice(L, 21, layout)
+    lat.run(5)
+    full = lat.download()
+    rng = np.random.default_rng(L)
+    for _ in range(4):
+        W = int(rng.integers(1, L + 1))
+        o = [int(v) for v in rng.integers(0, L, size=3)]
+        w = lat.window(o, W)
+        z, y, x = np.ix_([(o[2] + k) % L for k in range(W)], [(o[1] + k) % L for k in range(W)],
+                         [(o[0] + k) % L for k in range(W)])
+        assert np.array_equal(w, full[z, y, x])
+
+
+def test_checkpoint_resume_is_exact(qz):
+    for layout, L in (("i8", 32), ("bit", 64)):
+        a = qz.Lattice(L, 44, layout)
+        a.run(30)
+        snap, t = a.download(), a.t
+        ta = a.run(30, 5)
+        b = qz.Lattice(L, 44, layout)
+        b.upload(snap, t)
+        tb = b.run(30, 5)
+        assert np.array_equal(ta, tb)
+        assert np.array_equal(a.download(), b.download())
+
+
+def test_run_device_trace_matches_host_trace(qz):
+    import torch
+    a = qz.Lattice(128, 8, "bit")
+    b = qz.Lattice(128, 8, "bit")
+    dev = torch.zeros(10, dtype=torch.int64, device="cuda")
+    a.run_device(50, 5, dev)
+    tb = b.run(50, 5)
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy().astype(np.uint64), tb)
+
+
+def test_bad_arguments_raise(qz):
+    with pytest.raises(qz.QuenchError):
+        qz.Lattice(96, 1, "bit")
+    with pytest.raises(qz.QuenchError):
+        qz.Lattice(7, 1, "i8")
+    lat = qz.Lattice(64, 1, "bit")
+    with pytest.raises(qz.QuenchError):
+        lat.set_tuning(3, 64, 8)
+    with pytest.raises(qz.QuenchError):
+        lat.run(10, 3)
+    i8 = qz.Lattice(8, 1, "i8")
+    with pytest.raises(qz.QuenchError):
+        i8.set_tuning(1, 8, 8)

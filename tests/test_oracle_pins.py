@@ -367,6 +367,15 @@ def test_window_replay_matches_full_run(orc):
             assert np.array_equal(got, want)
 
 
+def test_init_window_is_a_slice_of_init(orc):
+    L = 12
+    s = orc.init(L, 8)
+    for o, W in (((0, 0, 0), 12), ((5, 11, 3), 7), ((11, 11, 11), 4)):
+        z, y, x = np.ix_([(o[2] + k) % L for k in range(W)], [(o[1] + k) % L for k in range(W)],
+                         [(o[0] + k) % L for k in range(W)])
+        assert np.array_equal(orc.init_window(L, 8, o, W), s[z, y, x])
+
+
 def test_host_derivations(orc):
     L = 32
     N = L ** 3
