@@ -105,9 +105,22 @@ __device__ __forceinline__ void update_words(const uint32_t (&own)[V], const uin
         r[v] = 0u;
     if (ties != 0u) {
         const Words4 rb = philox10(ctr0 >> 2, t, p, 0u, k0, k1);
+        // Word (sub + v) of the block, chosen without a dynamically indexed
+        // array (which would live in scratch memory).  With V = 4 the lane's
+        // words start a block (sub = 0); with V = 2, sub is 0 or 2.
+        if constexpr (V == 4) {
 #pragma unroll
-        for (int v = 0; v < V; ++v)
-            r[v] = rb.w[(sub + v) & 3];
+            for (int v = 0; v < V; ++v)
+                r[v] = rb.w[v];
+        } else if constexpr (V == 2) {
+            const bool hi = (sub & 2u) != 0u;
+            r[0] = hi ? rb.w[2] : rb.w[0];
+            r[1] = hi ? rb.w[3] : rb.w[1];
+        } else {
+            const uint32_t lo = (sub & 1u) ? rb.w[1] : rb.w[0];
+            const uint32_t hi = (sub & 1u) ? rb.w[3] : rb.w[2];
+            r[0] = (sub & 2u) ? hi : lo;
+        }
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -186,22 +199,16 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
         uint32_t *X1 = lds + (size_t)(qi & 1) * 2 * E * W;   // old colour 1 of plane q
         uint32_t *X0 = X1 + (size_t)E * W;                  // new colour 0 of plane q-1
         if (held) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                X1[e * W + w0 + v] = c1c[v];
-                X0[e * W + w0 + v] = n0m1[v];
-            }
+            store_words<V>(X1 + e * W + w0, c1c);   // aligned: W and w0 are multiples of V
+            store_words<V>(X0 + e * W + w0, n0m1);
         }
         __syncthreads();
 
         const uint32_t pi = (y + zq) & 1u;   // x parity of colour 0 at (y, zq), colour 1 at (y, zm)
         if (c0_row) {
             uint32_t ym[V], yp[V];
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                ym[v] = X1[em * W + w0 + v];
-                yp[v] = X1[ep * W + w0 + v];
-            }
+            load_words<V>(X1 + em * W + w0, ym);
+            load_words<V>(X1 + ep * W + w0, yp);
             const uint32_t adj = X1[e * W + (pi == 0u ? wprev : wnext)];
             const uint32_t g0 = (uint32_t)(((size_t)zq * L + y) * W + w0);
             uint32_t a0 = 0, a1 = 0, a2 = 0;
@@ -217,11 +224,8 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
         }
         if (owned && qi >= 1) {
             uint32_t ym[V], yp[V];
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                ym[v] = X0[em * W + w0 + v];
-                yp[v] = X0[ep * W + w0 + v];
-            }
+            load_words<V>(X0 + em * W + w0, ym);
+            load_words<V>(X0 + ep * W + w0, yp);
             const uint32_t adj = X0[e * W + (pi == 0u ? wprev : wnext)];
             const uint32_t g1 = (uint32_t)(((size_t)zm * L + y) * W + w0);
             uint32_t d0 = 0, d1 = 0, d2 = 0;
@@ -339,161 +343,6 @@ __global__ void __launch_bounds__(256) k_bit_bonds(uint32_t L, uint32_t W, uint6
             tot += part[threadIdx.x][k];
         atomicAdd(acc3 + threadIdx.x, tot);
     }
-}
-
-// --------------------------------------------------------------------------
-// Correlation along y (AX = 1) or z (AX = 2).  For a fixed x-parity pi, word
-// column w and other coordinate o (z for AX = 1, y for AX = 2), the words
-// line[u] = P_{(pi+u+o)&1}[...] for u = 0..L-1 hold 32 parallel lines of sites
-// along the axis.  anti(r) = sum_u popc(line[u] ^ line[(u+r) mod L]) counts the
-// anti-aligned pairs at separation r; S(r) = N - 2 * sum anti(r).
-// A tile is (o, K consecutive words); both parities are held in LDS.
-// --------------------------------------------------------------------------
-constexpr int kCorrG = 8;    // separations per work item
-
-template <int AX, int kCorrK>
-__global__ void __launch_bounds__(256) k_bit_corr_lines(uint32_t L, uint32_t W, const uint32_t *P0,
-                                                        const uint32_t *P1, unsigned long long *anti)
-{
-    extern __shared__ uint32_t sm[];
-    const uint32_t R = L / 2 + 1;
-    uint32_t *lines = sm;                                            // [2][K][L]
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(sm + 2 * kCorrK * L);  // [R]
-    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x)
-        acc[r] = 0ull;
-    const uint32_t wt = W / kCorrK;
-    const uint32_t ntiles = L * wt;
-    const uint32_t ngroups = (R + kCorrG - 1) / kCorrG;
-    const uint32_t nitems = 2 * kCorrK * ngroups;
-    const size_t plane = (size_t)L * W;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t o = tile / wt, wb = (tile % wt) * kCorrK;
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < 2 * kCorrK * L; k += blockDim.x) {
-            const uint32_t kk = k % kCorrK, u = (k / kCorrK) % L, pi = k / (kCorrK * L);
-            const uint32_t c = (pi + u + o) & 1u;
-            const uint32_t *P = c ? P1 : P0;
-            const size_t addr = (AX == 1) ? (size_t)o * plane + (size_t)u * W + wb + kk
-                                          : (size_t)u * plane + (size_t)o * W + wb + kk;
-            lines[(pi * kCorrK + kk) * L + u] = P[addr];
-        }
-        __syncthreads();
-        for (uint32_t it = threadIdx.x; it < nitems; it += blockDim.x) {
-            const uint32_t g = it % ngroups, line = it / ngroups;
-            const uint32_t *ln = lines + line * L;
-            const uint32_t r0 = g * kCorrG;
-            uint32_t a[kCorrG];
-#pragma unroll
-            for (int d = 0; d < kCorrG; ++d)
-                a[d] = 0u;
-            uint32_t ywin[2 * kCorrG];
-#pragma unroll
-            for (int d = 0; d < kCorrG; ++d)
-                ywin[d] = ln[(r0 + d) % L];
-            for (uint32_t u = 0; u < L; u += kCorrG) {
-                uint32_t xw[kCorrG];
-#pragma unroll
-                for (int d = 0; d < kCorrG; ++d) {
-                    xw[d] = ln[u + d];
-                    ywin[kCorrG + d] = ln[(u + r0 + kCorrG + d) % L];
-                }
-#pragma unroll
-                for (int i = 0; i < kCorrG; ++i)
-#pragma unroll
-                    for (int d = 0; d < kCorrG; ++d)
-                        a[d] += __builtin_popcount(xw[i] ^ ywin[i + d]);
-#pragma unroll
-                for (int d = 0; d < kCorrG; ++d)
-                    ywin[d] = ywin[kCorrG + d];
-            }
-#pragma unroll
-            for (int d = 0; d < kCorrG; ++d)
-                if (r0 + d < R)
-                    atomicAdd(acc + r0 + d, (unsigned long long)a[d]);
-        }
-    }
-    __syncthreads();
-    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x)
-        if (acc[r])
-            atomicAdd(anti + r, acc[r]);
-}
-
-// Correlation along x, plus the count of up spins.  For row (y, z) let E / O
-// be the rows of even-x / odd-x sites (colour planes (y+z)&1 and its
-// complement).  With rot(X, m)[k] = X[(k+m) mod L/2]:
-//   r = 2m    pairs E[k]-E[k+m] and O[k]-O[k+m]
-//   r = 2m+1  pairs E[k]-O[k+m] and O[k]-E[k+m+1].
-// A work item is (row, q): the 32 shifts m = 32q .. 32q+31.
-__global__ void __launch_bounds__(256) k_bit_corr_x(uint32_t L, uint32_t W, const uint32_t *P0,
-                                                    const uint32_t *P1, unsigned long long *anti,
-                                                    unsigned long long *ones)
-{
-    extern __shared__ uint32_t sm[];
-    const uint32_t R = L / 2 + 1;
-    constexpr uint32_t kRows = 16;
-    uint32_t *rows = sm;                                             // [kRows][2][W]
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(sm + kRows * 2 * W);
-    __shared__ unsigned long long ones_acc;
-    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x)
-        acc[r] = 0ull;
-    if (threadIdx.x == 0)
-        ones_acc = 0ull;
-    const uint32_t nq = W / 2 + 1;   // m = 0 .. L/4
-    const uint64_t nrows = (uint64_t)L * L;
-    const uint32_t ntiles = (uint32_t)(nrows / kRows);
-    uint32_t my_ones = 0;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < kRows * 2 * W; k += blockDim.x) {
-            const uint32_t w = k % W, side = (k / W) & 1u, rr = k / (2 * W);
-            const uint64_t row = (uint64_t)tile * kRows + rr;
-            const uint32_t y = (uint32_t)(row % L), z = (uint32_t)(row / L);
-            const uint32_t ce = (y + z) & 1u;
-            const uint32_t c = side ? 1u - ce : ce;           // side 0 = even x, 1 = odd x
-            rows[k] = (c ? P1 : P0)[(size_t)row * W + w];
-        }
-        __syncthreads();
-        for (uint32_t it = threadIdx.x; it < kRows * nq; it += blockDim.x) {
-            const uint32_t q = it % nq, rr = it / nq;
-            const uint32_t *Ev = rows + rr * 2 * W, *Ov = Ev + W;
-            uint32_t ae[32], ao[32];
-#pragma unroll
-            for (int s = 0; s < 32; ++s)
-                ae[s] = ao[s] = 0u;
-            for (uint32_t w = 0; w < W; ++w) {
-                const uint32_t e0 = Ev[w], o0 = Ov[w];
-                if (q == 0)
-                    my_ones += __builtin_popcount(e0) + __builtin_popcount(o0);
-                const uint32_t ea = Ev[(w + q) % W], eb = Ev[(w + q + 1) % W],
-                               ec = Ev[(w + q + 2) % W];
-                const uint32_t oa = Ov[(w + q) % W], ob = Ov[(w + q + 1) % W];
-#pragma unroll
-                for (int s = 0; s < 32; ++s) {
-                    const uint32_t re = funnel(eb, ea, s);                           // rotE(32q+s)
-                    const uint32_t re1 = (s < 31) ? funnel(eb, ea, s + 1) : funnel(ec, eb, 0);  // rotE(+1)
-                    const uint32_t ro = funnel(ob, oa, s);                           // rotO(32q+s)
-                    ae[s] += __builtin_popcount(e0 ^ re) + __builtin_popcount(o0 ^ ro);
-                    ao[s] += __builtin_popcount(e0 ^ ro) + __builtin_popcount(o0 ^ re1);
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < 32; ++s) {
-                const uint32_t m = 32 * q + s;
-                if (2 * m < R)
-                    atomicAdd(acc + 2 * m, (unsigned long long)ae[s]);
-                if (2 * m + 1 < R)
-                    atomicAdd(acc + 2 * m + 1, (unsigned long long)ao[s]);
-            }
-        }
-    }
-    if (my_ones)
-        atomicAdd(&ones_acc, (unsigned long long)my_ones);
-    __syncthreads();
-    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x)
-        if (acc[r])
-            atomicAdd(anti + r, acc[r]);
-    if (threadIdx.x == 0 && ones_acc)
-        atomicAdd(ones, ones_acc);
 }
 
 // --------------------------------------------------------------------------
@@ -672,39 +521,6 @@ hipError_t bit_bonds(hipStream_t st, uint32_t L, const uint32_t *P0, const uint3
     const uint64_t nw = (uint64_t)L * L * W;
     hipLaunchKernelGGL(k_bit_bonds, dim3(grid_cap(nw, 4096)), dim3(256), 0, st, L, W, nw, P0, P1,
                        acc3);
-    return hipGetLastError();
-}
-
-hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
-                    unsigned long long *anti, unsigned long long *ones)
-{
-    const uint32_t W = L / 64;
-    const uint32_t R = L / 2 + 1;
-    // words per line tile: 4, else 2, else 1 (W need not be a multiple of 4)
-    const int K = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
-    const size_t lds_lines = (size_t)2 * K * L * 4 + (size_t)R * 8;
-    const uint32_t ntiles_lines = L * (W / K);
-    const uint32_t g_lines = ntiles_lines < 2048 ? ntiles_lines : 2048;
-    if (K == 4) {
-        hipLaunchKernelGGL((k_bit_corr_lines<1, 4>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
-                           P0, P1, anti + 1 * R);
-        hipLaunchKernelGGL((k_bit_corr_lines<2, 4>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
-                           P0, P1, anti + 2 * R);
-    } else if (K == 2) {
-        hipLaunchKernelGGL((k_bit_corr_lines<1, 2>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
-                           P0, P1, anti + 1 * R);
-        hipLaunchKernelGGL((k_bit_corr_lines<2, 2>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
-                           P0, P1, anti + 2 * R);
-    } else {
-        hipLaunchKernelGGL((k_bit_corr_lines<1, 1>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
-                           P0, P1, anti + 1 * R);
-        hipLaunchKernelGGL((k_bit_corr_lines<2, 1>), dim3(g_lines), dim3(256), lds_lines, st, L, W,
-                           P0, P1, anti + 2 * R);
-    }
-    const size_t lds_x = (size_t)16 * 2 * W * 4 + (size_t)R * 8;
-    const uint32_t ntiles_x = (uint32_t)((uint64_t)L * L / 16);
-    const uint32_t g_x = ntiles_x < 2048 ? ntiles_x : 2048;
-    hipLaunchKernelGGL(k_bit_corr_x, dim3(g_x), dim3(256), lds_x, st, L, W, P0, P1, anti, ones);
     return hipGetLastError();
 }
 
