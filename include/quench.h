@@ -142,6 +142,74 @@ int qz_download_window(qz_lattice *q, const uint32_t origin[3], uint32_t W, int8
 int qz_set_tuning(qz_lattice *q, int V, int Ty, int Tz);
 int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
 
+/* ------------------------------------------------------------------------
+ * Batched replicas.  Many independent lattices ("replicas", each its own L
+ * and seed, 1-bit layout with L % 64 == 0 and L <= 256) held in one caller
+ * buffer and advanced together: one kernel launch sweeps every active replica
+ * once, each at its own time t, and groups of sweeps are replayed from a
+ * captured HIP graph.  Every replica follows exactly the trajectory a single
+ * lattice created from the same (L, seed) would follow: batching never changes
+ * results.  The paper runs 40 independent realisations per lattice size
+ * (Results); a batch runs such ensembles side by side.
+ *
+ * Slots keep their L for the life of the batch; a slot can be restarted with
+ * a new seed (serving) or parked (inactive slots are skipped).
+ * ------------------------------------------------------------------------ */
+typedef struct qz_batch qz_batch;  /* opaque, library-owned host object */
+
+typedef struct {
+    uint32_t L;      /* side; L % 64 == 0 and 64 <= L <= 256 */
+    uint64_t seed;   /* seed of the T = infinity start and of the tie bits */
+} qz_replica_spec;
+
+/* Device bytes for n replica slots with a bond-count ring of trace_cap
+ * entries per slot; 0 if a size is unsupported. */
+size_t qz_batch_state_bytes(const qz_replica_spec *specs, size_t n, uint32_t trace_cap);
+
+/* Create the batch in caller memory and draw every slot's start (t := 0, all
+ * slots active).  If trace_every > 0, the sweep starting at each time t with
+ * t % trace_every == 0 records B(t) of that slot into its ring of trace_cap
+ * entries (entry (t / trace_every) % trace_cap).  The library also creates a
+ * private stream, used only to capture graphs.  Errors: QZ_EINVAL, QZ_ENOMEM,
+ * QZ_EUNSUPPORTED, QZ_EDEVICE. */
+int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t trace_every,
+                    uint32_t trace_cap, void *dev_mem, size_t dev_bytes, void *hip_stream,
+                    qz_batch **out);
+int qz_batch_destroy(qz_batch *b);
+
+/* Advance every active slot by n_sweeps MCS (asynchronous). */
+int qz_batch_run(qz_batch *b, uint64_t n_sweeps);
+
+/* Wait for the batch's work and refresh the host view of slot times. */
+int qz_batch_sync(qz_batch *b);
+
+/* Restart a slot from a new T = infinity start drawn from `seed`, at t = 0,
+ * and make it active (synchronises). */
+int qz_batch_slot_reset(qz_batch *b, size_t slot, uint64_t seed);
+
+/* Park (active = 0) or resume (active = 1) a slot (synchronises). */
+int qz_batch_slot_active(qz_batch *b, size_t slot, int active);
+
+/* Current time of a slot (synchronises). */
+int qz_batch_slot_time(qz_batch *b, size_t slot, uint64_t *t);
+
+/* host[i] = B(t_from + i*trace_every) for i < count, from the slot's ring;
+ * QZ_EINVAL if t_from is not a multiple of trace_every, if an entry lies at
+ * or beyond the slot's current time, or if it has been overwritten. */
+int qz_batch_trace(qz_batch *b, size_t slot, uint64_t t_from, uint64_t count, uint64_t *host);
+
+/* A slot's lattice as int8 +-1 (L^3 bytes, index i), per-axis bond counts and
+ * axis correlation sums, with the meanings of qz_download_spins, qz_bonds and
+ * qz_corr (all synchronise). */
+int qz_batch_download(qz_batch *b, size_t slot, int8_t *host);
+int qz_batch_bonds(qz_batch *b, size_t slot, uint64_t out_B_axes[3]);
+int qz_batch_corr(qz_batch *b, size_t slot, int64_t *out_S, int64_t *out_M);
+
+/* Planes per sub-tile for slots of side L (Tz divides L, Tz >= 8; 0 keeps the
+ * current value) and sweeps per captured graph (0 = no graph).  Results never
+ * depend on it. */
+int qz_batch_set_tuning(qz_batch *b, uint32_t L, uint32_t Tz, uint32_t graph_sweeps);
+
 /* Text for a status code, and the calling thread's last error message. */
 const char *qz_status_string(int status);
 const char *qz_last_error(void);

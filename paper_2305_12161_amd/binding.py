@@ -166,3 +166,128 @@ class Lattice:
         out = (ctypes.c_int * 3)()
         _check(lib.qz_get_tuning(self._h, out))
         return tuple(int(v) for v in out)
+
+
+# --------------------------------------------------------------------------
+# batched replicas
+# --------------------------------------------------------------------------
+class _ReplicaSpec(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+def _batch_signatures():
+    c = ctypes
+    vp, u32, u64, sz, i32 = c.c_void_p, c.c_uint32, c.c_uint64, c.c_size_t, c.c_int
+    spec_p = c.POINTER(_ReplicaSpec)
+    sig = {
+        "qz_batch_state_bytes": ([spec_p, sz, u32], sz),
+        "qz_batch_create": ([spec_p, sz, u32, u32, vp, sz, vp, c.POINTER(vp)], i32),
+        "qz_batch_destroy": ([vp], i32),
+        "qz_batch_run": ([vp, u64], i32),
+        "qz_batch_sync": ([vp], i32),
+        "qz_batch_slot_reset": ([vp, sz, u64], i32),
+        "qz_batch_slot_active": ([vp, sz, i32], i32),
+        "qz_batch_slot_time": ([vp, sz, c.POINTER(u64)], i32),
+        "qz_batch_trace": ([vp, sz, u64, u64, c.POINTER(u64)], i32),
+        "qz_batch_download": ([vp, sz, c.POINTER(c.c_int8)], i32),
+        "qz_batch_bonds": ([vp, sz, c.POINTER(u64)], i32),
+        "qz_batch_corr": ([vp, sz, c.POINTER(c.c_int64), c.POINTER(c.c_int64)], i32),
+        "qz_batch_set_tuning": ([vp, u32, u32, u32], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+
+
+_batch_signatures()
+
+
+def batch_state_bytes(specs, trace_cap: int) -> int:
+    arr = (_ReplicaSpec * len(specs))(*[_ReplicaSpec(int(L), int(s) & (2**64 - 1))
+                                        for L, s in specs])
+    return int(lib.qz_batch_state_bytes(arr, len(specs), trace_cap))
+
+
+class Batch:
+    """Replica slots (L, seed) advanced together on the device."""
+
+    def __init__(self, specs, trace_every: int = 0, trace_cap: int = 1024, device=None,
+                 stream=None):
+        import torch
+        self.specs = [(int(L), int(s)) for L, s in specs]
+        arr = (_ReplicaSpec * len(self.specs))(*[_ReplicaSpec(L, s & (2**64 - 1))
+                                                 for L, s in self.specs])
+        nbytes = int(lib.qz_batch_state_bytes(arr, len(self.specs), trace_cap))
+        if nbytes == 0:
+            raise QuenchError(QZ_EUNSUPPORTED, "unsupported replica size in the batch")
+        device = torch.device("cuda") if device is None else torch.device(device)
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream, sh = _stream_handle(stream)
+        self.trace_every, self.trace_cap = int(trace_every), int(trace_cap)
+        h = ctypes.c_void_p()
+        _check(lib.qz_batch_create(arr, len(self.specs), self.trace_every, self.trace_cap,
+                                   ctypes.c_void_p(self.mem.data_ptr()), nbytes, sh,
+                                   ctypes.byref(h)))
+        self._h = h
+
+    def __len__(self):
+        return len(self.specs)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.qz_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, n: int) -> None:
+        _check(lib.qz_batch_run(self._h, n))
+
+    def sync(self) -> None:
+        _check(lib.qz_batch_sync(self._h))
+
+    def reset(self, slot: int, seed: int) -> None:
+        _check(lib.qz_batch_slot_reset(self._h, slot, int(seed) & (2**64 - 1)))
+        self.specs[slot] = (self.specs[slot][0], int(seed))
+
+    def set_active(self, slot: int, active: bool) -> None:
+        _check(lib.qz_batch_slot_active(self._h, slot, 1 if active else 0))
+
+    def time(self, slot: int) -> int:
+        v = ctypes.c_uint64()
+        _check(lib.qz_batch_slot_time(self._h, slot, ctypes.byref(v)))
+        return int(v.value)
+
+    def trace(self, slot: int, t_from: int, count: int) -> np.ndarray:
+        out = np.zeros(count, dtype=np.uint64)
+        _check(lib.qz_batch_trace(self._h, slot, t_from, count,
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return out
+
+    def download(self, slot: int) -> np.ndarray:
+        L = self.specs[slot][0]
+        out = np.empty((L, L, L), dtype=np.int8)
+        _check(lib.qz_batch_download(self._h, slot,
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))))
+        return out
+
+    def bonds(self, slot: int) -> np.ndarray:
+        out = np.zeros(3, dtype=np.uint64)
+        _check(lib.qz_batch_bonds(self._h, slot, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return out.astype(np.int64)
+
+    def corr(self, slot: int):
+        L = self.specs[slot][0]
+        S = np.zeros((3, L // 2 + 1), dtype=np.int64)
+        M = ctypes.c_int64()
+        _check(lib.qz_batch_corr(self._h, slot, S.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 ctypes.byref(M)))
+        return S, int(M.value)
+
+    def set_tuning(self, L: int, Tz: int, graph_sweeps: int) -> None:
+        _check(lib.qz_batch_set_tuning(self._h, L, Tz, graph_sweeps))

@@ -125,6 +125,8 @@ int run_impl(qz_lattice *q, uint64_t n, uint64_t every, unsigned long long *dev_
 }  // namespace
 
 namespace qz {
+int set_error(int status, const char *msg) { return fail(status, msg); }
+
 bool state_map(uint32_t L, int layout, StateMap *m)
 {
     if (!layout_ok(L, layout))

@@ -1,0 +1,237 @@
+// qz_batch.hip -- one launch sweeps many independent 1-bit lattices (replicas).
+//
+// Each replica uses the colour-separated 1-bit layout of the single-lattice
+// path (plane c = words [z][y][W], W = L/64) with two copies (read / write).
+// A launch performs ONE sweep (colour 0 then colour 1, Methods "Checkerboard
+// update") of every active replica, each at its own time t, so replicas of
+// different L and different ages can share a launch.  The work is cut into
+// sub-tiles: Tz consecutive planes (whole planes) of one replica.  A lane owns
+// a quad -- 4 consecutive words of a plane, i.e. exactly one Philox block of
+// tie bits -- so no lane draws bits it does not use, even when a row is only
+// one or two words long.  A workgroup of 256 lanes runs 256/Q sub-tiles of one
+// lattice size in lockstep (Q = quads per plane), streaming along z as the
+// single-lattice kernel does: colour 0 of plane q, then colour 1 of plane q-1,
+// with the other colour's plane exchanged through LDS.
+#include "qz_device.hpp"
+#include "qz_internal.hpp"
+
+namespace qz {
+namespace {
+
+constexpr int kBatchBlock = 256;
+
+__global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
+{
+    extern __shared__ uint32_t lds[];
+    const uint32_t tid = threadIdx.x;
+    const BatchGroup G = A.groups[blockIdx.x];          // all sub-tiles of this block share L, nz
+    const uint32_t L = G.L, W = L / 64, PW = L * W;    // words per plane
+    const uint32_t Q = PW / 4;                          // quads (lanes) per plane
+    const uint32_t S = kBatchBlock / Q >= 1 ? kBatchBlock / Q : 1;
+    const uint32_t sub = tid / Q, lane = tid % Q;
+    const uint32_t nz = G.nz;
+
+    // this lane's sub-tile
+    bool act = false;
+    BatchTile T = {0u, 0u};
+    BatchReplica R;
+    if (sub < S && G.first + sub < G.last) {
+        T = A.tiles[G.first + sub];
+        R = A.reps[T.slot];
+        act = R.active != 0u;
+    }
+    const uint64_t t64 = act ? R.t + A.step : 0;
+    const uint32_t t = (uint32_t)t64;
+    const uint32_t rd = act ? ((R.cur ^ A.step) & 1u) : 0u;
+    const size_t pw_all = (size_t)L * PW;                // words of one colour plane set
+    const uint32_t *S0 = act ? R.base + (2 * rd + 0) * pw_all : nullptr;
+    const uint32_t *S1 = act ? R.base + (2 * rd + 1) * pw_all : nullptr;
+    uint32_t *D0 = act ? R.base + (2 * (1 - rd) + 0) * pw_all : nullptr;
+    uint32_t *D1 = act ? R.base + (2 * (1 - rd) + 1) * pw_all : nullptr;
+    const bool counting = act && A.every != 0u && R.trace != nullptr && (t64 % A.every) == 0u;
+    const uint32_t k0 = act ? (uint32_t)R.seed : 0u, k1 = act ? (uint32_t)(R.seed >> 32) : 0u;
+
+    // word geometry of this lane's quad within a plane
+    const uint32_t g0 = 4 * lane;
+    uint32_t yv[4], gym[4], gyp[4], gpr[4], gnx[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const uint32_t g = g0 + v, y = g / W, w = g % W;
+        yv[v] = y;
+        gym[v] = (g + PW - W) % PW;
+        gyp[v] = (g + W) % PW;
+        gpr[v] = (w == 0) ? g + W - 1 : g - 1;          // x-neighbour at colour index k-1
+        gnx[v] = (w == W - 1) ? g + 1 - W : g + 1;      // x-neighbour at colour index k+1
+    }
+
+    uint32_t *X1base = lds + (size_t)sub * 4 * PW;       // [2 buffers][X1 | X0][PW]
+    uint32_t c1m[4], c1c[4], c1p[4], c0o[4], n0m2[4], n0m1[4], n0c[4], c1n[4], pf1[4], pf0[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        c1m[v] = c1c[v] = c1p[v] = c0o[v] = n0m2[v] = n0m1[v] = n0c[v] = c1n[v] = pf1[v] = pf0[v] = 0u;
+    auto ld4 = [&](const uint32_t *P, uint32_t z, uint32_t (&r)[4]) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(P + (size_t)z * PW + g0);
+        r[0] = q.x; r[1] = q.y; r[2] = q.z; r[3] = q.w;
+    };
+    auto st4 = [&](uint32_t *P, uint32_t z, const uint32_t (&r)[4]) {
+        *reinterpret_cast<uint4 *>(P + (size_t)z * PW + g0) = make_uint4(r[0], r[1], r[2], r[3]);
+    };
+    const uint32_t z0 = T.z0;
+    if (act) {
+        ld4(S1, (z0 + L - 2) % L, c1m);
+        ld4(S1, (z0 + L - 1) % L, c1c);
+        ld4(S1, z0 % L, c1p);
+        ld4(S0, (z0 + L - 1) % L, c0o);
+    }
+    int bonds = 0;
+
+    // one colour update of the lane's quad; Xo = other colour's plane in LDS,
+    // same = the lane's own words of that plane, zm/zp = planes below/above
+    auto update = [&](const uint32_t *Xo, const uint32_t (&own)[4], const uint32_t (&same)[4],
+                      const uint32_t (&zmn)[4], const uint32_t (&zpn)[4], uint32_t zp_plane,
+                      uint32_t colour, uint32_t (&out)[4], bool count) {
+        UpCount c[4];
+        uint32_t ties = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t pi = (colour + yv[v] + zp_plane) & 1u;
+            const uint32_t adj = Xo[pi ? gnx[v] : gpr[v]];
+            const uint32_t sh = pi ? funnel(adj, same[v], 1) : funnel(same[v], adj, 31);
+            c[v] = count_up(same[v], sh, Xo[gym[v]], Xo[gyp[v]], zmn[v], zpn[v]);
+            ties |= up_tie(c[v]);
+        }
+        uint32_t r[4] = {0u, 0u, 0u, 0u};
+        if (ties != 0u) {
+            const uint32_t blk = (zp_plane * PW + g0) >> 2;      // Philox block = word index / 4
+            const Words4 rb = philox10(blk, t, colour, 0u, k0, k1);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                r[v] = rb.w[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            out[v] = up_rule(own[v], c[v], r[v]);
+            if (count)
+                bonds += up_antialigned_sum(own[v], c[v]);
+        }
+    };
+
+    for (int qi = -1; qi <= (int)nz; ++qi) {
+        const uint32_t zq = (z0 + L + qi) % L;
+        const uint32_t zm = (zq + L - 1) % L;
+        if (act && qi < (int)nz) {
+            ld4(S1, (zq + 2) % L, pf1);
+            ld4(S0, (zq + 1) % L, pf0);
+        }
+        uint32_t *X1 = X1base + (size_t)(qi & 1) * 2 * PW;
+        uint32_t *X0 = X1 + PW;
+        if (act) {
+            *reinterpret_cast<uint4 *>(X1 + g0) = make_uint4(c1c[0], c1c[1], c1c[2], c1c[3]);
+            *reinterpret_cast<uint4 *>(X0 + g0) = make_uint4(n0m1[0], n0m1[1], n0m1[2], n0m1[3]);
+        }
+        __syncthreads();
+        if (act) {
+            const bool mine = qi >= 0 && qi < (int)nz;
+            update(X1, c0o, c1c, c1m, c1p, zq, 0u, n0c, counting && mine);
+            if (mine)
+                st4(D0, zq, n0c);
+            if (qi >= 1) {
+                update(X0, c1m, n0m1, n0m2, n0c, zm, 1u, c1n, false);
+                st4(D1, zm, c1n);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                c1m[v] = c1c[v];
+                c1c[v] = c1p[v];
+                c1p[v] = pf1[v];
+                c0o[v] = pf0[v];
+                n0m2[v] = n0m1[v];
+                n0m1[v] = n0c[v];
+            }
+        }
+    }
+    // per-sub-tile bond sums -> the replica's trace slot
+    __syncthreads();
+    uint32_t *sacc = lds;                                 // S counters
+    if (tid < S)
+        sacc[tid] = 0u;
+    __syncthreads();
+    if (counting && bonds)
+        atomicAdd(sacc + sub, (uint32_t)bonds);
+    __syncthreads();
+    if (counting && lane == 0 && sacc[sub]) {
+        const uint32_t slot = (uint32_t)((t64 / A.every) % A.cap);
+        atomicAdd(R.trace + slot, (unsigned long long)sacc[sub]);
+    }
+}
+
+// After a group of k sweeps: every active replica's time advances by k and
+// its current copy flips k times; traced slots of the next group are cleared.
+__global__ void k_batch_advance(BatchReplica *reps, uint32_t n, uint32_t k)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && reps[i].active) {
+        reps[i].t += k;
+        reps[i].cur ^= (k & 1u);
+    }
+}
+
+// Zero trace slots of active replicas for times [t0, t0 + span) before they
+// are accumulated (launched as a kernel so that it can sit inside a graph).
+__global__ void k_batch_clear_trace(BatchReplica *reps, uint32_t n, uint32_t span, uint32_t every,
+                                    uint32_t cap)
+{
+    const uint32_t i = blockIdx.x;
+    if (i >= n || !reps[i].active || reps[i].trace == nullptr)
+        return;
+    const uint64_t t0 = reps[i].t;
+    for (uint32_t d = threadIdx.x; d < span; d += blockDim.x) {
+        const uint64_t t = t0 + d;
+        if (t % every == 0u)
+            reps[i].trace[(t / every) % cap] = 0ull;
+    }
+}
+
+}  // namespace
+
+uint32_t batch_subtiles_per_block(uint32_t L)
+{
+    const uint32_t Q = L * (L / 64) / 4;
+    return Q >= (uint32_t)kBatchBlock ? 1u : (uint32_t)kBatchBlock / Q;
+}
+
+bool batch_size_ok(uint32_t L)
+{
+    if (L < 64 || L % 64)
+        return false;
+    const uint32_t PW = L * (L / 64);
+    const uint32_t Q = PW / 4;
+    if (Q > (uint32_t)kBatchBlock)
+        return false;                       // one plane per workgroup of 256 lanes
+    return (size_t)batch_subtiles_per_block(L) * 4 * PW * 4 <= 60 * 1024;
+}
+
+hipError_t batch_sweep(hipStream_t st, const BatchArgs &a, uint32_t ngroups)
+{
+    if (ngroups == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_batch_sweep, dim3(ngroups), dim3(kBatchBlock), a.lds_bytes, st, a);
+    return hipGetLastError();
+}
+
+hipError_t batch_advance(hipStream_t st, BatchReplica *reps, uint32_t n, uint32_t k)
+{
+    hipLaunchKernelGGL(k_batch_advance, dim3((n + 255) / 256), dim3(256), 0, st, reps, n, k);
+    return hipGetLastError();
+}
+
+hipError_t batch_clear_trace(hipStream_t st, BatchReplica *reps, uint32_t n, uint32_t span,
+                             uint32_t every, uint32_t cap)
+{
+    if (n == 0 || every == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_batch_clear_trace, dim3(n), dim3(64), 0, st, reps, n, span, every, cap);
+    return hipGetLastError();
+}
+
+}  // namespace qz

@@ -1,0 +1,563 @@
+// qz_batch_api.hip -- C ABI of the batched engine (include/quench.h, qz_batch_*).
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/quench.h"
+#include "qz_internal.hpp"
+
+#define QZ_EXPORT extern "C" __attribute__((visibility("default")))
+
+namespace qz {
+// shared with qz_api.hip: sets the calling thread's last error
+int set_error(int status, const char *msg);
+}  // namespace qz
+
+struct qz_batch {
+    hipStream_t st;                          // caller's stream (all work)
+    hipStream_t cap_st;                      // private stream used only to capture graphs
+    uint8_t *base;
+    size_t bytes;
+    uint32_t every, cap;
+    std::vector<qz_replica_spec> specs;
+    std::vector<qz::BatchReplica> host_reps;  // mirror of the device table
+    qz::BatchReplica *d_reps;
+    qz::BatchTile *d_tiles;
+    qz::BatchGroup *d_groups;
+    uint32_t ntiles, ngroups;
+    size_t lds_bytes;
+    int8_t *stage;
+    size_t stage_bytes;
+    unsigned long long *counters;            // 64 scratch counters
+    unsigned long long *corr;                // correlation accumulators for the largest L
+    std::map<uint32_t, uint32_t> tz;         // planes per sub-tile, by L
+    uint32_t graph_sweeps;
+    hipGraphExec_t graph;
+    bool graph_ok;
+    bool failed;
+    bool dirty;                              // host table newer than the device copy
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+uint64_t nsites(uint32_t L) { return (uint64_t)L * L * L; }
+size_t replica_bytes(uint32_t L) { return align256((size_t)(nsites(L) / 8) * 2); }
+
+int fail(int status, const std::string &msg) { return qz::set_error(status, msg.c_str()); }
+
+int dev_fail(qz_batch *b, hipError_t e, const char *where)
+{
+    if (b)
+        b->failed = true;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+    return fail(QZ_EDEVICE, buf);
+}
+
+#define BZ_HIP(b, call)                              \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess)                        \
+            return dev_fail((b), e_, #call);         \
+    } while (0)
+
+uint32_t default_tz(uint32_t L)
+{
+    if (L <= 64)
+        return 16;
+    if (L <= 128)
+        return 16;
+    return 32;
+}
+
+struct Layout {
+    std::vector<size_t> rep_off;
+    size_t reps_off, tiles_off, groups_off, trace_off, counters_off, corr_off, stage_off;
+    size_t stage_bytes, total;
+    uint32_t max_L;
+    size_t max_tiles, max_groups;
+};
+
+// Device layout for a slot list; sizes of the tile/group tables are bounded by
+// the smallest plane count per sub-tile (8).
+bool plan(const qz_replica_spec *specs, size_t n, uint32_t cap, Layout *lay)
+{
+    size_t off = 0;
+    lay->rep_off.resize(n);
+    lay->max_L = 0;
+    lay->max_tiles = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const uint32_t L = specs[i].L;
+        if (!qz::batch_size_ok(L))
+            return false;
+        lay->rep_off[i] = off;
+        off += replica_bytes(L);
+        lay->max_L = std::max(lay->max_L, L);
+        lay->max_tiles += (L + 7) / 8;
+    }
+    lay->max_groups = lay->max_tiles;
+    lay->reps_off = off;
+    off = align256(off + n * sizeof(qz::BatchReplica));
+    lay->tiles_off = off;
+    off = align256(off + lay->max_tiles * sizeof(qz::BatchTile));
+    lay->groups_off = off;
+    off = align256(off + lay->max_groups * sizeof(qz::BatchGroup));
+    lay->trace_off = off;
+    off = align256(off + n * (size_t)cap * 8);
+    lay->counters_off = off;
+    off = align256(off + 64 * 8);
+    lay->corr_off = off;
+    off = align256(off + (size_t)(3 * (lay->max_L / 2 + 1) + 1) * 8);
+    lay->stage_off = off;
+    lay->stage_bytes = std::min<size_t>(nsites(lay->max_L), size_t(32) << 20);
+    lay->stage_bytes = std::max<size_t>(lay->stage_bytes, (size_t)lay->max_L * lay->max_L);
+    off = align256(off + lay->stage_bytes);
+    lay->total = off;
+    return true;
+}
+
+// Rebuild the tile and group tables (slots grouped by L; sub-tiles of Tz
+// planes; S sub-tiles of one L per workgroup).
+int build_tables(qz_batch *b)
+{
+    std::map<uint32_t, std::vector<uint32_t>> by_L;
+    for (size_t i = 0; i < b->specs.size(); ++i)
+        by_L[b->specs[i].L].push_back((uint32_t)i);
+    std::vector<qz::BatchTile> tiles;
+    std::vector<qz::BatchGroup> groups;
+    for (auto &kv : by_L) {
+        const uint32_t L = kv.first;
+        uint32_t tz = b->tz.count(L) ? b->tz[L] : default_tz(L);
+        if (tz < 8 || L % tz)
+            tz = default_tz(L);
+        const uint32_t S = qz::batch_subtiles_per_block(L);
+        const size_t start = tiles.size();
+        for (uint32_t slot : kv.second)
+            for (uint32_t z0 = 0; z0 < L; z0 += tz)
+                tiles.push_back({slot, z0});
+        for (size_t f = start; f < tiles.size(); f += S) {
+            qz::BatchGroup g;
+            g.L = L;
+            g.nz = tz;
+            g.first = (uint32_t)f;
+            g.last = (uint32_t)std::min(tiles.size(), f + S);
+            groups.push_back(g);
+        }
+    }
+    b->ntiles = (uint32_t)tiles.size();
+    b->ngroups = (uint32_t)groups.size();
+    BZ_HIP(b, hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(qz::BatchTile),
+                             hipMemcpyHostToDevice, b->st));
+    BZ_HIP(b, hipMemcpyAsync(b->d_groups, groups.data(), groups.size() * sizeof(qz::BatchGroup),
+                             hipMemcpyHostToDevice, b->st));
+    BZ_HIP(b, hipStreamSynchronize(b->st));
+    b->lds_bytes = 0;
+    for (auto &kv : by_L) {
+        const uint32_t L = kv.first, PW = L * (L / 64);
+        b->lds_bytes = std::max(b->lds_bytes,
+                                (size_t)qz::batch_subtiles_per_block(L) * 4 * PW * 4);
+    }
+    return QZ_OK;
+}
+
+int push_reps(qz_batch *b)
+{
+    BZ_HIP(b, hipMemcpyAsync(b->d_reps, b->host_reps.data(),
+                             b->host_reps.size() * sizeof(qz::BatchReplica),
+                             hipMemcpyHostToDevice, b->st));
+    BZ_HIP(b, hipStreamSynchronize(b->st));
+    b->dirty = false;
+    return QZ_OK;
+}
+
+// Enqueue one group of k sweeps on stream s: clear the traced slots, k sweep
+// launches (step = 0..k-1), then advance every active replica by k.
+hipError_t enqueue_group(qz_batch *b, hipStream_t s, uint32_t k)
+{
+    hipError_t e = qz::batch_clear_trace(s, b->d_reps, (uint32_t)b->specs.size(), k, b->every,
+                                         b->cap);
+    if (e != hipSuccess)
+        return e;
+    qz::BatchArgs a;
+    a.reps = b->d_reps;
+    a.tiles = b->d_tiles;
+    a.groups = b->d_groups;
+    a.every = b->every;
+    a.cap = b->cap;
+    a.lds_bytes = b->lds_bytes;
+    for (uint32_t j = 0; j < k; ++j) {
+        a.step = j;
+        e = qz::batch_sweep(s, a, b->ngroups);
+        if (e != hipSuccess)
+            return e;
+    }
+    return qz::batch_advance(s, b->d_reps, (uint32_t)b->specs.size(), k);
+}
+
+int ensure_graph(qz_batch *b)
+{
+    if (b->graph_ok || b->graph_sweeps == 0)
+        return QZ_OK;
+    hipGraph_t g = nullptr;
+    BZ_HIP(b, hipStreamBeginCapture(b->cap_st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_group(b, b->cap_st, b->graph_sweeps);
+    hipError_t e2 = hipStreamEndCapture(b->cap_st, &g);
+    if (e != hipSuccess)
+        return dev_fail(b, e, "capturing the sweep graph");
+    if (e2 != hipSuccess)
+        return dev_fail(b, e2, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
+        return dev_fail(b, e, "hipGraphInstantiate");
+    b->graph_ok = true;
+    return QZ_OK;
+}
+
+void drop_graph(qz_batch *b)
+{
+    if (b->graph_ok)
+        (void)hipGraphExecDestroy(b->graph);
+    b->graph_ok = false;
+}
+
+int check(qz_batch *b)
+{
+    if (!b)
+        return fail(QZ_EINVAL, "null batch handle");
+    if (b->failed)
+        return fail(QZ_ESTATE, "batch unusable after an earlier device failure");
+    return QZ_OK;
+}
+
+int check_slot(qz_batch *b, size_t slot)
+{
+    int rc = check(b);
+    if (rc != QZ_OK)
+        return rc;
+    if (slot >= b->specs.size())
+        return fail(QZ_EINVAL, "slot out of range");
+    return QZ_OK;
+}
+
+// bring the host mirror's times up to date after device-side advances
+int pull_reps(qz_batch *b)
+{
+    BZ_HIP(b, hipMemcpyAsync(b->host_reps.data(), b->d_reps,
+                             b->host_reps.size() * sizeof(qz::BatchReplica),
+                             hipMemcpyDeviceToHost, b->st));
+    BZ_HIP(b, hipStreamSynchronize(b->st));
+    return QZ_OK;
+}
+
+uint32_t *slot_plane(qz_batch *b, size_t slot, int copy, int colour)
+{
+    const qz::BatchReplica &r = b->host_reps[slot];
+    const uint32_t L = b->specs[slot].L;
+    return r.base + (size_t)(2 * copy + colour) * (nsites(L) / 64);
+}
+
+}  // namespace
+
+QZ_EXPORT size_t qz_batch_state_bytes(const qz_replica_spec *specs, size_t n, uint32_t trace_cap)
+{
+    if (!specs || n == 0)
+        return 0;
+    Layout lay;
+    return plan(specs, n, trace_cap, &lay) ? lay.total : 0;
+}
+
+QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t trace_every,
+                              uint32_t trace_cap, void *dev_mem, size_t dev_bytes,
+                              void *hip_stream, qz_batch **out)
+{
+    if (!out)
+        return fail(QZ_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!specs || n == 0 || n > (1u << 20))
+        return fail(QZ_EINVAL, "need 1 .. 2^20 replica specs");
+    if (trace_every > 0 && trace_cap == 0)
+        return fail(QZ_EINVAL, "trace_cap must be > 0 when tracing");
+    for (size_t i = 0; i < n; ++i)
+        if (!qz::batch_size_ok(specs[i].L))
+            return fail(QZ_EUNSUPPORTED, "batched replicas need L % 64 == 0 and L <= 256");
+    if (!dev_mem || (reinterpret_cast<uintptr_t>(dev_mem) & 255u))
+        return fail(QZ_EINVAL, "device buffer must be non-null and 256-byte aligned");
+    Layout lay;
+    plan(specs, n, trace_cap, &lay);
+    if (dev_bytes < lay.total)
+        return fail(QZ_ENOMEM, "device buffer smaller than qz_batch_state_bytes()");
+    qz_batch *b = new (std::nothrow) qz_batch();
+    if (!b)
+        return fail(QZ_ENOMEM, "host allocation failed");
+    b->st = reinterpret_cast<hipStream_t>(hip_stream);
+    b->cap_st = nullptr;
+    b->base = reinterpret_cast<uint8_t *>(dev_mem);
+    b->bytes = dev_bytes;
+    b->every = trace_every;
+    b->cap = trace_every ? trace_cap : 1;
+    b->specs.assign(specs, specs + n);
+    b->d_reps = reinterpret_cast<qz::BatchReplica *>(b->base + lay.reps_off);
+    b->d_tiles = reinterpret_cast<qz::BatchTile *>(b->base + lay.tiles_off);
+    b->d_groups = reinterpret_cast<qz::BatchGroup *>(b->base + lay.groups_off);
+    b->stage = reinterpret_cast<int8_t *>(b->base + lay.stage_off);
+    b->stage_bytes = lay.stage_bytes;
+    b->counters = reinterpret_cast<unsigned long long *>(b->base + lay.counters_off);
+    b->corr = reinterpret_cast<unsigned long long *>(b->base + lay.corr_off);
+    b->graph_sweeps = 16;
+    b->graph_ok = false;
+    b->failed = false;
+    b->host_reps.resize(n);
+    unsigned long long *traces = reinterpret_cast<unsigned long long *>(b->base + lay.trace_off);
+    for (size_t i = 0; i < n; ++i) {
+        qz::BatchReplica &r = b->host_reps[i];
+        r.base = reinterpret_cast<uint32_t *>(b->base + lay.rep_off[i]);
+        r.trace = trace_every ? traces + i * (size_t)trace_cap : nullptr;
+        r.seed = specs[i].seed;
+        r.t = 0;
+        r.cur = 0;
+        r.active = 1;
+    }
+    hipError_t e = hipStreamCreateWithFlags(&b->cap_st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        int rc = dev_fail(nullptr, e, "hipStreamCreateWithFlags");
+        delete b;
+        return rc;
+    }
+    int rc = build_tables(b);
+    if (rc == QZ_OK)
+        rc = push_reps(b);
+    for (size_t i = 0; rc == QZ_OK && i < n; ++i) {
+        e = qz::bit_init(b->st, specs[i].L, specs[i].seed, slot_plane(b, i, 0, 0),
+                         slot_plane(b, i, 0, 1));
+        if (e != hipSuccess)
+            rc = dev_fail(b, e, "init kernel");
+    }
+    if (rc != QZ_OK) {
+        (void)hipStreamDestroy(b->cap_st);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_batch_destroy(qz_batch *b)
+{
+    if (!b)
+        return fail(QZ_EINVAL, "null batch handle");
+    drop_graph(b);
+    if (b->cap_st)
+        (void)hipStreamDestroy(b->cap_st);
+    delete b;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_batch_set_tuning(qz_batch *b, uint32_t L, uint32_t Tz, uint32_t graph_sweeps)
+{
+    int rc = check(b);
+    if (rc != QZ_OK)
+        return rc;
+    if (Tz != 0) {
+        if (!qz::batch_size_ok(L) || Tz < 8 || L % Tz)
+            return fail(QZ_EINVAL, "Tz must divide L and be >= 8");
+        b->tz[L] = Tz;
+    }
+    b->graph_sweeps = graph_sweeps;
+    drop_graph(b);
+    return build_tables(b);
+}
+
+QZ_EXPORT int qz_batch_run(qz_batch *b, uint64_t n_sweeps)
+{
+    int rc = check(b);
+    if (rc != QZ_OK)
+        return rc;
+    if (b->dirty) {
+        rc = push_reps(b);
+        if (rc != QZ_OK)
+            return rc;
+    }
+    uint64_t left = n_sweeps;
+    if (b->graph_sweeps > 0 && left >= b->graph_sweeps) {
+        rc = ensure_graph(b);
+        if (rc != QZ_OK)
+            return rc;
+        while (left >= b->graph_sweeps) {
+            BZ_HIP(b, hipGraphLaunch(b->graph, b->st));
+            left -= b->graph_sweeps;
+        }
+    }
+    if (left > 0)
+        BZ_HIP(b, enqueue_group(b, b->st, (uint32_t)left));
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_batch_sync(qz_batch *b)
+{
+    int rc = check(b);
+    if (rc != QZ_OK)
+        return rc;
+    BZ_HIP(b, hipStreamSynchronize(b->st));
+    return pull_reps(b);
+}
+
+QZ_EXPORT int qz_batch_slot_time(qz_batch *b, size_t slot, uint64_t *t)
+{
+    int rc = check_slot(b, slot);
+    if (rc != QZ_OK)
+        return rc;
+    if (!t)
+        return fail(QZ_EINVAL, "null output");
+    rc = pull_reps(b);
+    if (rc != QZ_OK)
+        return rc;
+    *t = b->host_reps[slot].t;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_batch_slot_reset(qz_batch *b, size_t slot, uint64_t seed)
+{
+    int rc = check_slot(b, slot);
+    if (rc != QZ_OK)
+        return rc;
+    rc = pull_reps(b);
+    if (rc != QZ_OK)
+        return rc;
+    qz::BatchReplica &r = b->host_reps[slot];
+    r.seed = seed;
+    r.t = 0;
+    r.cur = 0;
+    r.active = 1;
+    b->specs[slot].seed = seed;
+    BZ_HIP(b, qz::bit_init(b->st, b->specs[slot].L, seed, slot_plane(b, slot, 0, 0),
+                           slot_plane(b, slot, 0, 1)));
+    return push_reps(b);
+}
+
+QZ_EXPORT int qz_batch_slot_active(qz_batch *b, size_t slot, int active)
+{
+    int rc = check_slot(b, slot);
+    if (rc != QZ_OK)
+        return rc;
+    rc = pull_reps(b);
+    if (rc != QZ_OK)
+        return rc;
+    b->host_reps[slot].active = active ? 1u : 0u;
+    return push_reps(b);
+}
+
+QZ_EXPORT int qz_batch_trace(qz_batch *b, size_t slot, uint64_t t_from, uint64_t count,
+                             uint64_t *host)
+{
+    int rc = check_slot(b, slot);
+    if (rc != QZ_OK)
+        return rc;
+    if (b->every == 0)
+        return fail(QZ_EINVAL, "the batch was created without a trace");
+    if (!host && count)
+        return fail(QZ_EINVAL, "null output");
+    if (t_from % b->every)
+        return fail(QZ_EINVAL, "t_from must be a multiple of trace_every");
+    rc = pull_reps(b);
+    if (rc != QZ_OK)
+        return rc;
+    const uint64_t tnow = b->host_reps[slot].t;
+    // B(t) is recorded by sweep t, so times up to tnow - 1 are available; the
+    // ring holds the last cap of them
+    const uint64_t k_from = t_from / b->every;
+    if (count > 0) {
+        const uint64_t k_last = k_from + count - 1;
+        if (k_last * b->every >= tnow)
+            return fail(QZ_EINVAL, "trace requested beyond the slot's current time");
+        const uint64_t k_newest = (tnow - 1) / b->every;
+        if (k_newest - k_from >= b->cap)
+            return fail(QZ_EINVAL, "trace entries already overwritten in the ring");
+    }
+    std::vector<unsigned long long> ring(b->cap);
+    BZ_HIP(b, hipMemcpyAsync(ring.data(), b->host_reps[slot].trace, (size_t)b->cap * 8,
+                             hipMemcpyDeviceToHost, b->st));
+    BZ_HIP(b, hipStreamSynchronize(b->st));
+    for (uint64_t i = 0; i < count; ++i)
+        host[i] = ring[(k_from + i) % b->cap];
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_batch_download(qz_batch *b, size_t slot, int8_t *host)
+{
+    int rc = check_slot(b, slot);
+    if (rc != QZ_OK)
+        return rc;
+    if (!host)
+        return fail(QZ_EINVAL, "null output");
+    rc = pull_reps(b);
+    if (rc != QZ_OK)
+        return rc;
+    const uint32_t L = b->specs[slot].L;
+    const int c = (int)b->host_reps[slot].cur;
+    const uint64_t plane = (uint64_t)L * L;
+    const uint32_t nzc = (uint32_t)std::max<uint64_t>(1, b->stage_bytes / plane);
+    for (uint32_t z0 = 0; z0 < L; z0 += nzc) {
+        const uint32_t nz = std::min<uint32_t>(nzc, L - z0);
+        BZ_HIP(b, qz::bit_unpack(b->st, L, slot_plane(b, slot, c, 0), slot_plane(b, slot, c, 1),
+                                 z0, nz, b->stage));
+        BZ_HIP(b, hipMemcpyAsync(host + z0 * plane, b->stage, (size_t)nz * plane,
+                                 hipMemcpyDeviceToHost, b->st));
+        BZ_HIP(b, hipStreamSynchronize(b->st));
+    }
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_batch_bonds(qz_batch *b, size_t slot, uint64_t out_B_axes[3])
+{
+    int rc = check_slot(b, slot);
+    if (rc != QZ_OK)
+        return rc;
+    if (!out_B_axes)
+        return fail(QZ_EINVAL, "null output");
+    rc = pull_reps(b);
+    if (rc != QZ_OK)
+        return rc;
+    const uint32_t L = b->specs[slot].L;
+    const int c = (int)b->host_reps[slot].cur;
+    BZ_HIP(b, qz::fill_u64(b->st, b->counters, 3, 0ull));
+    BZ_HIP(b, qz::bit_bonds(b->st, L, slot_plane(b, slot, c, 0), slot_plane(b, slot, c, 1),
+                            b->counters));
+    unsigned long long h[3];
+    BZ_HIP(b, hipMemcpyAsync(h, b->counters, sizeof h, hipMemcpyDeviceToHost, b->st));
+    BZ_HIP(b, hipStreamSynchronize(b->st));
+    for (int a = 0; a < 3; ++a)
+        out_B_axes[a] = h[a];
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_batch_corr(qz_batch *b, size_t slot, int64_t *out_S, int64_t *out_M)
+{
+    int rc = check_slot(b, slot);
+    if (rc != QZ_OK)
+        return rc;
+    if (!out_S || !out_M)
+        return fail(QZ_EINVAL, "null output");
+    rc = pull_reps(b);
+    if (rc != QZ_OK)
+        return rc;
+    const uint32_t L = b->specs[slot].L, R = L / 2 + 1;
+    const int c = (int)b->host_reps[slot].cur;
+    BZ_HIP(b, qz::fill_u64(b->st, b->corr, 3 * (size_t)R + 1, 0ull));
+    BZ_HIP(b, qz::bit_corr(b->st, L, slot_plane(b, slot, c, 0), slot_plane(b, slot, c, 1), b->corr,
+                           b->corr + 3 * R));
+    std::vector<unsigned long long> h(3 * (size_t)R + 1);
+    BZ_HIP(b, hipMemcpyAsync(h.data(), b->corr, h.size() * 8, hipMemcpyDeviceToHost, b->st));
+    BZ_HIP(b, hipStreamSynchronize(b->st));
+    const int64_t N = (int64_t)nsites(L);
+    for (size_t k = 0; k < 3 * (size_t)R; ++k)
+        out_S[k] = N - 2 * (int64_t)h[k];
+    *out_M = 2 * (int64_t)h[3 * R] - N;
+    return QZ_OK;
+}

@@ -59,6 +59,16 @@ __device__ __forceinline__ void store_words(uint32_t *p, const uint32_t (&r)[V])
     }
 }
 
+// Store to HBM with the nontemporal hint: the written copy is not read again
+// in this sweep, so it should not displace the read copy's rows from cache.
+template <int V>
+__device__ __forceinline__ void store_words_nt(uint32_t *p, const uint32_t (&r)[V])
+{
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        __builtin_nontemporal_store(r[v], p + v);
+}
+
 struct SweepArgs {
     const uint32_t *S0, *S1;   // read copy, colour planes 0 and 1
     uint32_t *D0, *D1;         // write copy
@@ -73,16 +83,16 @@ struct SweepArgs {
 // other colour's same-row words (x-neighbour at the same index); adj = the
 // word just outside the lane's range on the side given by pi; ym/yp/zm/zp the
 // other colour's rows y-1, y+1 and planes z-1, z+1.
-template <int V>
+// COUNT: also add the sites' anti-aligned counts (sum a) to `acc`.
+template <int V, bool COUNT>
 __device__ __forceinline__ void update_words(const uint32_t (&own)[V], const uint32_t (&same)[V],
                                              uint32_t adj, uint32_t pi, const uint32_t (&ym)[V],
                                              const uint32_t (&yp)[V], const uint32_t (&zm)[V],
                                              const uint32_t (&zp)[V], uint32_t k0, uint32_t k1,
                                              uint32_t ctr0, uint32_t sub, uint32_t t, uint32_t p,
-                                             uint32_t (&out)[V], uint32_t &cnt0, uint32_t &cnt1,
-                                             uint32_t &cnt2)
+                                             uint32_t (&out)[V], int &acc)
 {
-    Counts c[V];
+    UpCount c[V];
     uint32_t ties = 0;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -96,8 +106,8 @@ __device__ __forceinline__ void update_words(const uint32_t (&own)[V], const uin
             const uint32_t hi = (v < V - 1) ? same[v < V - 1 ? v + 1 : 0] : adj;
             shifted = funnel(hi, same[v], 1);
         }
-        c[v] = count_antialigned(own[v], same[v], shifted, ym[v], yp[v], zm[v], zp[v]);
-        ties |= tie_mask(c[v]);
+        c[v] = count_up(same[v], shifted, ym[v], yp[v], zm[v], zp[v]);
+        ties |= up_tie(c[v]);
     }
     uint32_t r[V];
 #pragma unroll
@@ -124,14 +134,13 @@ __device__ __forceinline__ void update_words(const uint32_t (&own)[V], const uin
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        out[v] = apply_rule(own[v], c[v], r[v]);
-        cnt0 += __builtin_popcount(c[v].a0);
-        cnt1 += __builtin_popcount(c[v].a1);
-        cnt2 += __builtin_popcount(c[v].a2);
+        out[v] = up_rule(own[v], c[v], r[v]);
+        if constexpr (COUNT)
+            acc += up_antialigned_sum(own[v], c[v]);
     }
 }
 
-template <int V>
+template <int V, bool COUNT>
 __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
 {
     extern __shared__ uint32_t lds[];
@@ -183,8 +192,7 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
     if (c0_row)
         load_words<V>(A.S0 + off((z0 + L - 1) % L), c0o);
 
-    uint32_t cnt0 = 0, cnt1 = 0, cnt2 = 0;
-    const bool counting = A.bond_acc != nullptr;
+    int bonds = 0;   // sum of a over owned colour-0 sites (COUNT only)
 
     for (int qi = -1; qi <= (int)Tza; ++qi) {
         const uint32_t zq = (z0 + L + qi) % L;            // plane of this step
@@ -211,16 +219,15 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
             load_words<V>(X1 + ep * W + w0, yp);
             const uint32_t adj = X1[e * W + (pi == 0u ? wprev : wnext)];
             const uint32_t g0 = (uint32_t)(((size_t)zq * L + y) * W + w0);
-            uint32_t a0 = 0, a1 = 0, a2 = 0;
-            update_words<V>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, A.k0, A.k1, g0, g0 & 3u, A.t,
-                            0u, n0c, a0, a1, a2);
-            if (counting && owned && qi >= 0 && qi < (int)Tza) {
-                cnt0 += a0;
-                cnt1 += a1;
-                cnt2 += a2;
+            const bool mine = owned && qi >= 0 && qi < (int)Tza;
+            int a_sum = 0;
+            update_words<V, COUNT>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, A.k0, A.k1, g0, g0 & 3u,
+                                   A.t, 0u, n0c, a_sum);
+            if (mine) {
+                if constexpr (COUNT)
+                    bonds += a_sum;
+                store_words_nt<V>(A.D0 + off(zq), n0c);
             }
-            if (owned && qi >= 0 && qi < (int)Tza)
-                store_words<V>(A.D0 + off(zq), n0c);
         }
         if (owned && qi >= 1) {
             uint32_t ym[V], yp[V];
@@ -228,10 +235,10 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
             load_words<V>(X0 + ep * W + w0, yp);
             const uint32_t adj = X0[e * W + (pi == 0u ? wprev : wnext)];
             const uint32_t g1 = (uint32_t)(((size_t)zm * L + y) * W + w0);
-            uint32_t d0 = 0, d1 = 0, d2 = 0;
-            update_words<V>(c1m, n0m1, adj, pi, ym, yp, n0m2, n0c, A.k0, A.k1, g1, g1 & 3u, A.t,
-                            1u, c1n, d0, d1, d2);
-            store_words<V>(A.D1 + off(zm), c1n);
+            int unused = 0;
+            update_words<V, false>(c1m, n0m1, adj, pi, ym, yp, n0m2, n0c, A.k0, A.k1, g1, g1 & 3u,
+                                   A.t, 1u, c1n, unused);
+            store_words_nt<V>(A.D1 + off(zm), c1n);
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -244,11 +251,9 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
         }
     }
 
-    if (counting) {
+    if constexpr (COUNT) {
         __shared__ unsigned long long part[16];
-        const unsigned long long mine =
-            (unsigned long long)cnt0 + 2ull * cnt1 + 4ull * cnt2;
-        const unsigned long long ws = wave_sum_u64(mine);
+        const unsigned long long ws = wave_sum_u64((unsigned long long)bonds);
         const uint32_t nw = (blockDim.x + 63) / 64;
         if ((tid & 63) == 0)
             part[tid >> 6] = ws;
@@ -506,10 +511,14 @@ hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, cons
     const uint32_t threads = ((a.E * a.R + 63) / 64) * 64;
     const size_t lds = (size_t)2 * 2 * a.E * a.W * 4;
     const dim3 grid(a.nty * ntz), block(threads);
-    switch (tu.V) {
-    case 4: hipLaunchKernelGGL(k_bit_sweep<4>, grid, block, lds, st, a); break;
-    case 2: hipLaunchKernelGGL(k_bit_sweep<2>, grid, block, lds, st, a); break;
-    default: hipLaunchKernelGGL(k_bit_sweep<1>, grid, block, lds, st, a); break;
+    const bool count = bond_acc != nullptr;
+    switch (tu.V * 2 + (count ? 1 : 0)) {
+    case 9: hipLaunchKernelGGL((k_bit_sweep<4, true>), grid, block, lds, st, a); break;
+    case 8: hipLaunchKernelGGL((k_bit_sweep<4, false>), grid, block, lds, st, a); break;
+    case 5: hipLaunchKernelGGL((k_bit_sweep<2, true>), grid, block, lds, st, a); break;
+    case 4: hipLaunchKernelGGL((k_bit_sweep<2, false>), grid, block, lds, st, a); break;
+    case 3: hipLaunchKernelGGL((k_bit_sweep<1, true>), grid, block, lds, st, a); break;
+    default: hipLaunchKernelGGL((k_bit_sweep<1, false>), grid, block, lds, st, a); break;
     }
     return hipGetLastError();
 }

@@ -27,7 +27,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kG = 8;             // separations per register block
 constexpr int kItems = 2;         // work items per thread in k_corr_lines
-constexpr size_t kLineLds = 48 * 1024;
+constexpr size_t kLineLds = 56 * 1024;
 
 struct LineGeom {
     uint32_t L, W, R;             // R = L/2 + 1 separations
@@ -37,12 +37,20 @@ struct LineGeom {
     uint32_t nsplit;              // blocks per separation chunk
 };
 
-// One block owns separations [rc*Rr, rc*Rr + Rr) and a strided share of the
-// tiles (o, Y) with Y a multiple of Cy.  Its threads keep their partial sums in
-// registers across all tiles and add them to the global counts once.
-// LDS holds rows [Y, Y+Cy) (block A) and [Y+r_base, Y+r_base+Cy+Rr) (block B)
-// of both colour planes, row-major, so that lanes (consecutive columns) read
-// consecutive words.
+__host__ __device__ inline size_t line_lds_bytes(uint32_t W, uint32_t Cy, uint32_t Rr)
+{
+    return (size_t)2 * W * ((Cy + 1) + (Cy + Rr + 1)) * 4;
+}
+
+// One block owns separations [r_base, r_base + Rr) and a strided share of the
+// tiles (o, Y), Y a multiple of Cy.  LDS holds, column-major, rows [Y, Y+Cy)
+// (region A) and [Y+r_base, Y+r_base+Cy+Rr) (region B) of both colour planes:
+// column c*W + w is word w of colour plane c, one entry per row, padded to an
+// odd length so that lanes (consecutive columns) hit distinct banks.  For line
+// (pi, w) the colour alternates with the row, so even and odd rows come from
+// two fixed columns and every read uses an immediate offset.  Threads keep
+// their partial sums in registers over all tiles and add them to the global
+// counts once.
 template <int AX>
 __global__ void __launch_bounds__(kBlock) k_corr_lines(LineGeom g, const uint32_t *P0,
                                                       const uint32_t *P1, unsigned long long *anti)
@@ -57,15 +65,20 @@ __global__ void __launch_bounds__(kBlock) k_corr_lines(LineGeom g, const uint32_
     const uint32_t r_base = rc * g.Rr;
     const uint32_t r_end = min(r_base + g.Rr, g.R);
     const uint32_t ngr = (r_end - r_base + kG - 1) / kG;   // register blocks in this chunk
-    const uint32_t ncol = W2;
-    const uint32_t nitems = ngr * ncol;
-    const uint32_t rowsA = g.Cy, rowsB = g.Cy + g.Rr;
+    const uint32_t nitems = ngr * W2;
+    const uint32_t Cy = g.Cy, PA = g.Cy + 1, PB = g.Cy + g.Rr + 1;
     uint32_t *A = sm;
-    uint32_t *B = sm + (size_t)rowsA * W2;
+    uint32_t *B = sm + (size_t)W2 * PA;
     const size_t plane = (size_t)L * W;
-    const uint32_t ntiles = L * (L / g.Cy);
+    const uint32_t ytiles = L / Cy;
+    const uint32_t ntiles = L * ytiles;
+    // fill geometry: thread -> (column fcw = c*W + w, first row fs0), frows rows apart
+    const uint32_t frows = kBlock / W2;           // >= 1 since W2 <= 128
+    const uint32_t fcw = threadIdx.x % W2, fs0 = threadIdx.x / W2;
+    const bool fill_active = fs0 < frows;
+    const uint32_t *fP = ((fcw / W) ? P1 : P0) + (fcw % W);
+    const size_t ustride = (AX == 1) ? (size_t)W : plane;   // words between consecutive rows u
 
-    // each thread owns items it and it + kBlock (at most kItems)
     uint32_t acc[kItems][kG];
 #pragma unroll
     for (int k = 0; k < kItems; ++k)
@@ -74,18 +87,21 @@ __global__ void __launch_bounds__(kBlock) k_corr_lines(LineGeom g, const uint32_
             acc[k][d] = 0u;
 
     for (uint32_t tile = split; tile < ntiles; tile += g.nsplit) {
-        const uint32_t o = tile / (L / g.Cy);
-        const uint32_t Y = (tile % (L / g.Cy)) * g.Cy;
+        const uint32_t o = tile / ytiles;
+        const uint32_t Y = (tile % ytiles) * Cy;
         __syncthreads();
-        // fill A and B: row slot s, colour c, word w
-        for (uint32_t k = threadIdx.x; k < (rowsA + rowsB) * W2; k += kBlock) {
-            const uint32_t s = k / W2, cw = k % W2;
-            const uint32_t c = cw / W, w = cw % W;
-            const uint32_t u = (s < rowsA) ? (Y + s) % L : (Y + r_base + (s - rowsA)) % L;
-            const uint32_t *P = c ? P1 : P0;
-            const size_t addr = (AX == 1) ? (size_t)o * plane + (size_t)u * W + w
-                                          : (size_t)u * plane + (size_t)o * W + w;
-            sm[k] = P[addr];
+        // fill: this thread always loads column fcw; rows advance by frows
+        if (fill_active) {
+            const uint32_t *col = fP + (AX == 1 ? (size_t)o * plane : (size_t)o * W);
+            for (uint32_t s = fs0; s < Cy; s += frows)          // A: rows Y .. Y+Cy-1, no wrap
+                A[fcw * PA + s] = col[(size_t)(Y + s) * ustride];
+            uint32_t u = (Y + r_base + fs0) % L;                  // B: rows from Y + r_base, wrapping
+            for (uint32_t s = fs0; s < Cy + g.Rr; s += frows) {
+                B[fcw * PB + s] = col[(size_t)u * ustride];
+                u += frows;
+                while (u >= L)   // frows may exceed L for small lattices
+                    u -= L;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -93,31 +109,29 @@ __global__ void __launch_bounds__(kBlock) k_corr_lines(LineGeom g, const uint32_
             const uint32_t it = threadIdx.x + k * kBlock;
             if (it >= nitems)
                 break;
-            const uint32_t col = it % ncol, gr = it / ncol;
+            const uint32_t col = it % W2, gr = it / W2;
             const uint32_t pi = col / W, w = col % W;
             const uint32_t r0 = gr * kG;            // relative to r_base
-            // word of column (pi, w) in row slot s of block X whose first row is u0
-            auto word = [&](const uint32_t *X, uint32_t s, uint32_t u0) -> uint32_t {
-                const uint32_t c = (pi + u0 + s + o) & 1u;
-                return X[s * W2 + c * W + w];
-            };
-            const uint32_t uB0 = Y + r_base;        // global row of B's slot 0 (mod L)
+            // colour of even rows of the line in A and in B
+            const uint32_t cA = (pi + Y + o) & 1u, cB = (pi + Y + r_base + o) & 1u;
+            const uint32_t *Ae = A + (cA * W + w) * PA, *Ao = A + ((1u - cA) * W + w) * PA;
+            const uint32_t *Be = B + (cB * W + w) * PB + r0, *Bo = B + ((1u - cB) * W + w) * PB + r0;
             uint32_t b[2 * kG];
 #pragma unroll
             for (int j = 0; j < kG; ++j)
-                b[j] = word(B, r0 + j, uB0);
-            for (uint32_t u = 0; u < g.Cy; u += kG) {
+                b[j] = (j & 1) ? Bo[j] : Be[j];
+            for (uint32_t u = 0; u < Cy; u += kG) {
                 uint32_t a[kG];
 #pragma unroll
                 for (int i = 0; i < kG; ++i) {
-                    a[i] = word(A, u + i, Y);
-                    b[kG + i] = word(B, u + r0 + kG + i, uB0);
+                    a[i] = (i & 1) ? Ao[u + i] : Ae[u + i];
+                    b[kG + i] = (i & 1) ? Bo[u + kG + i] : Be[u + kG + i];
                 }
 #pragma unroll
                 for (int i = 0; i < kG; ++i)
 #pragma unroll
                     for (int d = 0; d < kG; ++d)
-                        acc[k][d] += __builtin_popcount(a[i] ^ b[i + d]);
+                        acc[k][d] = popc_acc(a[i] ^ b[i + d], acc[k][d]);
 #pragma unroll
                 for (int j = 0; j < kG; ++j)
                     b[j] = b[kG + j];
@@ -135,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_lines(LineGeom g, const uint32_
         const uint32_t it = threadIdx.x + k * kBlock;
         if (it >= nitems)
             break;
-        const uint32_t gr = it / ncol;
+        const uint32_t gr = it / W2;
 #pragma unroll
         for (int d = 0; d < kG; ++d) {
             const uint32_t rr = gr * kG + d;
@@ -195,16 +209,19 @@ __global__ void __launch_bounds__(kBlock) k_corr_x(uint32_t L, uint32_t W, const
         const uint32_t *E = sm + ph * W2, *O = E + W;
         for (uint32_t w = 0; w < W; ++w) {
             const uint32_t e0 = E[w], o0 = O[w];
-            const uint32_t ea = E[(w + qq) % W], eb = E[(w + qq + 1) % W], ec = E[(w + qq + 2) % W];
+            const uint32_t ea = E[(w + qq) % W], eb = E[(w + qq + 1) % W];
             const uint32_t oa = O[(w + qq) % W], ob = O[(w + qq + 1) % W];
+            // re[k] = rot(E, 16q + k) for k = 0..16; shift 32 is the next word
+            uint32_t re[17];
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                re[k] = funnel(eb, ea, sb + k);
+            re[16] = (sb == 0u) ? funnel(eb, ea, 16) : eb;
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
-                const uint32_t sh = sb + s;                                   // < 32
-                const uint32_t re = funnel(eb, ea, sh);                       // rot(E, m)
-                const uint32_t ro = funnel(ob, oa, sh);                       // rot(O, m)
-                const uint32_t re1 = (sh < 31) ? funnel(eb, ea, sh + 1) : funnel(ec, eb, 0);  // rot(E, m+1)
-                ae[s] += __builtin_popcount(e0 ^ re) + __builtin_popcount(o0 ^ ro);
-                ao[s] += __builtin_popcount(e0 ^ ro) + __builtin_popcount(o0 ^ re1);
+                const uint32_t ro = funnel(ob, oa, sb + s);                   // rot(O, m)
+                ae[s] = popc_acc(o0 ^ ro, popc_acc(e0 ^ re[s], ae[s]));
+                ao[s] = popc_acc(o0 ^ re[s + 1], popc_acc(e0 ^ ro, ao[s]));
             }
             if (q == 0) {
                 my_ones += __builtin_popcount(e0) + __builtin_popcount(o0);
@@ -254,27 +271,23 @@ LineGeom line_geom(uint32_t L)
     g.L = L;
     g.W = L / 64;
     g.R = L / 2 + 1;
-    const uint32_t row_bytes = 2 * g.W * 4;
-    uint32_t rows = (uint32_t)(kLineLds / row_bytes);       // A + B rows that fit
-    uint32_t unit = rows / 3;                                // Cy = Rr = unit, rounded to kG
-    unit = (unit / kG) * kG;
-    if (unit < kG)
-        unit = kG;
-    uint32_t Cy = unit;
-    while (L % Cy)
-        Cy -= kG;                                            // L is a multiple of 64
-    g.Cy = Cy;
-    // separations per block: enough register blocks to give every thread work
-    const uint32_t ncol = 2 * g.W;
-    uint32_t ngr = (kItems * kBlock) / ncol;                 // at most kItems per thread
+    // separations per block: kG per register block, at most kItems items per
+    // thread over the 2W columns, no more than the separations there are
+    uint32_t ngr = (kItems * kBlock) / (2 * g.W);
     if (ngr < 1)
         ngr = 1;
     uint32_t Rr = ngr * kG;
     const uint32_t Rmax = ((g.R + kG - 1) / kG) * kG;
     if (Rr > Rmax)
         Rr = Rmax;
-    if (Rr > unit)
-        Rr = unit;                                           // A + B rows fit the budget
+    uint32_t Cy = L < 64 ? L : 64;
+    if (Rr > 64 && line_lds_bytes(g.W, Cy, Rr) > kLineLds)
+        Rr = 64;
+    while (line_lds_bytes(g.W, Cy, Rr) > kLineLds && Cy > kG) {
+        Cy /= 2;
+        Rr = Rr > kG ? Rr / 2 : Rr;
+    }
+    g.Cy = Cy;
     g.Rr = Rr;
     g.nrc = (g.R + Rr - 1) / Rr;
     return g;
@@ -295,8 +308,7 @@ hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32
     while (nsplit > 8 && nsplit / 2 >= ntiles)
         nsplit /= 2;
     g.nsplit = nsplit;
-    const size_t lds_lines = std::max<size_t>((size_t)(2 * g.Cy + g.Rr) * 2 * W * 4,
-                                              (size_t)g.Rr * 8);
+    const size_t lds_lines = std::max<size_t>(line_lds_bytes(W, g.Cy, g.Rr), (size_t)g.Rr * 8);
     const dim3 grid_lines(g.nrc * nsplit);
     hipLaunchKernelGGL(k_corr_lines<1>, grid_lines, dim3(kBlock), lds_lines, st, g, P0, P1,
                        anti + 1 * R);

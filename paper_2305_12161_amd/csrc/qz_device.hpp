@@ -58,6 +58,15 @@ __device__ __forceinline__ uint32_t and3(uint32_t a, uint32_t b, uint32_t c)
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x80);
 }
 
+// acc + popcount(x) as one v_bcnt_u32_b32 (the compiler otherwise tends to
+// pair popcounts through v_add3, costing an extra instruction per two).
+__device__ __forceinline__ uint32_t popc_acc(uint32_t x, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
 // Funnel shift: the low 32 bits of ((hi:lo) >> s), 0 <= s < 32.
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
 {
@@ -65,42 +74,51 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
 }
 
 // ---------------------------------------------------------------------------
-// The zero-temperature rule on 32 sites at once.  s holds 32 spins of one
-// colour, n[0..5] the matching bits of their six neighbours.  The number of
-// anti-aligned neighbours a = sum_k (s ^ n_k) is formed as three bit planes
-// (a = 4*a2 + 2*a1 + a0) by two full adders over the neighbour triples; the
-// spin flips where a >= 4 (energy falls) or a == 3 (energy unchanged) and the
-// tie bit r is set.
+// The zero-temperature rule on 32 sites of one colour at once (T -> 0 Glauber
+// acceptance, Methods).  It is written through the number U of UP neighbours
+// (0..6) among the six, which does not depend on the site's own spin.  With a
+// the number of anti-aligned neighbours, a = U for a down spin and a = 6 - U
+// for an up spin, and the energy change of a flip is 12 - 4a, so:
+//   U >= 4           -> the site ends up (a >= 4 flips a down spin; an up
+//                       spin has a <= 2 and stays),
+//   U <= 2           -> the site ends down (symmetrically),
+//   U == 3 (a == 3)  -> the spin flips iff the tie bit r is set: s ^ r.
+// In bit planes (U = 4*u2 + 2*u1 + u0; U = 7 is impossible, so u1 & u0 alone
+// means U == 3): new = u2 | (u1 & u0 & (s ^ r)).
 // ---------------------------------------------------------------------------
-struct Counts {
-    uint32_t a0, a1, a2;
+struct UpCount {
+    uint32_t u0, u1, u2;
 };
 
-__device__ __forceinline__ Counts count_antialigned(uint32_t s, uint32_t n0, uint32_t n1,
-                                                    uint32_t n2, uint32_t n3, uint32_t n4,
-                                                    uint32_t n5)
+__device__ __forceinline__ UpCount count_up(uint32_t n0, uint32_t n1, uint32_t n2, uint32_t n3,
+                                            uint32_t n4, uint32_t n5)
 {
-    // Adder over (s^n0, s^n1, s^n2): sum = s ^ xor3(n), carry = s ^ maj3(n).
     const uint32_t xa = xor3(n0, n1, n2), ma = maj3(n0, n1, n2);
     const uint32_t xb = xor3(n3, n4, n5), mb = maj3(n3, n4, n5);
-    const uint32_t sa = s ^ xa, sb = s ^ xb;
-    const uint32_t ca = s ^ ma, cb = s ^ mb;
-    Counts c;
-    c.a0 = xa ^ xb;           // sa ^ sb
-    const uint32_t k = sa & sb;
-    c.a1 = xor3(ca, cb, k);
-    c.a2 = maj3(ca, cb, k);
-    return c;
+    const uint32_t k = xa & xb;
+    UpCount u;
+    u.u0 = xa ^ xb;
+    u.u1 = xor3(ma, mb, k);
+    u.u2 = maj3(ma, mb, k);
+    return u;
 }
 
-__device__ __forceinline__ uint32_t tie_mask(const Counts &c)
+__device__ __forceinline__ uint32_t up_tie(const UpCount &u) { return u.u1 & u.u0; }
+
+__device__ __forceinline__ uint32_t up_rule(uint32_t s, const UpCount &u, uint32_t r)
 {
-    return c.a1 & c.a0 & ~c.a2;   // a == 3
+    return (up_tie(u) & (s ^ r)) | u.u2;
 }
 
-__device__ __forceinline__ uint32_t apply_rule(uint32_t s, const Counts &c, uint32_t r)
+// Sum of the anti-aligned counts a over the 32 sites:
+// sum a = sum over down sites of U + sum over up sites of (6 - U)
+//       = 6 popc(s) + sum_j 2^j (popc(u_j) - 2 popc(s & u_j)).
+__device__ __forceinline__ int up_antialigned_sum(uint32_t s, const UpCount &u)
 {
-    return s ^ (c.a2 | and3(c.a1, c.a0, r));
+    const int p0 = __builtin_popcount(u.u0) - 2 * __builtin_popcount(s & u.u0);
+    const int p1 = __builtin_popcount(u.u1) - 2 * __builtin_popcount(s & u.u1);
+    const int p2 = __builtin_popcount(u.u2) - 2 * __builtin_popcount(s & u.u2);
+    return 6 * __builtin_popcount(s) + p0 + 2 * p1 + 4 * p2;
 }
 
 // ---------------------------------------------------------------------------

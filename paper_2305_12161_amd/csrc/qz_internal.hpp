@@ -67,4 +67,35 @@ hipError_t i8_window(hipStream_t st, uint32_t L, const int8_t *s, uint32_t ox, u
 
 hipError_t fill_u64(hipStream_t st, unsigned long long *p, size_t n, unsigned long long v);
 
+// ----- batched replicas (qz_batch.hip) -----
+struct BatchReplica {
+    uint32_t *base;                 // copy k, colour c plane at base + (2k + c) * L*L*(L/64) words
+    unsigned long long *trace;      // bond-count ring (cap slots), or null
+    uint64_t seed;
+    uint64_t t;                     // time at the start of the current group of sweeps
+    uint32_t cur;                   // copy holding the state at time t
+    uint32_t active;                // 0: skipped by the sweeps
+};
+struct BatchTile {
+    uint32_t slot;                  // replica
+    uint32_t z0;                    // first plane
+};
+struct BatchGroup {                 // the sub-tiles of one workgroup: same L and plane count
+    uint32_t L, nz, first, last;    // tiles [first, last)
+};
+struct BatchArgs {
+    const BatchReplica *reps;
+    const BatchTile *tiles;
+    const BatchGroup *groups;
+    uint32_t step;                  // sweeps already done in this group of sweeps
+    uint32_t every, cap;            // bond count every `every` sweeps into a ring of `cap`
+    size_t lds_bytes;
+};
+uint32_t batch_subtiles_per_block(uint32_t L);
+bool batch_size_ok(uint32_t L);
+hipError_t batch_sweep(hipStream_t st, const BatchArgs &a, uint32_t ngroups);
+hipError_t batch_advance(hipStream_t st, BatchReplica *reps, uint32_t n, uint32_t k);
+hipError_t batch_clear_trace(hipStream_t st, BatchReplica *reps, uint32_t n, uint32_t span,
+                             uint32_t every, uint32_t cap);
+
 }  // namespace qz
