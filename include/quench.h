@@ -142,6 +142,15 @@ int qz_download_window(qz_lattice *q, const uint32_t origin[3], uint32_t W, int8
 int qz_set_tuning(qz_lattice *q, int V, int Ty, int Tz);
 int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
 
+/* Sublattice order (Supplementary Methods I B).  QZ_CYCLE_01 (the default, the
+ * paper's main runs): colour 0 then colour 1 in every sweep.  QZ_CYCLE_MIXED:
+ * the colour updated first in sweep t is drawn at random for each sweep --
+ * colour 1 first iff bit 0 of word 0 of Philox block (0, t, 2, 0) is set --
+ * which restores detailed balance.  The bond trace of a sweep is still the
+ * bond count of the state entering it. */
+enum { QZ_CYCLE_01 = 0, QZ_CYCLE_MIXED = 1 };
+int qz_set_cycle(qz_lattice *q, int cycle);
+
 /* ------------------------------------------------------------------------
  * Batched replicas.  Many independent lattices ("replicas", each its own L
  * and seed, 1-bit layout with L % 64 == 0 and L <= 256) held in one caller

@@ -57,6 +57,13 @@ def _load():
                                       ctypes.c_int, ctypes.c_int, _i8p, ctypes.c_uint64,
                                       ctypes.c_uint64]
     lib.or_window_advance.restype = None
+    lib.or_first_colour.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+    lib.or_first_colour.restype = ctypes.c_int
+    lib.or_sweep_mixed.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, _i8p]
+    lib.or_sweep_mixed.restype = ctypes.c_int64
+    lib.or_run_cycle.argtypes = [ctypes.c_int, ctypes.c_uint64, _i8p, ctypes.c_uint64,
+                                 ctypes.c_uint64, ctypes.c_uint64, _i64p, ctypes.c_int]
+    lib.or_run_cycle.restype = None
     lib.or_init_window.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, _i8p]
     lib.or_init_window.restype = None
@@ -146,8 +153,12 @@ def corr(s: np.ndarray):
     return S, int(M[0])
 
 
-def run(s: np.ndarray, seed: int, t0: int, n: int, every: int = 0) -> np.ndarray:
-    """Advance n sweeps in place from time t0; returns B(t0 + k*every) for k < n/every."""
+def run(s: np.ndarray, seed: int, t0: int, n: int, every: int = 0,
+        mixed: bool = False) -> np.ndarray:
+    """Advance n sweeps in place from time t0; returns B(t0 + k*every) for k < n/every.
+
+    mixed=True uses the mixed cycle (colour order drawn per sweep), else the 01 cycle.
+    """
     L = s.shape[0]
     _check_L(L)
     if every > 0:
@@ -156,8 +167,19 @@ def run(s: np.ndarray, seed: int, t0: int, n: int, every: int = 0) -> np.ndarray
     else:
         tr = np.zeros(0, dtype=np.int64)
         ptr = None
-    _load().or_run(L, seed, _i8(s), t0, n, every, ptr)
+    _load().or_run_cycle(L, seed, _i8(s), t0, n, every, ptr, 1 if mixed else 0)
     return tr
+
+
+def first_colour(seed: int, t: int) -> int:
+    """Mixed cycle: the colour updated first in sweep t."""
+    return int(_load().or_first_colour(seed, t))
+
+
+def sweep_mixed(s: np.ndarray, seed: int, t: int) -> int:
+    L = s.shape[0]
+    _check_L(L)
+    return int(_load().or_sweep_mixed(L, seed, t, _i8(s)))
 
 
 def window_advance(L: int, seed: int, origin, w: np.ndarray, t0: int, T: int) -> None:

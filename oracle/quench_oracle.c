@@ -188,6 +188,29 @@ int64_t or_sweep(int L, uint64_t seed, uint32_t t, int8_t *s)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Mixed cycle (Supplementary Methods I B): which sublattice goes first is   */
+/* drawn at random for every sweep, independently of the others.  Our draw:  */
+/* colour 1 goes first in sweep t iff bit 0 of word 0 of the Philox block    */
+/* with counter (0, t, 2, 0) is set.                                         */
+/* ------------------------------------------------------------------------ */
+int or_first_colour(uint64_t seed, uint32_t t)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { 0u, t, 2u, 0u };
+    uint32_t w[4];
+    or_philox4x32_10(ctr, key, w);
+    return (int)(w[0] & 1u);
+}
+
+int64_t or_sweep_mixed(int L, uint64_t seed, uint32_t t, int8_t *s)
+{
+    int first = or_first_colour(seed, t);
+    int64_t f = or_half_sweep(L, seed, t, first, s);
+    f += or_half_sweep(L, seed, t, 1 - first, s);
+    return f;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Unsatisfied-bond counts per axis: B_a = #{i : s_i != s_{i+e_a}}.          */
 /* Energy E = -(3N - 2B), B = B_x + B_y + B_z.                               */
 /* ------------------------------------------------------------------------ */
@@ -242,10 +265,11 @@ void or_corr(int L, const int8_t *s, int64_t *S, int64_t *M)
 /* ------------------------------------------------------------------------ */
 /* A run of n sweeps starting at time t0.  If every > 0, trace receives      */
 /* B(t0 + k*every) for k = 0 .. n/every - 1, each the total bond count of    */
-/* the state at the start of that sweep.                                     */
+/* the state at the start of that sweep.  mixed != 0 selects the mixed      */
+/* cycle, else the 01 cycle.                                                 */
 /* ------------------------------------------------------------------------ */
-void or_run(int L, uint64_t seed, int8_t *s, uint64_t t0, uint64_t n, uint64_t every,
-            int64_t *trace)
+void or_run_cycle(int L, uint64_t seed, int8_t *s, uint64_t t0, uint64_t n, uint64_t every,
+                  int64_t *trace, int mixed)
 {
     for (uint64_t k = 0; k < n; ++k) {
         if (every > 0 && trace != NULL && (k % every) == 0) {
@@ -253,8 +277,17 @@ void or_run(int L, uint64_t seed, int8_t *s, uint64_t t0, uint64_t n, uint64_t e
             or_bonds(L, s, B);
             trace[k / every] = B[0] + B[1] + B[2];
         }
-        or_sweep(L, seed, (uint32_t)(t0 + k), s);
+        if (mixed)
+            or_sweep_mixed(L, seed, (uint32_t)(t0 + k), s);
+        else
+            or_sweep(L, seed, (uint32_t)(t0 + k), s);
     }
+}
+
+void or_run(int L, uint64_t seed, int8_t *s, uint64_t t0, uint64_t n, uint64_t every,
+            int64_t *trace)
+{
+    or_run_cycle(L, seed, s, t0, n, every, trace, 0);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -43,6 +43,7 @@ def _load():
         "qz_upload_spins": ([vp, c.POINTER(c.c_int8), u64], i32),
         "qz_download_window": ([vp, c.POINTER(u32), u32, c.POINTER(c.c_int8)], i32),
         "qz_set_tuning": ([vp, i32, i32, i32], i32),
+        "qz_set_cycle": ([vp, i32], i32),
         "qz_get_tuning": ([vp, c.POINTER(i32)], i32),
         "qz_status_string": ([i32], c.c_char_p),
         "qz_last_error": ([], c.c_char_p),
@@ -161,6 +162,10 @@ class Lattice:
 
     def set_tuning(self, V: int, Ty: int, Tz: int) -> None:
         _check(lib.qz_set_tuning(self._h, V, Ty, Tz))
+
+    def set_cycle(self, mixed: bool) -> None:
+        """Mixed cycle (colour order drawn per sweep) if True, else the 01 cycle."""
+        _check(lib.qz_set_cycle(self._h, 1 if mixed else 0))
 
     def tuning(self):
         out = (ctypes.c_int * 3)()

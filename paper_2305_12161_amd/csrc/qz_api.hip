@@ -22,6 +22,7 @@ struct qz_lattice {
     qz::StateMap map;
     int cur;                 // bit layout: which copy holds the current state
     qz::BitTuning tune;
+    bool mixed;              // mixed cycle instead of the 01 cycle
     bool failed;
 };
 
@@ -96,13 +97,13 @@ int sweep_once(qz_lattice *q, unsigned long long *bond_acc)
 {
     const uint32_t t = (uint32_t)q->t;
     if (q->layout == QZ_LAYOUT_I8) {
-        QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 0, i8_spins(q), bond_acc));
-        QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 1, i8_spins(q), nullptr));
+        QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 0, q->mixed, i8_spins(q), bond_acc));
+        QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 1, q->mixed, i8_spins(q), nullptr));
     } else {
         const int a = q->cur, b = 1 - q->cur;
         QZ_HIP(q, qz::bit_sweep(q->st, q->L, q->seed, t, q->tune, bit_plane(q, a, 0),
                                 bit_plane(q, a, 1), bit_plane(q, b, 0), bit_plane(q, b, 1),
-                                bond_acc));
+                                bond_acc, q->mixed));
         q->cur = b;
     }
     q->t += 1;
@@ -191,6 +192,7 @@ QZ_EXPORT int qz_create(uint32_t L, uint64_t seed, int layout, void *dev_mem, si
     q->st = reinterpret_cast<hipStream_t>(hip_stream);
     q->map = m;
     q->cur = 0;
+    q->mixed = false;
     q->failed = false;
     if (layout == QZ_LAYOUT_BIT)
         q->tune = qz::bit_tuning_default(L);
@@ -451,6 +453,16 @@ QZ_EXPORT int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3])
     out_V_Ty_Tz[0] = q->tune.V;
     out_V_Ty_Tz[1] = q->tune.Ty;
     out_V_Ty_Tz[2] = q->tune.Tz;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_set_cycle(qz_lattice *q, int cycle)
+{
+    if (!q)
+        return fail(QZ_EINVAL, "null handle");
+    if (cycle != QZ_CYCLE_01 && cycle != QZ_CYCLE_MIXED)
+        return fail(QZ_EINVAL, "unknown cycle");
+    q->mixed = cycle == QZ_CYCLE_MIXED;
     return QZ_OK;
 }
 

@@ -115,7 +115,7 @@ bool plan(const qz_replica_spec *specs, size_t n, uint32_t cap, Layout *lay)
     lay->corr_off = off;
     off = align256(off + (size_t)(3 * (lay->max_L / 2 + 1) + 1) * 8);
     lay->stage_off = off;
-    lay->stage_bytes = std::min<size_t>(nsites(lay->max_L), size_t(32) << 20);
+    lay->stage_bytes = std::min<size_t>(nsites(lay->max_L), size_t(4) << 20);
     lay->stage_bytes = std::max<size_t>(lay->stage_bytes, (size_t)lay->max_L * lay->max_L);
     off = align256(off + lay->stage_bytes);
     lay->total = off;

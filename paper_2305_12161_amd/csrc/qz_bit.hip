@@ -77,6 +77,7 @@ struct SweepArgs {
     uint32_t Ty, E, Tz, nty;   // E = rows held per tile (Ty + 4, or L for whole planes)
     uint32_t whole;            // 1 when a tile is a whole plane (no y halo)
     uint32_t k0, k1, t;
+    uint32_t mixed;            // 1: mixed cycle (first colour drawn per sweep)
 };
 
 // Update V words of one colour.  own = the words being updated; same = the
@@ -183,14 +184,20 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
         pf1[v] = pf0[v] = 0u;
     }
     auto off = [&](uint32_t z) -> size_t { return (size_t)z * plane_words + (size_t)y * row_words + w0; };
+    // Colour f is updated first: 0 in the 01 cycle; in the mixed cycle bit 0 of
+    // Philox block (0, t, 2, 0) (Supplementary Methods I B: order drawn per sweep).
+    // Below, "c0" names the first colour and "c1" the second.
+    const uint32_t f = A.mixed ? (philox10(0u, A.t, 2u, 0u, A.k0, A.k1).w[0] & 1u) : 0u;
+    const uint32_t *SF = f ? A.S1 : A.S0, *SS = f ? A.S0 : A.S1;
+    uint32_t *DF = f ? A.D1 : A.D0, *DS = f ? A.D0 : A.D1;
 
     if (held) {
-        load_words<V>(A.S1 + off((z0 + L - 2) % L), c1m);
-        load_words<V>(A.S1 + off((z0 + L - 1) % L), c1c);
-        load_words<V>(A.S1 + off(z0 % L), c1p);
+        load_words<V>(SS + off((z0 + L - 2) % L), c1m);
+        load_words<V>(SS + off((z0 + L - 1) % L), c1c);
+        load_words<V>(SS + off(z0 % L), c1p);
     }
     if (c0_row)
-        load_words<V>(A.S0 + off((z0 + L - 1) % L), c0o);
+        load_words<V>(SF + off((z0 + L - 1) % L), c0o);
 
     int bonds = 0;   // sum of a over owned colour-0 sites (COUNT only)
 
@@ -200,9 +207,9 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
         // prefetch the next step's words
         if (qi < (int)Tza) {
             if (held)
-                load_words<V>(A.S1 + off((zq + 2) % L), pf1);
+                load_words<V>(SS + off((zq + 2) % L), pf1);
             if (c0_row)
-                load_words<V>(A.S0 + off((zq + 1) % L), pf0);
+                load_words<V>(SF + off((zq + 1) % L), pf0);
         }
         uint32_t *X1 = lds + (size_t)(qi & 1) * 2 * E * W;   // old colour 1 of plane q
         uint32_t *X0 = X1 + (size_t)E * W;                  // new colour 0 of plane q-1
@@ -212,7 +219,7 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
         }
         __syncthreads();
 
-        const uint32_t pi = (y + zq) & 1u;   // x parity of colour 0 at (y, zq), colour 1 at (y, zm)
+        const uint32_t pi = (f + y + zq) & 1u;   // x parity of the first colour at (y, zq), second at (y, zm)
         if (c0_row) {
             uint32_t ym[V], yp[V];
             load_words<V>(X1 + em * W + w0, ym);
@@ -222,11 +229,11 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
             const bool mine = owned && qi >= 0 && qi < (int)Tza;
             int a_sum = 0;
             update_words<V, COUNT>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, A.k0, A.k1, g0, g0 & 3u,
-                                   A.t, 0u, n0c, a_sum);
+                                   A.t, f, n0c, a_sum);
             if (mine) {
                 if constexpr (COUNT)
                     bonds += a_sum;
-                store_words_nt<V>(A.D0 + off(zq), n0c);
+                store_words_nt<V>(DF + off(zq), n0c);
             }
         }
         if (owned && qi >= 1) {
@@ -237,8 +244,8 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
             const uint32_t g1 = (uint32_t)(((size_t)zm * L + y) * W + w0);
             int unused = 0;
             update_words<V, false>(c1m, n0m1, adj, pi, ym, yp, n0m2, n0c, A.k0, A.k1, g1, g1 & 3u,
-                                   A.t, 1u, c1n, unused);
-            store_words_nt<V>(A.D1 + off(zm), c1n);
+                                   A.t, 1u - f, c1n, unused);
+            store_words_nt<V>(DS + off(zm), c1n);
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -489,7 +496,7 @@ hipError_t bit_init(hipStream_t st, uint32_t L, uint64_t seed, uint32_t *P0, uin
 
 hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                      const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
-                     unsigned long long *bond_acc)
+                     unsigned long long *bond_acc, bool mixed)
 {
     if (!bit_tuning_valid(L, tu))
         return hipErrorInvalidValue;
@@ -508,6 +515,7 @@ hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, cons
     a.k0 = (uint32_t)seed;
     a.k1 = (uint32_t)(seed >> 32);
     a.t = t;
+    a.mixed = mixed ? 1u : 0u;
     const uint32_t threads = ((a.E * a.R + 63) / 64) * 64;
     const size_t lds = (size_t)2 * 2 * a.E * a.W * 4;
     const dim3 grid(a.nty * ntz), block(threads);

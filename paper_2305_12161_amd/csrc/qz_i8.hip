@@ -56,12 +56,17 @@ __global__ void __launch_bounds__(kThreads) k_i8_init(uint64_t N, uint32_t k0, u
     }
 }
 
-// Half-sweep of colour p: thread per colour index j (consecutive lanes hold
-// consecutive j, so a wave shares one Philox block and evaluates it once).
+// Half-sweep number `which` (0 = first, 1 = second) of sweep t: thread per
+// colour index j (consecutive lanes hold consecutive j, so a wave shares one
+// Philox block and evaluates it once).  The colour updated is p = which in the
+// 01 cycle; in the mixed cycle the first colour is bit 0 of Philox block
+// (0, t, 2, 0) (Supplementary Methods I B: order drawn per sweep).
 __global__ void __launch_bounds__(kThreads)
-    k_i8_half(uint32_t L, uint64_t half_n, uint32_t k0, uint32_t k1, uint32_t t, uint32_t p,
-              int8_t *s, unsigned long long *bond_acc)
+    k_i8_half(uint32_t L, uint64_t half_n, uint32_t k0, uint32_t k1, uint32_t t, uint32_t which,
+              uint32_t mixed, int8_t *s, unsigned long long *bond_acc)
 {
+    const uint32_t first = mixed ? (philox10(0u, t, 2u, 0u, k0, k1).w[0] & 1u) : 0u;
+    const uint32_t p = which ^ first;
     const uint32_t H = L >> 1;
     unsigned long long acc = 0;
     for (uint64_t j = (uint64_t)blockIdx.x * kThreads + threadIdx.x; j < half_n;
@@ -194,12 +199,13 @@ hipError_t i8_init(hipStream_t st, uint32_t L, uint64_t seed, int8_t *s)
     return hipGetLastError();
 }
 
-hipError_t i8_half_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, int p, int8_t *s,
-                         unsigned long long *bond_acc)
+hipError_t i8_half_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, int which,
+                         bool mixed, int8_t *s, unsigned long long *bond_acc)
 {
     const uint64_t half_n = (uint64_t)L * L * L / 2;
     hipLaunchKernelGGL(k_i8_half, dim3(grid_for(half_n, 8192)), dim3(kThreads), 0, st, L, half_n,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), t, (uint32_t)p, s, bond_acc);
+                       (uint32_t)seed, (uint32_t)(seed >> 32), t, (uint32_t)which,
+                       mixed ? 1u : 0u, s, bond_acc);
     return hipGetLastError();
 }
 

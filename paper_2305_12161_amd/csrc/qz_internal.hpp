@@ -21,7 +21,7 @@ struct StateMap {
 };
 
 constexpr size_t kTraceCap = 4096;
-constexpr size_t kStageMax = size_t(32) << 20;
+constexpr size_t kStageMax = size_t(4) << 20;   // at least one L*L plane is always allowed
 
 bool state_map(uint32_t L, int layout, StateMap *m);
 
@@ -36,8 +36,10 @@ BitTuning bit_tuning_default(uint32_t L);
 
 // ----- int8 layout -----
 hipError_t i8_init(hipStream_t st, uint32_t L, uint64_t seed, int8_t *s);
-hipError_t i8_half_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, int p, int8_t *s,
-                         unsigned long long *bond_acc);
+// which = 0: first half-sweep of sweep t (colour 0, or the drawn colour in the
+// mixed cycle), which = 1: the second.
+hipError_t i8_half_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, int which,
+                         bool mixed, int8_t *s, unsigned long long *bond_acc);
 hipError_t i8_bonds(hipStream_t st, uint32_t L, const int8_t *s, unsigned long long *acc3);
 hipError_t i8_corr(hipStream_t st, uint32_t L, const int8_t *s, long long *S, long long *M);
 hipError_t i8_check_pm1(hipStream_t st, size_t n, const int8_t *s, unsigned long long *bad);
@@ -47,7 +49,7 @@ hipError_t i8_check_pm1(hipStream_t st, size_t n, const int8_t *s, unsigned long
 hipError_t bit_init(hipStream_t st, uint32_t L, uint64_t seed, uint32_t *P0, uint32_t *P1);
 hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                      const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
-                     unsigned long long *bond_acc);
+                     unsigned long long *bond_acc, bool mixed);
 hipError_t bit_bonds(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
                      unsigned long long *acc3);
 hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,

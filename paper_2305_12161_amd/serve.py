@@ -1,0 +1,208 @@
+"""Continuous-batching service for quench requests.
+
+A request asks for the quench of one lattice (L, seed) up to t_max sweeps; it
+is answered with its bond-count trace (every `every` sweeps) and its final
+bond count.  Requests arrive over time; the server admits them into device
+slots as memory and slots allow, advances every admitted lattice together in
+chunks of `chunk` sweeps, and retires finished ones at chunk boundaries, so
+new work joins while earlier work is still on the GPU.
+
+Backends:
+  * GpuBackend -- the HIP library: lattice sizes the batched engine takes
+    (L % 64 == 0, L <= 256) live in fixed batch slots advanced by one graph
+    replay per chunk; other sizes run as single lattices (the 1-bit layout when
+    L % 64 == 0, else int8), all on one stream.
+  * Any object with the same methods (tests use a CPU one).
+
+Results never depend on what else is running: every lattice follows exactly
+its own (L, seed) trajectory.
+"""
+import collections
+import heapq
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+
+@dataclass
+class Result:
+    idx: int
+    L: int
+    seed: int
+    t_max: int
+    arrival_s: float
+    admitted_s: float = 0.0
+    done_s: float = 0.0
+    trace: Optional[np.ndarray] = None   # B(0), B(every), ..., B(t_max - every)
+    final_B: int = -1
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+class GpuBackend:
+    """Device slots for served quenches.
+
+    budget_bytes caps the device memory of lattice state held at once.  The
+    batch slots are pre-allocated: `batch_slots` maps L -> number of slots.
+    Single lattices are allocated per request from the remaining budget.
+    """
+
+    def __init__(self, budget_bytes: int, batch_slots: Dict[int, int], every: int, chunk: int,
+                 t_max_cap: int = 10_000, device=None, graph_sweeps: Optional[int] = None):
+        import torch
+        from . import binding
+        self.qz = binding
+        self.torch = torch
+        self.every, self.chunk = every, chunk
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        specs = []
+        for L in sorted(batch_slots):
+            for _ in range(batch_slots[L]):
+                specs.append((L, 0))
+        self.batch = None
+        self.batch_bytes = 0
+        self.free_batch: Dict[int, List[int]] = collections.defaultdict(list)
+        if specs:
+            cap = t_max_cap // every + 2
+            self.batch_bytes = binding.batch_state_bytes(specs, cap)
+            self.batch = binding.Batch(specs, trace_every=every, trace_cap=cap, device=self.device,
+                                       stream=self.stream)
+            self.batch.set_tuning(64, 0, chunk if graph_sweeps is None else graph_sweeps)
+            for slot, (L, _) in enumerate(specs):
+                self.batch.set_active(slot, False)
+                self.free_batch[L].append(slot)
+        self.single_budget = budget_bytes - self.batch_bytes
+        if self.single_budget < 0:
+            raise ValueError("batch slots exceed the memory budget")
+        self.single_used = 0
+        self.live: Dict[int, dict] = {}          # request idx -> placement
+
+    @staticmethod
+    def layout_for(L: int) -> str:
+        return "bit" if L % 64 == 0 else "i8"
+
+    def single_bytes(self, L: int) -> int:
+        return self.qz.state_bytes(L, self.layout_for(L)) + 8 * (10_000 // self.every + 2)
+
+    def can_admit(self, L: int) -> bool:
+        if self.batch is not None and self.free_batch.get(L):
+            return True
+        if self.batch is not None and L in self.free_batch and not self.free_batch[L]:
+            return False            # a batch size with all slots busy waits for a slot
+        return self.single_used + self.single_bytes(L) <= self.single_budget
+
+    def admit(self, req) -> None:
+        if self.batch is not None and self.free_batch.get(req.L):
+            slot = self.free_batch[req.L].pop()
+            self.batch.reset(slot, req.seed)
+            self.live[req.idx] = {"kind": "batch", "slot": slot, "t": 0, "t_max": req.t_max}
+            return
+        lat = self.qz.Lattice(req.L, req.seed, self.layout_for(req.L), device=self.device,
+                              stream=self.stream)
+        tr = self.torch.zeros(req.t_max // self.every, dtype=self.torch.int64, device=self.device)
+        self.single_used += self.single_bytes(req.L)
+        self.live[req.idx] = {"kind": "single", "lat": lat, "trace": tr, "t": 0,
+                              "t_max": req.t_max, "bytes": self.single_bytes(req.L)}
+
+    def advance(self) -> None:
+        """One chunk of sweeps for every live lattice (asynchronous)."""
+        if self.batch is not None and any(p["kind"] == "batch" for p in self.live.values()):
+            self.batch.run(self.chunk)
+        for p in self.live.values():
+            if p["kind"] == "single":
+                t = p["t"]
+                sl = p["trace"][t // self.every: (t + self.chunk) // self.every]
+                p["lat"].run_device(self.chunk, self.every, sl)
+        for p in self.live.values():
+            p["t"] += self.chunk
+
+    def sync(self) -> None:
+        self.torch.cuda.synchronize(self.device)
+
+    def finished(self) -> List[int]:
+        return [i for i, p in self.live.items() if p["t"] >= p["t_max"]]
+
+    def retire(self, idx: int) -> dict:
+        p = self.live.pop(idx)
+        n = p["t_max"] // self.every
+        if p["kind"] == "batch":
+            slot = p["slot"]
+            trace = self.batch.trace(slot, 0, n).astype(np.int64)
+            final_B = int(self.batch.bonds(slot).sum())
+            self.batch.set_active(slot, False)
+            L = self.batch.specs[slot][0]
+            self.free_batch[L].append(slot)
+        else:
+            trace = p["trace"].cpu().numpy().astype(np.int64)
+            final_B = int(p["lat"].bonds().sum())
+            p["lat"].close()
+            self.single_used -= p["bytes"]
+        return {"trace": trace, "final_B": final_B}
+
+
+class Server:
+    """Event loop: admit arrivals at chunk boundaries, advance, retire."""
+
+    def __init__(self, backend, chunk: int):
+        self.backend = backend
+        self.chunk = chunk
+
+    def serve(self, requests, clock=time.perf_counter, time_scale: float = 1.0) -> List[Result]:
+        """Serve `requests` (objects with idx, L, seed, t_max, arrival_s), arrivals
+        replayed in real time (arrival_s * time_scale after the start)."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
+        waiting: collections.deque = collections.deque()
+        results: Dict[int, Result] = {}
+        t_start = clock()
+        done = 0
+        total = len(pending)
+        while done < total:
+            now = clock() - t_start
+            while pending and pending[0].arrival_s * time_scale <= now:
+                r = pending.popleft()
+                waiting.append(r)
+                results[r.idx] = Result(r.idx, r.L, r.seed, r.t_max, r.arrival_s * time_scale)
+            # admit in arrival order, skipping requests whose size has no room yet
+            still = collections.deque()
+            while waiting:
+                r = waiting.popleft()
+                if self.backend.can_admit(r.L):
+                    self.backend.admit(r)
+                    results[r.idx].admitted_s = clock() - t_start
+                else:
+                    still.append(r)
+            waiting = still
+            if not self.backend.live:
+                if pending:
+                    # idle until the next arrival
+                    wait = pending[0].arrival_s * time_scale - (clock() - t_start)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.01))
+                continue
+            self.backend.advance()
+            self.backend.sync()
+            for idx in self.backend.finished():
+                out = self.backend.retire(idx)
+                res = results[idx]
+                res.trace = out["trace"]
+                res.final_B = out["final_B"]
+                res.done_s = clock() - t_start
+                done += 1
+        return [results[k] for k in sorted(results)]
+
+
+def summarize(results: List[Result], wall_s: float) -> dict:
+    lat = np.array([r.latency_s for r in results])
+    attempts = float(sum(r.L ** 3 * r.t_max for r in results))
+    return {
+        "requests": len(results),
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "attempts_per_ns": attempts / (wall_s * 1e9),
+        "wall_s": wall_s,
+    }

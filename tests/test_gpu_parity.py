@@ -245,3 +245,32 @@ def test_bad_arguments_raise(qz):
     i8 = qz.Lattice(8, 1, "i8")
     with pytest.raises(qz.QuenchError):
         i8.set_tuning(1, 8, 8)
+
+
+# --------------------------------------------------------------------------
+# mixed cycle: the colour updated first is drawn per sweep
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("layout,L,tuning", [("i8", 6, None), ("i8", 16, None), ("bit", 64, None),
+                                             ("bit", 128, (2, 28, 11)), ("bit", 256, (4, 28, 10))])
+def test_mixed_cycle_matches_oracle(qz, orc, layout, L, tuning):
+    seed = 31 + L
+    say("mixed", layout, L, tuning)
+    lat = qz.Lattice(L, seed, layout)
+    if tuning:
+        lat.set_tuning(*tuning)
+    lat.set_cycle(True)
+    n = 12
+    tr = lat.run(n, 1)
+    s = orc.init(L, seed)
+    want = orc.run(s, seed, 0, n, 1, mixed=True)
+    assert np.array_equal(tr.astype(np.int64), want)
+    assert np.array_equal(lat.download(), s)
+
+
+def test_mixed_differs_from_01(qz):
+    a = qz.Lattice(64, 3, "bit")
+    b = qz.Lattice(64, 3, "bit")
+    b.set_cycle(True)
+    a.run(20)
+    b.run(20)
+    assert not np.array_equal(a.download(), b.download())

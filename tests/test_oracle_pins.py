@@ -414,3 +414,51 @@ def test_physics_bands_file_parses():
     with open(os.path.join(GOLDEN, "paper_physics_bands.json")) as f:
         d = json.load(f)
     assert d["ell_L256_t4000_rescaled"]["checkerboard_time_factor"] == 1.75
+
+
+# --------------------------------------------------------------------------
+# mixed cycle (Supplementary Methods I B): colour order drawn per sweep
+# --------------------------------------------------------------------------
+def test_mixed_cycle_order_keying_and_balance(orc, torch_philox):
+    rows = [[0, t, 2, 0, 77, 0] for t in range(400)]
+    want = [w[0] & 1 for w in torch_philox(rows)]
+    got = [orc.first_colour(77, t) for t in range(400)]
+    assert got == want
+    assert 150 < sum(got) < 250
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_mixed_cycle_bruteforce(orc, torch_philox, L):
+    """Each sweep: the drawn colour first, every proposal judged by full energies."""
+    col = colour(L)
+    jj = colour_index(L)
+    seed = 5
+    s_or = orc.init(L, seed)
+    s_bf = s_or.copy()
+    firsts = [w[0] & 1 for w in torch_philox([[0, t, 2, 0, seed, 0] for t in range(16)])]
+    assert 0 < sum(firsts) < 16
+    for t in range(16):
+        for p in (firsts[t], 1 - firsts[t]):
+            bits = bits_from_blocks(torch_philox, seed, jj.ravel(), t, p, 0).reshape(L, L, L)
+            for (z, y, x) in np.argwhere(col == p):
+                e0 = energy(s_bf)
+                s_bf[z, y, x] = -s_bf[z, y, x]
+                dE = energy(s_bf) - e0
+                if not (dE < 0 or (dE == 0 and bits[z, y, x] == 1)):
+                    s_bf[z, y, x] = -s_bf[z, y, x]
+    orc.run(s_or, seed, 0, 16, mixed=True)
+    assert np.array_equal(s_bf, s_or)
+
+
+def test_mixed_cycle_keeps_invariants(orc):
+    L = 12
+    s = orc.init(L, 3)
+    B_prev = int(orc.bonds(s).sum())
+    for t in range(10):
+        orc.sweep_mixed(s, 3, t)
+        B = int(orc.bonds(s).sum())
+        assert B <= B_prev
+        B_prev = B
+    u = np.ones((L, L, L), dtype=np.int8)
+    orc.run(u, 3, 0, 5, mixed=True)
+    assert np.all(u == 1)

@@ -1,0 +1,102 @@
+"""The continuous-batching scheduler.
+
+CPU: the scheduler against a backend built on the oracle (admission by slots
+and memory, arrivals while others run, every result equal to its run alone).
+GPU: a small served stream on the HIP backend, each result equal to the same
+request run alone through the single-lattice path.
+"""
+import collections
+import os
+
+import numpy as np
+import pytest
+
+from paper_2305_12161_amd import serve, workloads as wl
+
+
+class OracleBackend:
+    """CPU stand-in with the GPU backend's interface; at most `slots` live lattices."""
+
+    def __init__(self, orc, slots, every, chunk):
+        self.orc, self.slots, self.every, self.chunk = orc, slots, every, chunk
+        self.live = {}
+        self.max_live = 0
+        self.admit_order = []
+
+    def can_admit(self, L):
+        return len(self.live) < self.slots
+
+    def admit(self, req):
+        s = self.orc.init(req.L, req.seed)
+        self.live[req.idx] = {"s": s, "seed": req.seed, "t": 0, "t_max": req.t_max, "trace": []}
+        self.max_live = max(self.max_live, len(self.live))
+        self.admit_order.append(req.idx)
+
+    def advance(self):
+        for p in self.live.values():
+            tr = self.orc.run(p["s"], p["seed"], p["t"], self.chunk, self.every)
+            p["trace"].extend(int(v) for v in tr)
+            p["t"] += self.chunk
+
+    def sync(self):
+        pass
+
+    def finished(self):
+        return [i for i, p in self.live.items() if p["t"] >= p["t_max"]]
+
+    def retire(self, idx):
+        p = self.live.pop(idx)
+        return {"trace": np.array(p["trace"], dtype=np.int64),
+                "final_B": int(self.orc.bonds(p["s"]).sum())}
+
+
+def test_scheduler_with_oracle_backend(orc):
+    reqs = wl.request_stream(n=24, rate_per_s=400.0, master_seed=9, sizes=(4, 6, 8),
+                             t_maxes=(20, 40))
+    be = OracleBackend(orc, slots=5, every=5, chunk=10)
+    srv = serve.Server(be, chunk=10)
+    res = srv.serve(reqs)
+    assert len(res) == len(reqs)
+    assert be.max_live <= 5
+    assert be.admit_order == sorted(be.admit_order)       # one size class here: FIFO
+    for r in res:
+        s = orc.init(r.L, r.seed)
+        want = orc.run(s, r.seed, 0, r.t_max, 5)
+        assert np.array_equal(r.trace, want)
+        assert r.final_B == int(orc.bonds(s).sum())
+        assert r.done_s >= r.admitted_s >= r.arrival_s - 1e-9
+    stats = serve.summarize(res, wall_s=1.0)
+    assert stats["requests"] == len(reqs) and stats["p99_latency_s"] >= stats["p50_latency_s"]
+
+
+def test_request_stream_is_seeded():
+    a = wl.request_stream(n=50, rate_per_s=10.0)
+    b = wl.request_stream(n=50, rate_per_s=10.0)
+    assert [(r.L, r.t_max, r.seed, r.arrival_s) for r in a] == \
+           [(r.L, r.t_max, r.seed, r.arrival_s) for r in b]
+    assert all(r.L in wl.SERVE_SIZES and r.t_max in wl.SERVE_TMAX for r in a)
+    assert all(y.arrival_s >= x.arrival_s for x, y in zip(a, a[1:]))
+    assert a[0].arrival_s == 0.0
+
+
+@pytest.mark.gpu
+def test_served_results_equal_alone():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_12161_amd import binding
+    reqs = wl.request_stream(n=30, rate_per_s=200.0, master_seed=7,
+                             sizes=(64, 96, 128, 192, 256, 384), t_maxes=(100, 300))
+    every, chunk = 50, 50
+    be = serve.GpuBackend(budget_bytes=256 << 20, batch_slots={64: 4, 128: 3, 192: 2, 256: 2},
+                          every=every, chunk=chunk, t_max_cap=300)
+    srv = serve.Server(be, chunk=chunk)
+    res = srv.serve(reqs)
+    assert len(res) == len(reqs)
+    for r in res:
+        print("served", r.idx, r.L, r.t_max, flush=True)
+        layout = "bit" if r.L % 64 == 0 else "i8"
+        lat = binding.Lattice(r.L, r.seed, layout)
+        tr = lat.run(r.t_max, every).astype(np.int64)
+        assert np.array_equal(r.trace, tr), (r.idx, r.L)
+        assert r.final_B == int(lat.bonds().sum())
