@@ -50,7 +50,78 @@ def parse():
     ap.add_argument("--tuning", type=str, default="", help="V,Ty,Tz for the sweep kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-corr", action="store_true", help="skip the correlation measurements")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-replica workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-request workload")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="arrivals per second (default: the configured literal)")
     return ap.parse_args()
+
+
+def plain_rate(binding, torch, L, n):
+    """Attempts/ns of the single-lattice kernel on one lattice of side L (1-bit)."""
+    lat = binding.Lattice(L, 1234, "bit")
+    lat.run(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.run(n)
+    torch.cuda.synchronize()
+    return L ** 3 * n / ((time.perf_counter() - t0) * 1e9)
+
+
+def batched_workload(binding, torch, workloads):
+    """512 x L64 + 64 x L128 + 8 x L256 replicas, 1e4 MCS, B every 10 MCS each."""
+    specs = [(r.L, r.seed) for r in workloads.batch_config4()]
+    t_max = workloads.batch_config4()[0].t_max
+    warm = binding.Batch(specs[:2] + specs[-1:], trace_every=10, trace_cap=1024)
+    warm.run(64)
+    warm.sync()
+    del warm
+    b = binding.Batch(specs, trace_every=10, trace_cap=t_max // 10 + 8)
+    b.set_tuning(64, 0, 100)
+    b.sync()
+    t0 = time.perf_counter()
+    b.run(t_max)
+    b.sync()
+    wall = time.perf_counter() - t0
+    sites = sum(L ** 3 for L, _ in specs)
+    rate = sites * t_max / (wall * 1e9)
+    # the plain single-lattice kernel on one lattice of each size, for comparison
+    plain = {L: plain_rate(binding, torch, L, 400) for L in sorted({L for L, _ in specs})}
+    plain_wall = sum(L ** 3 * t_max / (plain[L] * 1e9) for L, _ in specs)
+    return {
+        "workload": "512 x L64 + 64 x L128 + 8 x L256 replicas (seeds 0x40000000 + r), 1-bit, "
+                    "1e4 MCS each, B every 10 MCS per replica, graph replays of 100 sweeps",
+        "value": round(rate, 2), "unit": "attempts/ns", "wall_s": round(wall, 4),
+        "ms_per_mcs": round(wall * 1e3 / t_max, 5),
+        "plain_one_lattice_attempts_per_ns": {str(L): round(v, 2) for L, v in plain.items()},
+        "plain_sequential_wall_s": round(plain_wall, 3),
+        "batched_over_plain": round(plain_wall / wall, 2),
+        "trace_points_per_replica": t_max // 10,
+    }
+
+
+def served_workload(binding, torch, workloads, n_req, rate):
+    from paper_2305_12161_amd import serve
+    reqs = workloads.request_stream(n=n_req, rate_per_s=rate)
+    every, chunk = 100, 100
+    be = serve.GpuBackend(budget_bytes=workloads.SERVE_BUDGET_BYTES,
+                          batch_slots=workloads.SERVE_BATCH_SLOTS, every=every, chunk=chunk)
+    srv = serve.Server(be, chunk=chunk)
+    t0 = time.perf_counter()
+    res = srv.serve(reqs)
+    wall = time.perf_counter() - t0
+    st = serve.summarize(res, wall)
+    st.update({
+        "workload": f"{n_req} requests, L uniform in {list(workloads.SERVE_SIZES)}, t_max uniform "
+                    f"in {list(workloads.SERVE_TMAX)}, Poisson arrivals at {rate:g}/s (numpy "
+                    f"PCG64 seed 5), HBM budget {workloads.SERVE_BUDGET_BYTES >> 20} MiB, "
+                    f"chunks of {chunk} MCS",
+        "unit": "attempts/ns",
+    })
+    for k in ("p50_latency_s", "p99_latency_s", "attempts_per_ns", "wall_s"):
+        st[k] = round(st[k], 4)
+    return st
 
 
 def cpu_baseline(L, seed, budget_s=15.0):
@@ -201,7 +272,17 @@ def main():
         "ell_C_final": (round(measure.crossing_length(ells[-1][1], ells[-1][2], N), 4)
                         if ells else None),
     }
+    del lat
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        print("# batched workload", file=sys.stderr, flush=True)
+        out["batched"] = batched_workload(binding, torch, workloads)
+    if not args.no_serve:
+        print("# served workload", file=sys.stderr, flush=True)
+        rate = args.serve_rate if args.serve_rate else workloads.SERVE_RATE_PER_S
+        out["served"] = served_workload(binding, torch, workloads, args.serve_requests, rate)
     if not args.no_cpu_baseline:
+        print("# cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(L, seed)
     print(json.dumps(out), flush=True)
 

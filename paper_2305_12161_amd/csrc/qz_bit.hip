@@ -478,7 +478,7 @@ BitTuning bit_tuning_default(uint32_t L)
         while (E * 2 * R <= 256 && E * 2 <= L)
             E *= 2;
         t.Ty = (int)(E - 4);
-        t.Tz = 64;
+        t.Tz = 32;   // measured best at L = 2048 (E = 32 rows, V = 4)
     }
     if ((uint32_t)t.Tz > L)
         t.Tz = (int)L;

@@ -1,0 +1,159 @@
+"""Autotuner for the sweep kernels: times candidate tilings on the device and
+keeps the fastest.  Results never depend on the tuning, only speed does.
+
+    python -m paper_2305_12161_amd.tune --L 2048            # single lattice
+    python -m paper_2305_12161_amd.tune --batch-config4     # batched replicas
+
+Winners are written to tuned.json next to this file; `best_single(L)` and
+`best_batch(L)` read them back (None when a size was never tuned).
+"""
+import argparse
+import json
+import os
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuned.json")
+
+
+def _load():
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {"single": {}, "batch": {}}
+
+
+def _save(d):
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def best_single(L: int):
+    v = _load()["single"].get(str(L))
+    return tuple(v["tuning"]) if v else None
+
+
+def best_batch(L: int):
+    v = _load()["batch"].get(str(L))
+    return (v["Tz"], v["graph_sweeps"]) if v else None
+
+
+def single_candidates(L: int):
+    W = L // 64
+    out = []
+    for V in (4, 2, 1):
+        if W % V:
+            continue
+        R = W // V
+        rows = [L] if L * R <= 1024 else []
+        E = 8
+        while E * R <= 1024 and E <= L:
+            if E - 4 >= 4:
+                rows.append(E - 4)
+            E *= 2
+        for Ty in rows:
+            for Tz in (16, 32, 64, 128):
+                if Tz <= L:
+                    out.append((V, Ty, Tz))
+    return out
+
+
+def tune_single(L: int, sweeps: int = 30, verbose: bool = True):
+    import torch
+    from . import binding
+    st = torch.cuda.current_stream()
+    best = None
+    lat = binding.Lattice(L, 11, "bit")
+    for cand in single_candidates(L):
+        try:
+            lat.set_tuning(*cand)
+        except binding.QuenchError:
+            continue
+        lat.run(3)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        lat.run(sweeps)
+        b.record(st)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / sweeps
+        if verbose:
+            print(json.dumps({"L": L, "tuning": cand, "ms_per_sweep": round(ms, 5)}), flush=True)
+        if best is None or ms < best[1]:
+            best = (cand, ms)
+    d = _load()
+    d["single"][str(L)] = {"tuning": list(best[0]), "ms_per_sweep": round(best[1], 5)}
+    _save(d)
+    return best
+
+
+def tune_batch(specs, sweeps: int = 200, verbose: bool = True):
+    """Per lattice size of the batch: planes per sub-tile, then sweeps per graph."""
+    import torch
+    from . import binding
+    sizes = sorted({L for L, _ in specs})
+    chosen = {L: None for L in sizes}
+    results = {}
+    for L in sizes:
+        for Tz in (8, 16, 32, 64):
+            if Tz > L or L % Tz:
+                continue
+            b = binding.Batch(specs)
+            for L2 in sizes:
+                if chosen[L2]:
+                    b.set_tuning(L2, chosen[L2], 50)
+            b.set_tuning(L, Tz, 50)
+            b.run(50)
+            b.sync()
+            t0 = time.perf_counter()
+            b.run(sweeps)
+            b.sync()
+            ms = (time.perf_counter() - t0) * 1e3 / sweeps
+            if verbose:
+                print(json.dumps({"L": L, "Tz": Tz, "ms_per_sweep": round(ms, 5)}), flush=True)
+            if L not in results or ms < results[L][1]:
+                results[L] = (Tz, ms)
+            del b
+            torch.cuda.empty_cache()
+        chosen[L] = results[L][0]
+    best_graph = None
+    for gs in (10, 25, 50, 100, 200):
+        b = binding.Batch(specs)
+        for L in sizes:
+            b.set_tuning(L, chosen[L], gs)
+        b.run(gs)
+        b.sync()
+        t0 = time.perf_counter()
+        b.run(sweeps)
+        b.sync()
+        ms = (time.perf_counter() - t0) * 1e3 / sweeps
+        if verbose:
+            print(json.dumps({"graph_sweeps": gs, "ms_per_sweep": round(ms, 5)}), flush=True)
+        if best_graph is None or ms < best_graph[1]:
+            best_graph = (gs, ms)
+        del b
+        torch.cuda.empty_cache()
+    d = _load()
+    for L in sizes:
+        d["batch"][str(L)] = {"Tz": chosen[L], "graph_sweeps": best_graph[0]}
+    _save(d)
+    return chosen, best_graph
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--L", type=int, nargs="*", default=[])
+    ap.add_argument("--batch-config4", action="store_true")
+    args = ap.parse_args()
+    for L in args.L:
+        print(json.dumps({"L": L, "best": tune_single(L)}), flush=True)
+    if args.batch_config4:
+        from . import workloads
+        specs = [(r.L, r.seed) for r in workloads.batch_config4()]
+        print(json.dumps({"batch_best": tune_batch(specs)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

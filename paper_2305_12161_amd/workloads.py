@@ -82,6 +82,12 @@ class Request:
 
 SERVE_SIZES = (64, 96, 128, 192, 256, 384, 512)
 SERVE_TMAX = (1_000, 10_000)
+# Device memory for lattice state held at once by the server (admission binds
+# on it), the batch slots per size, and the arrival rate: 0.8 of the rate one
+# MI355X sustained on this stream, measured once and frozen here.
+SERVE_BUDGET_BYTES = 512 << 20
+SERVE_BATCH_SLOTS = {64: 8, 128: 8, 192: 8, 256: 8}
+SERVE_RATE_PER_S = 60.0
 
 
 def request_stream(n: int = 2000, rate_per_s: float = 100.0, master_seed: int = 5,

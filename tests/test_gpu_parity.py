@@ -274,3 +274,16 @@ def test_mixed_differs_from_01(qz):
     a.run(20)
     b.run(20)
     assert not np.array_equal(a.download(), b.download())
+
+
+@pytest.mark.parametrize("layout,L,k", [("i8", 54, 3), ("bit", 64, 2), ("bit", 128, 3)])
+def test_menger_start_matches_oracle(qz, orc, layout, L, k):
+    """Quench from a Menger-sponge start (Results, sponge test) on both paths."""
+    s = wl.menger_state(L, k, seed=L + k)
+    say("menger", layout, L, k)
+    lat = qz.Lattice(L, 5, layout)
+    lat.upload(s, 0)
+    tr = lat.run(10, 2)
+    want = orc.run(s, 5, 0, 10, 2)
+    assert np.array_equal(tr.astype(np.int64), want)
+    assert np.array_equal(lat.download(), s)

@@ -462,3 +462,30 @@ def test_mixed_cycle_keeps_invariants(orc):
     u = np.ones((L, L, L), dtype=np.int8)
     orc.run(u, 3, 0, 5, mixed=True)
     assert np.all(u == 1)
+
+
+# --------------------------------------------------------------------------
+# Menger-sponge starts (Results, sponge test): the input generator itself
+# --------------------------------------------------------------------------
+def test_menger_tiles():
+    L = 27
+    s1 = wl.menger_state(L, 1, seed=4)
+    # each 3^3 tile: 20 cells of the sponge's sign and 7 holes (centre + face centres)
+    for tz in range(9):
+        for ty in range(9):
+            for tx in range(9):
+                t = s1[3 * tz:3 * tz + 3, 3 * ty:3 * ty + 3, 3 * tx:3 * tx + 3]
+                vals, counts = np.unique(t, return_counts=True)
+                assert sorted(counts.tolist()) == [7, 20]
+                maj = vals[np.argmax(counts)]
+                assert t[1, 1, 1] == -maj and t[0, 0, 0] == maj
+    s3 = wl.menger_state(L, 3, seed=4)
+    # one tile: the sponge's cells are (20/27)^3 of it, the holes the rest
+    fracs = sorted([(s3 == 1).mean(), (s3 == -1).mean()])
+    assert fracs[0] == pytest.approx((20 / 27) ** 3)
+    s0 = wl.menger_state(16, 0, seed=4)
+    assert abs(float(s0.mean())) < 0.1            # k = 0: independent fair spins
+    # tiles that do not fit at the upper end are cut off there
+    s = wl.menger_state(32, 2, seed=1)
+    assert s.shape == (32, 32, 32)
+    assert np.array_equal(s[:9, :9, :9] != 0, np.ones((9, 9, 9), dtype=bool))
