@@ -151,6 +151,25 @@ int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
 enum { QZ_CYCLE_01 = 0, QZ_CYCLE_MIXED = 1 };
 int qz_set_cycle(qz_lattice *q, int cycle);
 
+/* The paper's own correlation measurement (Methods, "Calculating the
+ * correlation function", eq:sisik): G(d) = (1/N) sum_i s_i s_{i+d} for every
+ * displacement d by a double-precision real FFT (in place), then averaged over
+ * spherical shells.  Shell b holds the displacements d (minimum image, each
+ * component in [-L/2, L/2)) with round(|d|) == b, and the wavevectors k
+ * (integer components in [-L/2, L/2), units 2 pi / L) with round(|k|) == b,
+ * for b < qz_fft_nbins(L) = round(sqrt(3) L / 2) + 2.
+ *   out_C[b]  = mean of G over shell b minus m^2 (connected C(r), Results)
+ *   out_Sk[b] = mean of |F s(k)|^2 / N over shell b (structure factor S(k))
+ *   out_nr[b], out_nk[b] = shell populations;  *out_m = M / N.
+ * qz_fft_prepare makes the FFT plans (kept with the handle) and reports the
+ * scratch bytes qz_fft_corr needs: about 8 L^2 (L + 2) bytes plus the FFT
+ * library's work area.  The scratch is caller-owned device memory; the
+ * library allocates nothing.  Synchronises. */
+uint32_t qz_fft_nbins(uint32_t L);
+int qz_fft_prepare(qz_lattice *q, size_t *scratch_bytes);
+int qz_fft_corr(qz_lattice *q, void *dev_scratch, size_t bytes, double *out_C, double *out_Sk,
+                uint64_t *out_nr, uint64_t *out_nk, double *out_m);
+
 /* ------------------------------------------------------------------------
  * Batched replicas.  Many independent lattices ("replicas", each its own L
  * and seed, 1-bit layout with L % 64 == 0 and L <= 256) held in one caller

@@ -219,3 +219,50 @@ def ell_intercept(S: np.ndarray, M: int, N: int, c: float = 0.5) -> float:
         if Cbar[r] < c:
             return (r - 1) + (Cbar[r - 1] - c) / (Cbar[r - 1] - Cbar[r])
     return float("inf")
+
+
+# --------------------------------------------------------------------------
+# The paper's FFT route to C(r,t) (Methods, "Calculating the correlation
+# function", eq:sisik), with numpy's FFT as the library primitive, followed by
+# the radial (spherical-shell) average, and the structure factor.
+# --------------------------------------------------------------------------
+def _signed(L):
+    v = np.arange(L)
+    return np.where(v < L // 2, v, v - L)
+
+
+def shell_index(L):
+    """round(|d|) for every displacement / wavevector, components in [-L/2, L/2)."""
+    c = _signed(L).astype(np.float64)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    return np.rint(np.sqrt(x * x + y * y + z * z)).astype(np.int64)
+
+
+def fft_G(s: np.ndarray) -> np.ndarray:
+    """G(d) = <s_i s_{i+d}> over i for every displacement d, indexed [dz, dy, dx]."""
+    f = s.astype(np.float64)
+    F = np.fft.fftn(f)
+    return np.fft.ifftn((F * np.conj(F)).real).real / f.size
+
+
+def fft_corr(s: np.ndarray):
+    """Shell means of C(d) = <s_i s_{i+d}> - m^2 and of S(k) = |F s(k)|^2 / N.
+
+    Returns (C, Sk, n_r, n_k, m) with shells b = 0 .. round(sqrt(3) L/2) + 1.
+    """
+    L = s.shape[0]
+    N = L ** 3
+    f = s.astype(np.float64)
+    F = np.fft.fftn(f)
+    P = (F * np.conj(F)).real
+    G = np.fft.ifftn(P).real / N            # sum_i s_i s_{i+d} = (1/N) sum_k |F|^2 e^{ikd}
+    m = float(f.sum()) / N
+    nb = int(0.8660254037844386 * L + 0.5) + 2
+    sh = shell_index(L).ravel()
+    n = np.bincount(sh, minlength=nb)[:nb]
+    gs = np.bincount(sh, weights=G.ravel(), minlength=nb)[:nb]
+    ps = np.bincount(sh, weights=P.ravel() / N, minlength=nb)[:nb]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        C = np.where(n > 0, gs / np.maximum(n, 1) - m * m, 0.0)
+        Sk = np.where(n > 0, ps / np.maximum(n, 1), 0.0)
+    return C, Sk, n.astype(np.int64), n.astype(np.int64), m

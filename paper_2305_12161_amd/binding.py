@@ -44,6 +44,10 @@ def _load():
         "qz_download_window": ([vp, c.POINTER(u32), u32, c.POINTER(c.c_int8)], i32),
         "qz_set_tuning": ([vp, i32, i32, i32], i32),
         "qz_set_cycle": ([vp, i32], i32),
+        "qz_fft_nbins": ([u32], u32),
+        "qz_fft_prepare": ([vp, c.POINTER(sz)], i32),
+        "qz_fft_corr": ([vp, vp, sz, c.POINTER(c.c_double), c.POINTER(c.c_double),
+                         c.POINTER(u64), c.POINTER(u64), c.POINTER(c.c_double)], i32),
         "qz_get_tuning": ([vp, c.POINTER(i32)], i32),
         "qz_status_string": ([i32], c.c_char_p),
         "qz_last_error": ([], c.c_char_p),
@@ -162,6 +166,29 @@ class Lattice:
 
     def set_tuning(self, V: int, Ty: int, Tz: int) -> None:
         _check(lib.qz_set_tuning(self._h, V, Ty, Tz))
+
+    def fft_corr(self):
+        """Shell means of C(r) and S(k) by the double-precision FFT route.
+
+        Returns (C, Sk, n_r, n_k, m); scratch device memory comes from torch.
+        """
+        import torch
+        need = ctypes.c_size_t()
+        _check(lib.qz_fft_prepare(self._h, ctypes.byref(need)))
+        scratch = torch.empty(int(need.value), dtype=torch.uint8, device=self.mem.device)
+        nb = int(lib.qz_fft_nbins(self.L))
+        C = np.zeros(nb)
+        Sk = np.zeros(nb)
+        nr = np.zeros(nb, dtype=np.uint64)
+        nk = np.zeros(nb, dtype=np.uint64)
+        m = ctypes.c_double()
+        dp = ctypes.POINTER(ctypes.c_double)
+        up = ctypes.POINTER(ctypes.c_uint64)
+        _check(lib.qz_fft_corr(self._h, ctypes.c_void_p(scratch.data_ptr()), int(need.value),
+                               C.ctypes.data_as(dp), Sk.ctypes.data_as(dp), nr.ctypes.data_as(up),
+                               nk.ctypes.data_as(up), ctypes.byref(m)))
+        del scratch
+        return C, Sk, nr.astype(np.int64), nk.astype(np.int64), float(m.value)
 
     def set_cycle(self, mixed: bool) -> None:
         """Mixed cycle (colour order drawn per sweep) if True, else the 01 cycle."""

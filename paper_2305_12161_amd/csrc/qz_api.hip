@@ -6,6 +6,10 @@
 #include <new>
 #include <string>
 
+#include <hipfft/hipfft.h>
+
+#include <vector>
+
 #include "../../include/quench.h"
 #include "qz_internal.hpp"
 
@@ -24,6 +28,9 @@ struct qz_lattice {
     qz::BitTuning tune;
     bool mixed;              // mixed cycle instead of the 01 cycle
     bool failed;
+    bool fft_ready;          // FFT plans made (qz_fft_prepare)
+    hipfftHandle fft_fwd, fft_inv;
+    size_t fft_work;
 };
 
 namespace {
@@ -194,6 +201,7 @@ QZ_EXPORT int qz_create(uint32_t L, uint64_t seed, int layout, void *dev_mem, si
     q->cur = 0;
     q->mixed = false;
     q->failed = false;
+    q->fft_ready = false;
     if (layout == QZ_LAYOUT_BIT)
         q->tune = qz::bit_tuning_default(L);
     hipError_t e;
@@ -214,6 +222,10 @@ QZ_EXPORT int qz_destroy(qz_lattice *q)
 {
     if (!q)
         return fail(QZ_EINVAL, "null handle");
+    if (q->fft_ready) {
+        hipfftDestroy(q->fft_fwd);
+        hipfftDestroy(q->fft_inv);
+    }
     delete q;
     return QZ_OK;
 }
@@ -463,6 +475,105 @@ QZ_EXPORT int qz_set_cycle(qz_lattice *q, int cycle)
     if (cycle != QZ_CYCLE_01 && cycle != QZ_CYCLE_MIXED)
         return fail(QZ_EINVAL, "unknown cycle");
     q->mixed = cycle == QZ_CYCLE_MIXED;
+    return QZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FFT correlation (qz_fft.hip).  Scratch: X | hipFFT work area | accumulators.
+// ---------------------------------------------------------------------------
+namespace {
+size_t fft_x_bytes(uint32_t L) { return align256((size_t)L * L * qz::fft_pad(L) * 8); }
+size_t fft_acc_bytes(uint32_t nb) { return align256((size_t)nb * 32 + 8); }
+}  // namespace
+
+QZ_EXPORT uint32_t qz_fft_nbins(uint32_t L) { return qz::fft_nbins(L); }
+
+QZ_EXPORT int qz_fft_prepare(qz_lattice *q, size_t *scratch_bytes)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if (!scratch_bytes)
+        return fail(QZ_EINVAL, "null output");
+    if (!q->fft_ready) {
+        const int n = (int)q->L;
+        size_t w1 = 0, w2 = 0;
+        if (hipfftCreate(&q->fft_fwd) != HIPFFT_SUCCESS)
+            return fail(QZ_EDEVICE, "hipfftCreate failed");
+        if (hipfftCreate(&q->fft_inv) != HIPFFT_SUCCESS) {
+            hipfftDestroy(q->fft_fwd);
+            return fail(QZ_EDEVICE, "hipfftCreate failed");
+        }
+        bool ok = hipfftSetAutoAllocation(q->fft_fwd, 0) == HIPFFT_SUCCESS &&
+                  hipfftSetAutoAllocation(q->fft_inv, 0) == HIPFFT_SUCCESS &&
+                  hipfftMakePlan3d(q->fft_fwd, n, n, n, HIPFFT_D2Z, &w1) == HIPFFT_SUCCESS &&
+                  hipfftMakePlan3d(q->fft_inv, n, n, n, HIPFFT_Z2D, &w2) == HIPFFT_SUCCESS &&
+                  hipfftSetStream(q->fft_fwd, q->st) == HIPFFT_SUCCESS &&
+                  hipfftSetStream(q->fft_inv, q->st) == HIPFFT_SUCCESS;
+        if (!ok) {
+            hipfftDestroy(q->fft_fwd);
+            hipfftDestroy(q->fft_inv);
+            return fail(QZ_EDEVICE, "hipFFT plan creation failed");
+        }
+        q->fft_work = align256(std::max(w1, w2));
+        q->fft_ready = true;
+    }
+    *scratch_bytes = fft_x_bytes(q->L) + q->fft_work + fft_acc_bytes(qz::fft_nbins(q->L));
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_fft_corr(qz_lattice *q, void *dev_scratch, size_t bytes, double *out_C,
+                          double *out_Sk, uint64_t *out_nr, uint64_t *out_nk, double *out_m)
+{
+    size_t need = 0;
+    int rc = qz_fft_prepare(q, &need);
+    if (rc != QZ_OK)
+        return rc;
+    if (!dev_scratch || (reinterpret_cast<uintptr_t>(dev_scratch) & 255u))
+        return fail(QZ_EINVAL, "scratch must be non-null and 256-byte aligned");
+    if (bytes < need)
+        return fail(QZ_ENOMEM, "scratch smaller than qz_fft_prepare() reported");
+    if (!out_C || !out_Sk || !out_nr || !out_nk || !out_m)
+        return fail(QZ_EINVAL, "null output");
+    const uint32_t L = q->L, nb = qz::fft_nbins(L);
+    uint8_t *base = reinterpret_cast<uint8_t *>(dev_scratch);
+    double *X = reinterpret_cast<double *>(base);
+    void *work = base + fft_x_bytes(L);
+    double *acc = reinterpret_cast<double *>(base + fft_x_bytes(L) + q->fft_work);
+    double *c_sum = acc, *sk_sum = acc + nb;
+    unsigned long long *c_cnt = reinterpret_cast<unsigned long long *>(acc + 2 * nb);
+    unsigned long long *sk_cnt = c_cnt + nb;
+    double *Mdev = acc + 4 * (size_t)nb;
+    QZ_HIP(q, qz::fft_zero(q->st, acc, 4 * (size_t)nb + 1));
+    if (q->layout == QZ_LAYOUT_I8)
+        QZ_HIP(q, qz::fft_unpack(q->st, L, 0, i8_spins(q), nullptr, X));
+    else
+        QZ_HIP(q, qz::fft_unpack(q->st, L, 1, bit_plane(q, q->cur, 0), bit_plane(q, q->cur, 1), X));
+    if (hipfftSetWorkArea(q->fft_fwd, work) != HIPFFT_SUCCESS ||
+        hipfftExecD2Z(q->fft_fwd, reinterpret_cast<hipfftDoubleReal *>(X),
+                      reinterpret_cast<hipfftDoubleComplex *>(X)) != HIPFFT_SUCCESS)
+        return fail(QZ_EDEVICE, "forward FFT failed");
+    QZ_HIP(q, qz::fft_power(q->st, L, X, nb, sk_sum, sk_cnt, Mdev));
+    if (hipfftSetWorkArea(q->fft_inv, work) != HIPFFT_SUCCESS ||
+        hipfftExecZ2D(q->fft_inv, reinterpret_cast<hipfftDoubleComplex *>(X),
+                      reinterpret_cast<hipfftDoubleReal *>(X)) != HIPFFT_SUCCESS)
+        return fail(QZ_EDEVICE, "inverse FFT failed");
+    QZ_HIP(q, qz::fft_radial(q->st, L, X, nb, c_sum, c_cnt));
+    std::vector<double> h(4 * (size_t)nb + 1);
+    QZ_HIP(q, hipMemcpyAsync(h.data(), acc, h.size() * 8, hipMemcpyDeviceToHost, q->st));
+    QZ_HIP(q, hipStreamSynchronize(q->st));
+    const double N = (double)n_sites(L);
+    const double m = h[4 * (size_t)nb] / N;
+    const unsigned long long *cc = reinterpret_cast<const unsigned long long *>(h.data() + 2 * nb);
+    const unsigned long long *kc = cc + nb;
+    for (uint32_t b = 0; b < nb; ++b) {
+        out_nr[b] = cc[b];
+        out_nk[b] = kc[b];
+        // R(d) = N * sum_i s_i s_{i+d}: the shell mean of R / N^2 is <s_i s_{i+d}>
+        out_C[b] = cc[b] ? h[b] / ((double)cc[b] * N * N) - m * m : 0.0;
+        out_Sk[b] = kc[b] ? h[nb + b] / ((double)kc[b] * N) : 0.0;
+    }
+    *out_m = m;
     return QZ_OK;
 }
 

@@ -69,6 +69,18 @@ hipError_t i8_window(hipStream_t st, uint32_t L, const int8_t *s, uint32_t ox, u
 
 hipError_t fill_u64(hipStream_t st, unsigned long long *p, size_t n, unsigned long long v);
 
+// ----- FFT correlation (qz_fft.hip) -----
+uint32_t fft_pad(uint32_t L);
+uint32_t fft_nbins(uint32_t L);
+// layout 1: spins0/spins1 = colour planes; layout 0: spins0 = int8 lattice
+hipError_t fft_unpack(hipStream_t st, uint32_t L, int layout, const void *spins0,
+                      const void *spins1, double *X);
+hipError_t fft_power(hipStream_t st, uint32_t L, double *X, uint32_t nb, double *sk_sum,
+                     unsigned long long *sk_cnt, double *M_out);
+hipError_t fft_radial(hipStream_t st, uint32_t L, const double *X, uint32_t nb, double *c_sum,
+                      unsigned long long *c_cnt);
+hipError_t fft_zero(hipStream_t st, double *d, size_t n);
+
 // ----- batched replicas (qz_batch.hip) -----
 struct BatchReplica {
     uint32_t *base;                 // copy k, colour c plane at base + (2k + c) * L*L*(L/64) words

@@ -287,3 +287,23 @@ def test_menger_start_matches_oracle(qz, orc, layout, L, k):
     want = orc.run(s, 5, 0, 10, 2)
     assert np.array_equal(tr.astype(np.int64), want)
     assert np.array_equal(lat.download(), s)
+
+
+# --------------------------------------------------------------------------
+# FFT route to C(r) and S(k) (eq:sisik, radial average).  Both sides sum in
+# double precision in different orders: the shell means agree to ~1e-12 at
+# these sizes (eps * log2 N * sqrt N); 1e-9 is used.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("layout,L,n", [("i8", 16, 3), ("i8", 32, 20), ("bit", 64, 10),
+                                        ("bit", 128, 40)])
+def test_fft_corr_matches_oracle(qz, orc, layout, L, n):
+    say("fft corr", layout, L)
+    lat = qz.Lattice(L, 70 + L, layout)
+    lat.run(n)
+    s = lat.download()
+    C, Sk, nr, nk, m = lat.fft_corr()
+    Co, Sko, nro, nko, mo = orc.fft_corr(s)
+    assert np.array_equal(nr, nro) and np.array_equal(nk, nko)
+    assert m == pytest.approx(mo, abs=1e-12)
+    assert np.allclose(C, Co, rtol=0, atol=1e-9)
+    assert np.allclose(Sk, Sko, rtol=1e-9, atol=1e-9)

@@ -489,3 +489,68 @@ def test_menger_tiles():
     s = wl.menger_state(32, 2, seed=1)
     assert s.shape == (32, 32, 32)
     assert np.array_equal(s[:9, :9, :9] != 0, np.ones((9, 9, 9), dtype=bool))
+
+
+# --------------------------------------------------------------------------
+# FFT correlation (eq:sisik) with the radial average and S(k)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [4, 6])
+def test_fft_corr_bruteforce(orc, L):
+    s = orc.init(L, 3 + L)
+    orc.run(s, 3 + L, 0, 1)
+    N = L ** 3
+    f = s.astype(np.float64)
+    # O(N^2): G(d) = (1/N) sum_i s_i s_{i+d} for every d by direct sums
+    G = np.zeros((L, L, L))
+    for dz in range(L):
+        for dy in range(L):
+            for dx in range(L):
+                G[dz, dy, dx] = (f * np.roll(f, (-dz, -dy, -dx), axis=(0, 1, 2))).sum() / N
+    m = f.mean()
+    sh = orc.oracle.shell_index(L).ravel()
+    C, Sk, nr, nk, mm = orc.fft_corr(s)
+    assert mm == pytest.approx(m)
+    for b in range(len(C)):
+        sel = sh == b
+        if sel.any():
+            assert C[b] == pytest.approx(G.ravel()[sel].mean() - m * m, abs=1e-12)
+    # structure factor by a direct discrete Fourier sum
+    k = 2 * np.pi * orc.oracle._signed(L) / L
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    S_direct = np.zeros(L ** 3)
+    idx = 0
+    for kz in k:
+        for ky in k:
+            for kx in k:
+                amp = (f * np.exp(-1j * (kx * x + ky * y + kz * z))).sum()
+                S_direct[idx] = abs(amp) ** 2 / N
+                idx += 1
+    sh_k = orc.oracle.shell_index(L).ravel()
+    for b in range(len(Sk)):
+        sel = sh_k == b
+        if sel.any():
+            assert Sk[b] == pytest.approx(S_direct[sel].mean(), rel=1e-10, abs=1e-10)
+
+
+def test_fft_corr_axis_points_and_sum_rules(orc):
+    L = 16
+    s = orc.init(L, 8)
+    orc.run(s, 8, 0, 6)
+    N = L ** 3
+    C, Sk, nr, nk, m = orc.fft_corr(s)
+    S, M = orc.corr(s)
+    assert m * N == pytest.approx(M)
+    # shell 0 is d = 0 alone: C(0) = 1 - m^2
+    assert nr[0] == 1 and C[0] == pytest.approx(1 - m * m)
+    # shell 1 holds |d| = 1 (6) and |d| = sqrt(2) (12)
+    assert nr[1] == 18
+    # along the axes G equals the exact integer sums S_a(r) / N
+    G = orc.oracle.fft_G(s)
+    for r in range(L // 2 + 1):
+        assert G[0, 0, r] == pytest.approx(S[0, r] / N, abs=1e-12)
+        assert G[0, r, 0] == pytest.approx(S[1, r] / N, abs=1e-12)
+        assert G[r, 0, 0] == pytest.approx(S[2, r] / N, abs=1e-12)
+    # Parseval: sum over all k of |F|^2 / N = sum_i s_i^2 = N; S(k = 0) = M^2 / N
+    assert (Sk * nk).sum() == pytest.approx(N)
+    assert Sk[0] == pytest.approx(M * M / N)
+    assert nr.sum() == N
