@@ -151,6 +151,16 @@ int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
 enum { QZ_CYCLE_01 = 0, QZ_CYCLE_MIXED = 1 };
 int qz_set_cycle(qz_lattice *q, int cycle);
 
+/* Double checkerboard (Supplementary Methods I A; bit layout).  Cubes of side
+ * B form a coarse checkerboard, coarse colour (x/B + y/B + z/B) mod 2; a sweep
+ * updates the coarse-colour-0 cubes (fine colour 0 sites, then fine colour 1
+ * sites), then the coarse-colour-1 cubes the same way.  Each site draws the
+ * same tie bit as in the plain checkerboard.  B must be a power of two >= 2
+ * with L % (2B) == 0 (QZ_EINVAL otherwise); B = 0 returns to the plain
+ * checkerboard.  Only the 01 order is available here (QZ_EUNSUPPORTED with
+ * the mixed cycle).  The paper does not state its block size. */
+int qz_set_double_checkerboard(qz_lattice *q, uint32_t B);
+
 /* The paper's own correlation measurement (Methods, "Calculating the
  * correlation function", eq:sisik): G(d) = (1/N) sum_i s_i s_{i+d} for every
  * displacement d by a double-precision real FFT (in place), then averaged over

@@ -64,6 +64,9 @@ def _load():
     lib.or_run_cycle.argtypes = [ctypes.c_int, ctypes.c_uint64, _i8p, ctypes.c_uint64,
                                  ctypes.c_uint64, ctypes.c_uint64, _i64p, ctypes.c_int]
     lib.or_run_cycle.restype = None
+    lib.or_sweep_double.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+                                    _i8p]
+    lib.or_sweep_double.restype = ctypes.c_int64
     lib.or_init_window.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, _i8p]
     lib.or_init_window.restype = None
@@ -174,6 +177,25 @@ def run(s: np.ndarray, seed: int, t0: int, n: int, every: int = 0,
 def first_colour(seed: int, t: int) -> int:
     """Mixed cycle: the colour updated first in sweep t."""
     return int(_load().or_first_colour(seed, t))
+
+
+def sweep_double(s: np.ndarray, B: int, seed: int, t: int) -> int:
+    """Double-checkerboard sweep with coarse cubes of side B (needs L % 2B == 0)."""
+    L = s.shape[0]
+    _check_L(L)
+    if B < 1 or L % (2 * B):
+        raise ValueError("need L % (2B) == 0")
+    return int(_load().or_sweep_double(L, B, seed, t, _i8(s)))
+
+
+def run_double(s: np.ndarray, B: int, seed: int, t0: int, n: int, every: int = 0) -> np.ndarray:
+    """n double-checkerboard sweeps from t0; B(t0 + k*every) traced at sweep starts."""
+    tr = []
+    for k in range(n):
+        if every and k % every == 0:
+            tr.append(int(bonds(s).sum()))
+        sweep_double(s, B, seed, t0 + k)
+    return np.array(tr, dtype=np.int64)
 
 
 def sweep_mixed(s: np.ndarray, seed: int, t: int) -> int:

@@ -211,6 +211,51 @@ int64_t or_sweep_mixed(int L, uint64_t seed, uint32_t t, int8_t *s)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Double checkerboard (Supplementary Methods I A): cubes of side B form a    */
+/* coarse checkerboard, coarse colour cc = (x/B + y/B + z/B) mod 2; a sweep   */
+/* updates the coarse-colour-0 cubes (fine colour 0 sites, then fine colour   */
+/* 1 sites), then the coarse-colour-1 cubes the same way.  Sites of one       */
+/* (coarse, fine) pair never touch, so each phase updates in place.  The tie  */
+/* bit of a site is the one of the plain checkerboard (same j, t, fine        */
+/* colour p).  Needs L % (2B) == 0.                                           */
+/* ------------------------------------------------------------------------ */
+static int64_t or_phase(int L, int B, uint64_t seed, uint32_t t, int cc, int p, int8_t *s)
+{
+    int64_t flips = 0;
+#pragma omp parallel for schedule(static) reduction(+ : flips)
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                if (((x + y + z) & 1) != p || ((x / B + y / B + z / B) & 1) != cc)
+                    continue;
+                int a = or_antialigned(L, s, x, y, z);
+                int flip = 0;
+                if (a >= 4) {
+                    flip = 1;
+                } else if (a == 3) {
+                    uint64_t j = (uint64_t)(x / 2) +
+                                 (uint64_t)(L / 2) * ((uint64_t)y + (uint64_t)L * (uint64_t)z);
+                    flip = or_tie_bit(seed, t, p, j);
+                }
+                if (flip) {
+                    int64_t i = or_idx(L, x, y, z);
+                    s[i] = (int8_t)-s[i];
+                    ++flips;
+                }
+            }
+    return flips;
+}
+
+int64_t or_sweep_double(int L, int B, uint64_t seed, uint32_t t, int8_t *s)
+{
+    int64_t f = 0;
+    for (int cc = 0; cc < 2; ++cc)
+        for (int p = 0; p < 2; ++p)
+            f += or_phase(L, B, seed, t, cc, p, s);
+    return f;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Unsatisfied-bond counts per axis: B_a = #{i : s_i != s_{i+e_a}}.          */
 /* Energy E = -(3N - 2B), B = B_x + B_y + B_z.                               */
 /* ------------------------------------------------------------------------ */

@@ -44,6 +44,7 @@ def _load():
         "qz_download_window": ([vp, c.POINTER(u32), u32, c.POINTER(c.c_int8)], i32),
         "qz_set_tuning": ([vp, i32, i32, i32], i32),
         "qz_set_cycle": ([vp, i32], i32),
+        "qz_set_double_checkerboard": ([vp, u32], i32),
         "qz_fft_nbins": ([u32], u32),
         "qz_fft_prepare": ([vp, c.POINTER(sz)], i32),
         "qz_fft_corr": ([vp, vp, sz, c.POINTER(c.c_double), c.POINTER(c.c_double),
@@ -189,6 +190,10 @@ class Lattice:
                                nk.ctypes.data_as(up), ctypes.byref(m)))
         del scratch
         return C, Sk, nr.astype(np.int64), nk.astype(np.int64), float(m.value)
+
+    def set_double_checkerboard(self, B: int) -> None:
+        """Double checkerboard with coarse cubes of side B (0: plain checkerboard)."""
+        _check(lib.qz_set_double_checkerboard(self._h, B))
 
     def set_cycle(self, mixed: bool) -> None:
         """Mixed cycle (colour order drawn per sweep) if True, else the 01 cycle."""

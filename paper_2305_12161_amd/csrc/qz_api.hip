@@ -27,6 +27,7 @@ struct qz_lattice {
     int cur;                 // bit layout: which copy holds the current state
     qz::BitTuning tune;
     bool mixed;              // mixed cycle instead of the 01 cycle
+    uint32_t dcb;            // > 0: double checkerboard with coarse cubes of this side
     bool failed;
     bool fft_ready;          // FFT plans made (qz_fft_prepare)
     hipfftHandle fft_fwd, fft_inv;
@@ -106,6 +107,13 @@ int sweep_once(qz_lattice *q, unsigned long long *bond_acc)
     if (q->layout == QZ_LAYOUT_I8) {
         QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 0, q->mixed, i8_spins(q), bond_acc));
         QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 1, q->mixed, i8_spins(q), nullptr));
+    } else if (q->dcb > 0) {
+        const int c = q->cur;
+        if (bond_acc)
+            QZ_HIP(q, qz::bit_bonds_total(q->st, q->L, bit_plane(q, c, 0), bit_plane(q, c, 1),
+                                          bond_acc));
+        QZ_HIP(q, qz::bit_double_sweep(q->st, q->L, q->dcb, q->seed, t, bit_plane(q, c, 0),
+                                       bit_plane(q, c, 1)));
     } else {
         const int a = q->cur, b = 1 - q->cur;
         QZ_HIP(q, qz::bit_sweep(q->st, q->L, q->seed, t, q->tune, bit_plane(q, a, 0),
@@ -200,6 +208,7 @@ QZ_EXPORT int qz_create(uint32_t L, uint64_t seed, int layout, void *dev_mem, si
     q->map = m;
     q->cur = 0;
     q->mixed = false;
+    q->dcb = 0;
     q->failed = false;
     q->fft_ready = false;
     if (layout == QZ_LAYOUT_BIT)
@@ -474,6 +483,8 @@ QZ_EXPORT int qz_set_cycle(qz_lattice *q, int cycle)
         return fail(QZ_EINVAL, "null handle");
     if (cycle != QZ_CYCLE_01 && cycle != QZ_CYCLE_MIXED)
         return fail(QZ_EINVAL, "unknown cycle");
+    if (cycle == QZ_CYCLE_MIXED && q->dcb)
+        return fail(QZ_EUNSUPPORTED, "the double checkerboard runs the 01 cycle only");
     q->mixed = cycle == QZ_CYCLE_MIXED;
     return QZ_OK;
 }
@@ -574,6 +585,24 @@ QZ_EXPORT int qz_fft_corr(qz_lattice *q, void *dev_scratch, size_t bytes, double
         out_Sk[b] = kc[b] ? h[nb + b] / ((double)kc[b] * N) : 0.0;
     }
     *out_m = m;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_set_double_checkerboard(qz_lattice *q, uint32_t B)
+{
+    if (!q)
+        return fail(QZ_EINVAL, "null handle");
+    if (B == 0) {
+        q->dcb = 0;
+        return QZ_OK;
+    }
+    if (q->layout != QZ_LAYOUT_BIT)
+        return fail(QZ_EUNSUPPORTED, "the double checkerboard runs on the bit layout");
+    if (B < 2 || (B & (B - 1)) || q->L % (2 * B))
+        return fail(QZ_EINVAL, "B must be a power of two >= 2 with L % (2B) == 0");
+    if (q->mixed)
+        return fail(QZ_EUNSUPPORTED, "the double checkerboard runs the 01 cycle only");
+    q->dcb = B;
     return QZ_OK;
 }
 

@@ -275,6 +275,55 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
 }
 
 // --------------------------------------------------------------------------
+// Double checkerboard (Supplementary Methods I A): cubes of side B = 2^sB form
+// a coarse checkerboard, coarse colour (x/B + y/B + z/B) & 1.  One phase
+// updates, in place, the fine-colour-p sites of the coarse-colour-cc cubes;
+// they read only fine colour 1-p, so threads never race.  Thread per word of
+// plane p; the sites outside the phase are masked out.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    k_bit_phase(uint32_t L, uint32_t W, uint32_t sB, uint32_t cc, uint32_t p, uint32_t k0,
+                uint32_t k1, uint32_t t, uint32_t *Pp, const uint32_t *Po)
+{
+    const uint64_t nwords = (uint64_t)L * L * W;
+    const size_t plane = (size_t)L * W;
+    // bit b of a word holds x = 64w + 2b + pi, so x / B = (32w + b) >> (sB - 1)
+    const uint32_t q = sB - 1;
+    const uint32_t pat = (q == 0) ? 0xAAAAAAAAu : (q == 1) ? 0xCCCCCCCCu : (q == 2) ? 0xF0F0F0F0u
+                       : (q == 3) ? 0xFF00FF00u : (q == 4) ? 0xFFFF0000u : 0u;
+    for (uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x; g < nwords;
+         g += (uint64_t)gridDim.x * 256) {
+        const uint32_t w = (uint32_t)(g % W);
+        const uint64_t row = g / W;
+        const uint32_t y = (uint32_t)(row % L), z = (uint32_t)(row / L);
+        const uint32_t A = (((32u * w) >> q) + (y >> sB) + (z >> sB)) & 1u;
+        const uint32_t mask = ((A ^ cc) & 1u) ? pat : ~pat;
+        if (mask == 0u)
+            continue;
+        const uint32_t pi = (p + y + z) & 1u;
+        const size_t rb = (size_t)row * W;
+        const uint32_t own = Pp[g], same = Po[g];
+        const uint32_t sh = pi ? funnel(Po[rb + (w + 1) % W], same, 1)
+                               : funnel(same, Po[rb + (w + W - 1) % W], 31);
+        const size_t zb = (size_t)z * plane;
+        const UpCount u = count_up(same, sh, Po[zb + (size_t)((y + L - 1) % L) * W + w],
+                                   Po[zb + (size_t)((y + 1) % L) * W + w],
+                                   Po[(size_t)((z + L - 1) % L) * plane + (size_t)y * W + w],
+                                   Po[(size_t)((z + 1) % L) * plane + (size_t)y * W + w]);
+        uint32_t r = 0u;
+        if ((up_tie(u) & mask) != 0u) {
+            const Words4 rb4 = philox10((uint32_t)(g >> 2), t, p, 0u, k0, k1);
+            const uint32_t sub = (uint32_t)(g & 3u);
+            const uint32_t lo = (sub & 1u) ? rb4.w[1] : rb4.w[0];
+            const uint32_t hi = (sub & 1u) ? rb4.w[3] : rb4.w[2];
+            r = (sub & 2u) ? hi : lo;
+        }
+        const uint32_t nw = up_rule(own, u, r);
+        Pp[g] = (own & ~mask) | (nw & mask);
+    }
+}
+
+// --------------------------------------------------------------------------
 // initial state: thread h covers lattice sites i = 64h .. 64h+63 (one row
 // segment), i.e. one word of each colour.
 // --------------------------------------------------------------------------
@@ -312,7 +361,7 @@ __global__ void __launch_bounds__(256) k_bit_init(uint32_t L, uint32_t W, uint64
 // --------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_bit_bonds(uint32_t L, uint32_t W, uint64_t nwords,
                                                    const uint32_t *P0, const uint32_t *P1,
-                                                   unsigned long long *acc3)
+                                                   unsigned long long *acc3, uint32_t total)
 {
     unsigned long long bx = 0, by = 0, bz = 0;
     const size_t plane = (size_t)L * W;
@@ -353,7 +402,7 @@ __global__ void __launch_bounds__(256) k_bit_bonds(uint32_t L, uint32_t W, uint6
         unsigned long long tot = 0;
         for (int k = 0; k < 4; ++k)
             tot += part[threadIdx.x][k];
-        atomicAdd(acc3 + threadIdx.x, tot);
+        atomicAdd(acc3 + (total ? 0 : threadIdx.x), tot);   // total: all axes into acc3[0]
     }
 }
 
@@ -537,8 +586,40 @@ hipError_t bit_bonds(hipStream_t st, uint32_t L, const uint32_t *P0, const uint3
     const uint32_t W = L / 64;
     const uint64_t nw = (uint64_t)L * L * W;
     hipLaunchKernelGGL(k_bit_bonds, dim3(grid_cap(nw, 4096)), dim3(256), 0, st, L, W, nw, P0, P1,
-                       acc3);
+                       acc3, 0u);
     return hipGetLastError();
+}
+
+hipError_t bit_bonds_total(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
+                           unsigned long long *acc)
+{
+    const uint32_t W = L / 64;
+    const uint64_t nw = (uint64_t)L * L * W;
+    hipLaunchKernelGGL(k_bit_bonds, dim3(grid_cap(nw, 4096)), dim3(256), 0, st, L, W, nw, P0, P1,
+                       acc, 1u);
+    return hipGetLastError();
+}
+
+hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
+                            uint32_t *P0, uint32_t *P1)
+{
+    uint32_t sB = 0;
+    while ((1u << sB) < B)
+        ++sB;
+    if (B < 2 || (1u << sB) != B || L % (2 * B))
+        return hipErrorInvalidValue;
+    const uint32_t W = L / 64;
+    const uint64_t nw = (uint64_t)L * L * W;
+    for (uint32_t cc = 0; cc < 2; ++cc)
+        for (uint32_t p = 0; p < 2; ++p) {
+            hipLaunchKernelGGL(k_bit_phase, dim3(grid_cap(nw, 8192)), dim3(256), 0, st, L, W, sB,
+                               cc, p, (uint32_t)seed, (uint32_t)(seed >> 32), t, p ? P1 : P0,
+                               p ? P0 : P1);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+        }
+    return hipSuccess;
 }
 
 hipError_t bit_unpack(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,

@@ -307,3 +307,30 @@ def test_fft_corr_matches_oracle(qz, orc, layout, L, n):
     assert m == pytest.approx(mo, abs=1e-12)
     assert np.allclose(C, Co, rtol=0, atol=1e-9)
     assert np.allclose(Sk, Sko, rtol=1e-9, atol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# double checkerboard (coarse cubes of side B)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L,B", [(64, 2), (64, 8), (64, 32), (128, 64), (256, 16)])
+def test_double_checkerboard_matches_oracle(qz, orc, L, B):
+    seed = 90 + L + B
+    say("double checkerboard", L, B)
+    lat = qz.Lattice(L, seed, "bit")
+    lat.set_double_checkerboard(B)
+    n = 6 if L < 256 else 3
+    tr = lat.run(n, 1)
+    s = orc.init(L, seed)
+    want = orc.run_double(s, B, seed, 0, n, 1)
+    assert np.array_equal(tr.astype(np.int64), want)
+    assert np.array_equal(lat.download(), s)
+
+
+def test_double_checkerboard_rejects(qz):
+    lat = qz.Lattice(64, 1, "bit")
+    for B in (3, 64, 1):
+        with pytest.raises(qz.QuenchError):
+            lat.set_double_checkerboard(B)
+    i8 = qz.Lattice(16, 1, "i8")
+    with pytest.raises(qz.QuenchError):
+        i8.set_double_checkerboard(4)
