@@ -67,6 +67,13 @@ def _load():
     lib.or_sweep_double.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
                                     _i8p]
     lib.or_sweep_double.restype = ctypes.c_int64
+    lib.or_sweep_double_mixed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                          ctypes.c_uint32, _i8p]
+    lib.or_sweep_double_mixed.restype = ctypes.c_int64
+    lib.or_coarse_first.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+    lib.or_coarse_first.restype = ctypes.c_int
+    lib.or_fine_first.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64]
+    lib.or_fine_first.restype = ctypes.c_int
     lib.or_init_window.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, _i8p]
     lib.or_init_window.restype = None
@@ -179,23 +186,43 @@ def first_colour(seed: int, t: int) -> int:
     return int(_load().or_first_colour(seed, t))
 
 
-def sweep_double(s: np.ndarray, B: int, seed: int, t: int) -> int:
-    """Double-checkerboard sweep with coarse cubes of side B (needs L % 2B == 0)."""
+def sweep_double(s: np.ndarray, B: int, seed: int, t: int, mixed: bool = False) -> int:
+    """Double-checkerboard sweep with coarse cubes of side B (needs L % 2B == 0).
+
+    mixed=False: the 01 order (coarse 0, then 1; fine 0 then 1 in each cube).
+    mixed=True: coarse order drawn per sweep, fine order per cube and sweep.
+    """
     L = s.shape[0]
     _check_L(L)
     if B < 1 or L % (2 * B):
         raise ValueError("need L % (2B) == 0")
+    if mixed:
+        f = int(_load().or_sweep_double_mixed(L, B, seed, t, _i8(s)))
+        if f < 0:
+            raise MemoryError("order table")
+        return f
     return int(_load().or_sweep_double(L, B, seed, t, _i8(s)))
 
 
-def run_double(s: np.ndarray, B: int, seed: int, t0: int, n: int, every: int = 0) -> np.ndarray:
+def run_double(s: np.ndarray, B: int, seed: int, t0: int, n: int, every: int = 0,
+               mixed: bool = False) -> np.ndarray:
     """n double-checkerboard sweeps from t0; B(t0 + k*every) traced at sweep starts."""
     tr = []
     for k in range(n):
         if every and k % every == 0:
             tr.append(int(bonds(s).sum()))
-        sweep_double(s, B, seed, t0 + k)
+        sweep_double(s, B, seed, t0 + k, mixed)
     return np.array(tr, dtype=np.int64)
+
+
+def coarse_first(seed: int, t: int) -> int:
+    """Mixed double checkerboard: the coarse colour updated first in sweep t."""
+    return int(_load().or_coarse_first(seed, t))
+
+
+def fine_first(seed: int, t: int, b: int) -> int:
+    """Mixed double checkerboard: the fine colour cube b updates first in sweep t."""
+    return int(_load().or_fine_first(seed, t, b))
 
 
 def sweep_mixed(s: np.ndarray, seed: int, t: int) -> int:

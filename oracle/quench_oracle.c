@@ -256,6 +256,85 @@ int64_t or_sweep_double(int L, int B, uint64_t seed, uint32_t t, int8_t *s)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Mixed cycle of the double checkerboard (Supplementary Methods I B): once   */
+/* per sweep the coarse colour updated first is drawn, and, independently,    */
+/* each coarse cube draws which fine colour it updates first.  Our draws:     */
+/*   coarse order: coarse colour 1 first iff bit 0 of word 0 of the block     */
+/*                 (0, t, 3, 0);                                              */
+/*   fine order of cube b = bx + nb*(by + nb*bz), nb = L/B, (bx, by, bz) =    */
+/*                 (x/B, y/B, z/B): fine colour 1 first iff bit b of the      */
+/*                 blocks (floor(b/128), t, 4, 0), extracted as the tie bits. */
+/* A sweep: for the two coarse colours in the drawn order, two steps; in      */
+/* step k every cube of that coarse colour updates its fine colour            */
+/* (first ^ k).  Cubes of one coarse colour never touch, so a step updates    */
+/* in place.  Tie bits are those of the plain checkerboard (j, t, fine p).    */
+/* ------------------------------------------------------------------------ */
+int or_coarse_first(uint64_t seed, uint32_t t)
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { 0u, t, 3u, 0u };
+    uint32_t w[4];
+    or_philox4x32_10(ctr, key, w);
+    return (int)(w[0] & 1u);
+}
+
+int or_fine_first(uint64_t seed, uint32_t t, uint64_t b)
+{
+    return or_bit_of(seed, b, t, 4u, 0u);
+}
+
+static int64_t or_step_mixed(int L, int B, uint64_t seed, uint32_t t, int cc, int k,
+                             const uint8_t *first, int8_t *s)
+{
+    const int nb = L / B;
+    int64_t flips = 0;
+#pragma omp parallel for schedule(static) reduction(+ : flips)
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                if (((x / B + y / B + z / B) & 1) != cc)
+                    continue;
+                int64_t b = (int64_t)(x / B) + (int64_t)nb * ((int64_t)(y / B) + (int64_t)nb * (z / B));
+                int p = (x + y + z) & 1;
+                if (p != (first[b] ^ k))
+                    continue;
+                int a = or_antialigned(L, s, x, y, z);
+                int flip = 0;
+                if (a >= 4) {
+                    flip = 1;
+                } else if (a == 3) {
+                    uint64_t j = (uint64_t)(x / 2) +
+                                 (uint64_t)(L / 2) * ((uint64_t)y + (uint64_t)L * (uint64_t)z);
+                    flip = or_tie_bit(seed, t, p, j);
+                }
+                if (flip) {
+                    int64_t i = or_idx(L, x, y, z);
+                    s[i] = (int8_t)-s[i];
+                    ++flips;
+                }
+            }
+    return flips;
+}
+
+/* Returns the number of flips, or -1 if the order table cannot be allocated. */
+int64_t or_sweep_double_mixed(int L, int B, uint64_t seed, uint32_t t, int8_t *s)
+{
+    const int64_t nb = L / B, ncubes = nb * nb * nb;
+    uint8_t *first = (uint8_t *)malloc((size_t)ncubes);
+    if (!first)
+        return -1;
+    for (int64_t b = 0; b < ncubes; ++b)
+        first[b] = (uint8_t)or_fine_first(seed, t, (uint64_t)b);
+    const int c0 = or_coarse_first(seed, t);
+    int64_t f = 0;
+    for (int m = 0; m < 2; ++m)
+        for (int k = 0; k < 2; ++k)
+            f += or_step_mixed(L, B, seed, t, c0 ^ m, k, first, s);
+    free(first);
+    return f;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Unsatisfied-bond counts per axis: B_a = #{i : s_i != s_{i+e_a}}.          */
 /* Energy E = -(3N - 2B), B = B_x + B_y + B_z.                               */
 /* ------------------------------------------------------------------------ */

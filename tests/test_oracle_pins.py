@@ -587,6 +587,83 @@ def test_double_checkerboard_bruteforce(orc, torch_philox, L, B):
         assert np.array_equal(s_bf, s_or), t
 
 
+@pytest.mark.parametrize("L,B", [(4, 2), (8, 2), (8, 4)])
+def test_double_checkerboard_mixed_bruteforce(orc, torch_philox, L, B):
+    """Mixed cycle (Supplementary Methods I B): the coarse order drawn per
+    sweep, each cube's fine order drawn per sweep; draws and tie bits from
+    torch's Philox, every proposal judged by full energies, the sites of a
+    step in random order."""
+    rng = np.random.default_rng(100 + B)
+    z, y, x = np.indices((L, L, L))
+    fine = (x + y + z) % 2
+    coarse = (x // B + y // B + z // B) % 2
+    nb = L // B
+    cube = (x // B) + nb * ((y // B) + nb * (z // B))
+    jj = colour_index(L)
+    seed = 0x1234_0000_0021
+    s_or = orc.init(L, seed)
+    s_bf = s_or.copy()
+    for t in range(5):
+        c0 = torch_philox([[0, t, 3, 0, seed & 0xFFFFFFFF, seed >> 32]])[0][0] & 1
+        first = bits_from_blocks(torch_philox, seed, np.arange(nb ** 3), t, 4, 0)
+        for m in (0, 1):
+            cc = c0 ^ m
+            for k in (0, 1):
+                p_site = first[cube] ^ k
+                sel = (coarse == cc) & (fine == p_site)
+                sites = np.argwhere(sel)
+                rng.shuffle(sites)
+                bits = {p: bits_from_blocks(torch_philox, seed, jj.ravel(), t, p, 0).reshape(L, L, L)
+                        for p in (0, 1)}
+                for (zz, yy, xx) in sites:
+                    e0 = energy(s_bf)
+                    s_bf[zz, yy, xx] = -s_bf[zz, yy, xx]
+                    dE = energy(s_bf) - e0
+                    tie = bits[fine[zz, yy, xx]][zz, yy, xx]
+                    if not (dE < 0 or (dE == 0 and tie == 1)):
+                        s_bf[zz, yy, xx] = -s_bf[zz, yy, xx]
+        orc.sweep_double(s_or, B, seed, t, mixed=True)
+        assert np.array_equal(s_bf, s_or), t
+
+
+def test_double_checkerboard_mixed_draws(orc, torch_philox):
+    """Keying of the two draws against torch's Philox, and their balance."""
+    seed = 91
+    rows = [[0, t, 3, 0, seed, 0] for t in range(400)]
+    want = [w[0] & 1 for w in torch_philox(rows)]
+    got = [orc.coarse_first(seed, t) for t in range(400)]
+    assert got == want
+    assert 150 < sum(got) < 250
+    b = np.arange(0, 4096, 7)
+    want_f = bits_from_blocks(torch_philox, seed, b, 9, 4, 0)
+    got_f = np.array([orc.fine_first(seed, 9, int(k)) for k in b])
+    assert np.array_equal(got_f, want_f)
+    assert abs(got_f.mean() - 0.5) < 5 * 0.5 / np.sqrt(len(b))
+    # the coarse draw is not the plain checkerboard's colour draw
+    assert got != [orc.first_colour(seed, t) for t in range(400)]
+
+
+def test_double_checkerboard_mixed_invariants(orc):
+    """Energy never rises, uniform states absorb, and an isolated flipped
+    spin (a = 6) heals in one sweep whatever the drawn orders."""
+    L, B = 16, 4
+    s = orc.init(L, 8)
+    Bprev = int(orc.bonds(s).sum())
+    for t in range(10):
+        orc.sweep_double(s, B, 8, t, mixed=True)
+        Bn = int(orc.bonds(s).sum())
+        assert Bn <= Bprev
+        Bprev = Bn
+    u = np.full((L, L, L), -1, dtype=np.int8)
+    orc.sweep_double(u, B, 8, 0, mixed=True)
+    assert np.all(u == -1)
+    for t in range(4):
+        w = np.full((L, L, L), 1, dtype=np.int8)
+        w[5, 6, 7] = -1
+        orc.sweep_double(w, B, 8, t, mixed=True)
+        assert np.all(w == 1)
+
+
 def test_double_checkerboard_reduces_to_plain_when_blocks_cover(orc):
     """With B = L/2 the coarse colours split the lattice into 8 cubes; the
     trajectory differs from the plain 01 cycle in general, but uniform states
