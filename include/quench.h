@@ -146,19 +146,25 @@ int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
  * paper's main runs): colour 0 then colour 1 in every sweep.  QZ_CYCLE_MIXED:
  * the colour updated first in sweep t is drawn at random for each sweep --
  * colour 1 first iff bit 0 of word 0 of Philox block (0, t, 2, 0) is set --
- * which restores detailed balance.  The bond trace of a sweep is still the
- * bond count of the state entering it. */
+ * which restores detailed balance.  With the double checkerboard the mixed
+ * cycle draws the coarse order and each cube's fine order instead (see
+ * qz_set_double_checkerboard).  The bond trace of a sweep is still the bond
+ * count of the state entering it. */
 enum { QZ_CYCLE_01 = 0, QZ_CYCLE_MIXED = 1 };
 int qz_set_cycle(qz_lattice *q, int cycle);
 
 /* Double checkerboard (Supplementary Methods I A; bit layout).  Cubes of side
- * B form a coarse checkerboard, coarse colour (x/B + y/B + z/B) mod 2; a sweep
- * updates the coarse-colour-0 cubes (fine colour 0 sites, then fine colour 1
- * sites), then the coarse-colour-1 cubes the same way.  Each site draws the
- * same tie bit as in the plain checkerboard.  B must be a power of two >= 2
- * with L % (2B) == 0 (QZ_EINVAL otherwise); B = 0 returns to the plain
- * checkerboard.  Only the 01 order is available here (QZ_EUNSUPPORTED with
- * the mixed cycle).  The paper does not state its block size. */
+ * B form a coarse checkerboard, coarse colour (x/B + y/B + z/B) mod 2.  In the
+ * 01 cycle a sweep updates the coarse-colour-0 cubes (fine colour 0 sites,
+ * then fine colour 1 sites), then the coarse-colour-1 cubes the same way.  In
+ * the mixed cycle (Supplementary Methods I B) the coarse colour taken first in
+ * sweep t is 1 iff bit 0 of word 0 of Philox block (0, t, 3, 0) is set, and
+ * cube b = x/B + (L/B)(y/B + (L/B) z/B) updates fine colour 1 first iff bit b
+ * of the blocks (b/128, t, 4, 0) is set (bit extraction as for the tie bits).
+ * Each site draws the same tie bit as in the plain checkerboard.  B must be a
+ * power of two >= 2 with L % (2B) == 0 (QZ_EINVAL otherwise); B = 0 returns to
+ * the plain checkerboard.  QZ_EUNSUPPORTED on the int8 layout.  The paper does
+ * not state its block size. */
 int qz_set_double_checkerboard(qz_lattice *q, uint32_t B);
 
 /* The paper's own correlation measurement (Methods, "Calculating the

@@ -113,7 +113,7 @@ int sweep_once(qz_lattice *q, unsigned long long *bond_acc)
             QZ_HIP(q, qz::bit_bonds_total(q->st, q->L, bit_plane(q, c, 0), bit_plane(q, c, 1),
                                           bond_acc));
         QZ_HIP(q, qz::bit_double_sweep(q->st, q->L, q->dcb, q->seed, t, bit_plane(q, c, 0),
-                                       bit_plane(q, c, 1)));
+                                       bit_plane(q, c, 1), q->mixed));
     } else {
         const int a = q->cur, b = 1 - q->cur;
         QZ_HIP(q, qz::bit_sweep(q->st, q->L, q->seed, t, q->tune, bit_plane(q, a, 0),
@@ -483,8 +483,6 @@ QZ_EXPORT int qz_set_cycle(qz_lattice *q, int cycle)
         return fail(QZ_EINVAL, "null handle");
     if (cycle != QZ_CYCLE_01 && cycle != QZ_CYCLE_MIXED)
         return fail(QZ_EINVAL, "unknown cycle");
-    if (cycle == QZ_CYCLE_MIXED && q->dcb)
-        return fail(QZ_EUNSUPPORTED, "the double checkerboard runs the 01 cycle only");
     q->mixed = cycle == QZ_CYCLE_MIXED;
     return QZ_OK;
 }
@@ -600,8 +598,6 @@ QZ_EXPORT int qz_set_double_checkerboard(qz_lattice *q, uint32_t B)
         return fail(QZ_EUNSUPPORTED, "the double checkerboard runs on the bit layout");
     if (B < 2 || (B & (B - 1)) || q->L % (2 * B))
         return fail(QZ_EINVAL, "B must be a power of two >= 2 with L % (2B) == 0");
-    if (q->mixed)
-        return fail(QZ_EUNSUPPORTED, "the double checkerboard runs the 01 cycle only");
     q->dcb = B;
     return QZ_OK;
 }

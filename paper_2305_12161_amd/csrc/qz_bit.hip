@@ -280,13 +280,47 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
 // updates, in place, the fine-colour-p sites of the coarse-colour-cc cubes;
 // they read only fine colour 1-p, so threads never race.  Thread per word of
 // plane p; the sites outside the phase are masked out.
+//
+// Mixed cycle (Supplementary Methods I B): the coarse colour updated first is
+// drawn once per sweep (coarse colour 1 first iff bit 0 of word 0 of Philox
+// block (0, t, 3, 0)), and each cube draws its fine order once per sweep (fine
+// colour 1 first iff bit b of blocks (b / 128, t, 4, 0), b = bx + nb (by + nb
+// bz) the cube index, nb = L / B).  Then `kc` is the position of the coarse
+// colour in the sweep's order and `step` selects, per cube, the fine colour
+// (first ^ step); a launch for plane p masks in the cubes whose fine colour
+// of this step is p.
 // --------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t cube_order_mask(uint32_t w, uint32_t y, uint32_t z,
+                                                    uint32_t L, uint32_t sB, uint32_t k0,
+                                                    uint32_t k1, uint32_t t)
+{
+    // bit b of the word lies in cube column (32w + b) >> (sB - 1) along x
+    const uint32_t q = sB - 1;
+    const uint32_t nb = L >> sB;
+    const uint64_t cb0 = (uint64_t)((32u * w) >> q) +
+                         (uint64_t)nb * ((uint64_t)(y >> sB) + (uint64_t)nb * (z >> sB));
+    const Words4 o = philox10((uint32_t)(cb0 >> 7), t, 4u, 0u, k0, k1);
+    const uint32_t sub = (uint32_t)(cb0 >> 5) & 3u;
+    const uint32_t word = (sub & 2u) ? ((sub & 1u) ? o.w[3] : o.w[2])
+                                     : ((sub & 1u) ? o.w[1] : o.w[0]);
+    const uint32_t bits = word >> (uint32_t)(cb0 & 31u);   // bit k: cube cb0 + k
+    if (q >= 5)
+        return (bits & 1u) ? 0xFFFFFFFFu : 0u;
+    uint32_t m = 0u;
+#pragma unroll
+    for (uint32_t b = 0; b < 32; ++b)
+        m |= ((bits >> (b >> q)) & 1u) << b;
+    return m;
+}
+
 __global__ void __launch_bounds__(256)
-    k_bit_phase(uint32_t L, uint32_t W, uint32_t sB, uint32_t cc, uint32_t p, uint32_t k0,
-                uint32_t k1, uint32_t t, uint32_t *Pp, const uint32_t *Po)
+    k_bit_phase(uint32_t L, uint32_t W, uint32_t sB, uint32_t kc, uint32_t p, uint32_t k0,
+                uint32_t k1, uint32_t t, uint32_t *Pp, const uint32_t *Po, uint32_t mixed,
+                uint32_t step)
 {
     const uint64_t nwords = (uint64_t)L * L * W;
     const size_t plane = (size_t)L * W;
+    const uint32_t cc = mixed ? (kc ^ (philox10(0u, t, 3u, 0u, k0, k1).w[0] & 1u)) : kc;
     // bit b of a word holds x = 64w + 2b + pi, so x / B = (32w + b) >> (sB - 1)
     const uint32_t q = sB - 1;
     const uint32_t pat = (q == 0) ? 0xAAAAAAAAu : (q == 1) ? 0xCCCCCCCCu : (q == 2) ? 0xF0F0F0F0u
@@ -297,7 +331,12 @@ __global__ void __launch_bounds__(256)
         const uint64_t row = g / W;
         const uint32_t y = (uint32_t)(row % L), z = (uint32_t)(row / L);
         const uint32_t A = (((32u * w) >> q) + (y >> sB) + (z >> sB)) & 1u;
-        const uint32_t mask = ((A ^ cc) & 1u) ? pat : ~pat;
+        uint32_t mask = ((A ^ cc) & 1u) ? pat : ~pat;
+        if (mixed && mask != 0u) {
+            // cubes whose fine colour in this step is p: first == p ^ step
+            const uint32_t first1 = cube_order_mask(w, y, z, L, sB, k0, k1, t);
+            mask &= ((p ^ step) & 1u) ? first1 : ~first1;
+        }
         if (mask == 0u)
             continue;
         const uint32_t pi = (p + y + z) & 1u;
@@ -601,7 +640,7 @@ hipError_t bit_bonds_total(hipStream_t st, uint32_t L, const uint32_t *P0, const
 }
 
 hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
-                            uint32_t *P0, uint32_t *P1)
+                            uint32_t *P0, uint32_t *P1, bool mixed)
 {
     uint32_t sB = 0;
     while ((1u << sB) < B)
@@ -610,15 +649,19 @@ hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t see
         return hipErrorInvalidValue;
     const uint32_t W = L / 64;
     const uint64_t nw = (uint64_t)L * L * W;
-    for (uint32_t cc = 0; cc < 2; ++cc)
-        for (uint32_t p = 0; p < 2; ++p) {
-            hipLaunchKernelGGL(k_bit_phase, dim3(grid_cap(nw, 8192)), dim3(256), 0, st, L, W, sB,
-                               cc, p, (uint32_t)seed, (uint32_t)(seed >> 32), t, p ? P1 : P0,
-                               p ? P0 : P1);
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess)
-                return e;
-        }
+    // 01 cycle: (coarse, fine) = (0,0), (0,1), (1,0), (1,1).  Mixed cycle: for
+    // each coarse colour in the drawn order, two steps, each one launch per plane.
+    const uint32_t nsteps = mixed ? 2u : 1u;
+    for (uint32_t kc = 0; kc < 2; ++kc)
+        for (uint32_t step = 0; step < nsteps; ++step)
+            for (uint32_t p = 0; p < 2; ++p) {
+                hipLaunchKernelGGL(k_bit_phase, dim3(grid_cap(nw, 8192)), dim3(256), 0, st, L, W,
+                                   sB, kc, p, (uint32_t)seed, (uint32_t)(seed >> 32), t,
+                                   p ? P1 : P0, p ? P0 : P1, mixed ? 1u : 0u, step);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess)
+                    return e;
+            }
     return hipSuccess;
 }
 

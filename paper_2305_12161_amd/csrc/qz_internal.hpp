@@ -56,7 +56,7 @@ hipError_t bit_bonds_total(hipStream_t st, uint32_t L, const uint32_t *P0, const
                            unsigned long long *acc);
 // Double-checkerboard sweep in place (B a power of two >= 2, L % 2B == 0).
 hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
-                            uint32_t *P0, uint32_t *P1);
+                            uint32_t *P0, uint32_t *P1, bool mixed);
 hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
                     unsigned long long *anti /* 3*(L/2+1) */, unsigned long long *ones);
 // Unpack planes z in [z0, z0+nz) to int8 (index (z-z0)*L*L + y*L + x).

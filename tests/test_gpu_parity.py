@@ -312,16 +312,19 @@ def test_fft_corr_matches_oracle(qz, orc, layout, L, n):
 # --------------------------------------------------------------------------
 # double checkerboard (coarse cubes of side B)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("L,B", [(64, 2), (64, 8), (64, 32), (128, 64), (256, 16)])
-def test_double_checkerboard_matches_oracle(qz, orc, L, B):
-    seed = 90 + L + B
-    say("double checkerboard", L, B)
+@pytest.mark.parametrize("mixed", [False, True], ids=["01", "mixed"])
+@pytest.mark.parametrize("L,B", [(64, 2), (64, 8), (64, 32), (128, 4), (128, 64), (256, 16)])
+def test_double_checkerboard_matches_oracle(qz, orc, L, B, mixed):
+    seed = 90 + L + B + (1000 if mixed else 0)
+    say("double checkerboard", L, B, "mixed" if mixed else "01")
     lat = qz.Lattice(L, seed, "bit")
     lat.set_double_checkerboard(B)
+    if mixed:
+        lat.set_cycle(True)
     n = 6 if L < 256 else 3
     tr = lat.run(n, 1)
     s = orc.init(L, seed)
-    want = orc.run_double(s, B, seed, 0, n, 1)
+    want = orc.run_double(s, B, seed, 0, n, 1, mixed=mixed)
     assert np.array_equal(tr.astype(np.int64), want)
     assert np.array_equal(lat.download(), s)
 
