@@ -8,6 +8,24 @@
 namespace qz {
 
 // ---------------------------------------------------------------------------
+// Symmetric three-input bitwise functions as single gfx950 v_bitop3_b32
+// instructions.  The truth tables below are symmetric in their three inputs,
+// so they do not depend on how the hardware orders the inputs in the index.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+__device__ __forceinline__ uint32_t and3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x80);
+}
+
+// ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round multiplies
 // counter words 0 and 2 by the two round multipliers (full 64-bit products),
 // then mixes: (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0)).
@@ -26,8 +44,8 @@ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
     for (int round = 0; round < 10; ++round) {
         const uint64_t pa = (uint64_t)kMulA * c0;
         const uint64_t pb = (uint64_t)kMulB * c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = n0;
@@ -40,23 +58,6 @@ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
     return r;
 }
 
-// ---------------------------------------------------------------------------
-// Symmetric three-input bitwise functions as single gfx950 v_bitop3_b32
-// instructions.  The truth tables below are symmetric in their three inputs,
-// so they do not depend on how the hardware orders the inputs in the index.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
-{
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-}
-__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c)
-{
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
-}
-__device__ __forceinline__ uint32_t and3(uint32_t a, uint32_t b, uint32_t c)
-{
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x80);
-}
 
 // acc + popcount(x) as one v_bcnt_u32_b32 (the compiler otherwise tends to
 // pair popcounts through v_add3, costing an extra instruction per two).
