@@ -142,6 +142,22 @@ int qz_download_window(qz_lattice *q, const uint32_t origin[3], uint32_t W, int8
 int qz_set_tuning(qz_lattice *q, int V, int Ty, int Tz);
 int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
 
+/* Sweeps per pass over memory (bit layout).  sweeps = 1 (the default): every
+ * sweep reads and writes the lattice once.  sweeps = 2: sweeps t and t+1 run
+ * in one pass that keeps the state after sweep t on chip, halving the memory
+ * traffic per sweep; the trajectory, the bond trace and every measurement are
+ * identical to sweeps = 1 (Methods, "Checkerboard update": the 01 cycle is
+ * applied exactly as before).  Runs of an odd number of sweeps end with one
+ * single sweep; the mixed cycle and the double checkerboard always run one
+ * sweep per pass.  V, Ty, Tz tune the two-sweep kernel as in qz_set_tuning
+ * (V words per lane, Ty owned rows per tile, Ty + 8 rows held, Tz planes);
+ * all three 0 selects the default for L.  QZ_EINVAL for another sweep count
+ * or a tuning that does not fit (at most 1024 threads and 60 KiB of LDS per
+ * workgroup); QZ_EUNSUPPORTED for the int8 layout.  qz_get_pass reports
+ * (sweeps, V, Ty, Tz). */
+int qz_set_pass(qz_lattice *q, int sweeps, int V, int Ty, int Tz);
+int qz_get_pass(const qz_lattice *q, int out_sweeps_V_Ty_Tz[4]);
+
 /* Sublattice order (Supplementary Methods I B).  QZ_CYCLE_01 (the default, the
  * paper's main runs): colour 0 then colour 1 in every sweep.  QZ_CYCLE_MIXED:
  * the colour updated first in sweep t is drawn at random for each sweep --

@@ -50,6 +50,8 @@ def _load():
         "qz_fft_corr": ([vp, vp, sz, c.POINTER(c.c_double), c.POINTER(c.c_double),
                          c.POINTER(u64), c.POINTER(u64), c.POINTER(c.c_double)], i32),
         "qz_get_tuning": ([vp, c.POINTER(i32)], i32),
+        "qz_set_pass": ([vp, i32, i32, i32, i32], i32),
+        "qz_get_pass": ([vp, c.POINTER(i32)], i32),
         "qz_status_string": ([i32], c.c_char_p),
         "qz_last_error": ([], c.c_char_p),
     }
@@ -202,6 +204,17 @@ class Lattice:
     def tuning(self):
         out = (ctypes.c_int * 3)()
         _check(lib.qz_get_tuning(self._h, out))
+        return tuple(int(v) for v in out)
+
+    def set_pass(self, sweeps: int, V: int = 0, Ty: int = 0, Tz: int = 0) -> None:
+        """Sweeps per pass over memory: 1, or 2 (two sweeps kept on chip; V, Ty,
+        Tz tune that kernel, all 0 = default).  Results do not change."""
+        _check(lib.qz_set_pass(self._h, sweeps, V, Ty, Tz))
+
+    def pass_config(self):
+        """(sweeps per pass, V, Ty, Tz of the two-sweep kernel)."""
+        out = (ctypes.c_int * 4)()
+        _check(lib.qz_get_pass(self._h, out))
         return tuple(int(v) for v in out)
 
 

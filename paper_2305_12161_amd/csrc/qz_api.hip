@@ -26,6 +26,8 @@ struct qz_lattice {
     qz::StateMap map;
     int cur;                 // bit layout: which copy holds the current state
     qz::BitTuning tune;
+    int pass;                // sweeps per pass over memory (1 or 2; bit layout)
+    qz::BitTuning tune2;     // tuning of the two-sweep pass
     bool mixed;              // mixed cycle instead of the 01 cycle
     uint32_t dcb;            // > 0: double checkerboard with coarse cubes of this side
     bool failed;
@@ -125,13 +127,34 @@ int sweep_once(qz_lattice *q, unsigned long long *bond_acc)
     return QZ_OK;
 }
 
+// Sweeps t and t+1 in one pass (bit layout, plain checkerboard, 01 cycle).
+int sweep_pair(qz_lattice *q, unsigned long long *acc_a, unsigned long long *acc_c)
+{
+    const int a = q->cur, b = 1 - q->cur;
+    QZ_HIP(q, qz::bit_sweep2(q->st, q->L, q->seed, (uint32_t)q->t, q->tune2, bit_plane(q, a, 0),
+                             bit_plane(q, a, 1), bit_plane(q, b, 0), bit_plane(q, b, 1), acc_a,
+                             acc_c));
+    q->cur = b;
+    q->t += 2;
+    return QZ_OK;
+}
+
 int run_impl(qz_lattice *q, uint64_t n, uint64_t every, unsigned long long *dev_trace)
 {
-    for (uint64_t k = 0; k < n; ++k) {
-        unsigned long long *acc = nullptr;
-        if (every > 0 && dev_trace != nullptr && k % every == 0)
-            acc = dev_trace + k / every;
-        int rc = sweep_once(q, acc);
+    const bool pairs = q->pass == 2 && q->layout == QZ_LAYOUT_BIT && !q->mixed && q->dcb == 0;
+    auto acc_at = [&](uint64_t k) -> unsigned long long * {
+        return (every > 0 && dev_trace != nullptr && k % every == 0) ? dev_trace + k / every
+                                                                      : nullptr;
+    };
+    for (uint64_t k = 0; k < n;) {
+        int rc;
+        if (pairs && n - k >= 2) {
+            rc = sweep_pair(q, acc_at(k), acc_at(k + 1));
+            k += 2;
+        } else {
+            rc = sweep_once(q, acc_at(k));
+            k += 1;
+        }
         if (rc != QZ_OK)
             return rc;
     }
@@ -209,10 +232,13 @@ QZ_EXPORT int qz_create(uint32_t L, uint64_t seed, int layout, void *dev_mem, si
     q->cur = 0;
     q->mixed = false;
     q->dcb = 0;
+    q->pass = 1;
     q->failed = false;
     q->fft_ready = false;
-    if (layout == QZ_LAYOUT_BIT)
+    if (layout == QZ_LAYOUT_BIT) {
         q->tune = qz::bit_tuning_default(L);
+        q->tune2 = qz::bit_tuning2_default(L);
+    }
     hipError_t e;
     if (layout == QZ_LAYOUT_I8)
         e = qz::i8_init(q->st, L, seed, i8_spins(q));
@@ -474,6 +500,44 @@ QZ_EXPORT int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3])
     out_V_Ty_Tz[0] = q->tune.V;
     out_V_Ty_Tz[1] = q->tune.Ty;
     out_V_Ty_Tz[2] = q->tune.Tz;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_set_pass(qz_lattice *q, int sweeps, int V, int Ty, int Tz)
+{
+    if (!q)
+        return fail(QZ_EINVAL, "null handle");
+    if (q->layout != QZ_LAYOUT_BIT)
+        return fail(QZ_EUNSUPPORTED, "only the bit layout has multi-sweep passes");
+    if (sweeps == 1) {
+        q->pass = 1;
+        return QZ_OK;
+    }
+    if (sweeps != 2)
+        return fail(QZ_EINVAL, "sweeps per pass must be 1 or 2");
+    qz::BitTuning t = qz::bit_tuning2_default(q->L);
+    if (V != 0 || Ty != 0 || Tz != 0) {
+        t.V = V;
+        t.Ty = Ty;
+        t.Tz = Tz;
+    }
+    if (!qz::bit_tuning2_valid(q->L, t))
+        return fail(QZ_EINVAL, "two-sweep tuning does not fit this lattice size");
+    q->tune2 = t;
+    q->pass = 2;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_get_pass(const qz_lattice *q, int out_sweeps_V_Ty_Tz[4])
+{
+    if (!q || !out_sweeps_V_Ty_Tz)
+        return fail(QZ_EINVAL, "null argument");
+    if (q->layout != QZ_LAYOUT_BIT)
+        return fail(QZ_EUNSUPPORTED, "only the bit layout has multi-sweep passes");
+    out_sweeps_V_Ty_Tz[0] = q->pass;
+    out_sweeps_V_Ty_Tz[1] = q->tune2.V;
+    out_sweeps_V_Ty_Tz[2] = q->tune2.Ty;
+    out_sweeps_V_Ty_Tz[3] = q->tune2.Tz;
     return QZ_OK;
 }
 

@@ -19,55 +19,17 @@
 // new colour 0 is recomputed for one halo row on each side and one halo plane
 // at each end of the tile (from copy A, so tiles never race).  Rows are
 // exchanged through LDS, one barrier per plane step.
+#include "qz_bitops.hpp"
 #include "qz_device.hpp"
 #include "qz_internal.hpp"
 
 namespace qz {
 namespace {
 
-// --------------------------------------------------------------------------
-// vector load/store of V consecutive words
-// --------------------------------------------------------------------------
-template <int V> struct VecT;
-template <> struct VecT<1> { using T = uint32_t; };
-template <> struct VecT<2> { using T = uint2; };
-template <> struct VecT<4> { using T = uint4; };
-
-template <int V>
-__device__ __forceinline__ void load_words(const uint32_t *p, uint32_t (&r)[V])
-{
-    if constexpr (V == 4) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(p);
-        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
-    } else if constexpr (V == 2) {
-        const uint2 v = *reinterpret_cast<const uint2 *>(p);
-        r[0] = v.x; r[1] = v.y;
-    } else {
-        r[0] = *p;
-    }
-}
-
-template <int V>
-__device__ __forceinline__ void store_words(uint32_t *p, const uint32_t (&r)[V])
-{
-    if constexpr (V == 4) {
-        *reinterpret_cast<uint4 *>(p) = make_uint4(r[0], r[1], r[2], r[3]);
-    } else if constexpr (V == 2) {
-        *reinterpret_cast<uint2 *>(p) = make_uint2(r[0], r[1]);
-    } else {
-        *p = r[0];
-    }
-}
-
-// Store to HBM with the nontemporal hint: the written copy is not read again
-// in this sweep, so it should not displace the read copy's rows from cache.
-template <int V>
-__device__ __forceinline__ void store_words_nt(uint32_t *p, const uint32_t (&r)[V])
-{
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-        __builtin_nontemporal_store(r[v], p + v);
-}
+using bitops::load_words;
+using bitops::store_words;
+using bitops::store_words_nt;
+using bitops::update_words;
 
 struct SweepArgs {
     const uint32_t *S0, *S1;   // read copy, colour planes 0 and 1
@@ -79,67 +41,6 @@ struct SweepArgs {
     uint32_t k0, k1, t;
     uint32_t mixed;            // 1: mixed cycle (first colour drawn per sweep)
 };
-
-// Update V words of one colour.  own = the words being updated; same = the
-// other colour's same-row words (x-neighbour at the same index); adj = the
-// word just outside the lane's range on the side given by pi; ym/yp/zm/zp the
-// other colour's rows y-1, y+1 and planes z-1, z+1.
-// COUNT: also add the sites' anti-aligned counts (sum a) to `acc`.
-template <int V, bool COUNT>
-__device__ __forceinline__ void update_words(const uint32_t (&own)[V], const uint32_t (&same)[V],
-                                             uint32_t adj, uint32_t pi, const uint32_t (&ym)[V],
-                                             const uint32_t (&yp)[V], const uint32_t (&zm)[V],
-                                             const uint32_t (&zp)[V], uint32_t k0, uint32_t k1,
-                                             uint32_t ctr0, uint32_t sub, uint32_t t, uint32_t p,
-                                             uint32_t (&out)[V], int &acc)
-{
-    UpCount c[V];
-    uint32_t ties = 0;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        uint32_t shifted;
-        if (pi == 0u) {
-            // neighbour at k-1: bits move up by one, bit 0 from the word below
-            const uint32_t lo = (v > 0) ? same[v > 0 ? v - 1 : 0] : adj;
-            shifted = funnel(same[v], lo, 31);
-        } else {
-            // neighbour at k+1: bits move down by one, bit 31 from the word above
-            const uint32_t hi = (v < V - 1) ? same[v < V - 1 ? v + 1 : 0] : adj;
-            shifted = funnel(hi, same[v], 1);
-        }
-        c[v] = count_up(same[v], shifted, ym[v], yp[v], zm[v], zp[v]);
-        ties |= up_tie(c[v]);
-    }
-    uint32_t r[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-        r[v] = 0u;
-    if (ties != 0u) {
-        const Words4 rb = philox10(ctr0 >> 2, t, p, 0u, k0, k1);
-        // Word (sub + v) of the block, chosen without a dynamically indexed
-        // array (which would live in scratch memory).  With V = 4 the lane's
-        // words start a block (sub = 0); with V = 2, sub is 0 or 2.
-        if constexpr (V == 4) {
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-                r[v] = rb.w[v];
-        } else if constexpr (V == 2) {
-            const bool hi = (sub & 2u) != 0u;
-            r[0] = hi ? rb.w[2] : rb.w[0];
-            r[1] = hi ? rb.w[3] : rb.w[1];
-        } else {
-            const uint32_t lo = (sub & 1u) ? rb.w[1] : rb.w[0];
-            const uint32_t hi = (sub & 1u) ? rb.w[3] : rb.w[2];
-            r[0] = (sub & 2u) ? hi : lo;
-        }
-    }
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        out[v] = up_rule(own[v], c[v], r[v]);
-        if constexpr (COUNT)
-            acc += up_antialigned_sum(own[v], c[v]);
-    }
-}
 
 template <int V, bool COUNT>
 __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)

@@ -1,0 +1,299 @@
+// qz_bit2.hip -- two sweeps of the 01 cycle in ONE streaming pass (1-bit layout).
+//
+// The one-sweep kernel reads every word once and writes it once per sweep, so
+// it is bound by HBM.  Here a workgroup carries the lattice through sweeps t
+// and t+1 before writing it back: the intermediate state lives only in
+// registers and LDS, halving the memory traffic per sweep.  A tile holds E =
+// Ty + 8 rows x all of x and streams along z through Tz planes.  At plane step
+// q four stages run, each one plane behind the one before:
+//   A  sweep t,   colour 0 of plane q    from old colour 1 of planes q-1, q, q+1
+//   B  sweep t,   colour 1 of plane q-1  from A's colour 0 of planes q-2, q-1, q
+//   C  sweep t+1, colour 0 of plane q-2  from B's colour 1 of planes q-3, q-2, q-1
+//   D  sweep t+1, colour 1 of plane q-3  from C's colour 0 of planes q-4, q-3, q-2
+// (Methods, "Checkerboard update": each colour reads only the other one).  The
+// y-neighbour rows of every stage's input come from LDS (four row sets per
+// step, double-buffered, one barrier per step); each stage loses one row at
+// each side, so the tile owns rows [4, E-4) and recomputes the rest, and it
+// recomputes three planes at each z end.  Reads copy A, writes copy B, so
+// tiles never race.  The results are identical to two one-sweep passes.
+#include "qz_bitops.hpp"
+#include "qz_device.hpp"
+#include "qz_internal.hpp"
+
+namespace qz {
+namespace {
+
+using bitops::load_words;
+using bitops::store_words;
+using bitops::store_words_nt;
+using bitops::update_words;
+
+struct Sweep2Args {
+    const uint32_t *S0, *S1;            // read copy, colour planes 0 and 1
+    uint32_t *D0, *D1;                  // write copy
+    unsigned long long *acc_a, *acc_c;  // bond counts entering sweeps t and t+1
+    uint32_t L, W, R;                   // R = W / V lanes per row
+    uint32_t Ty, E, Tz, nty;            // E = Ty + 8 rows held per tile
+    uint32_t k0, k1, t;
+};
+
+template <int V>
+__device__ __forceinline__ void copy_words(uint32_t (&d)[V], const uint32_t (&s)[V])
+{
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        d[v] = s[v];
+}
+
+// CA / CC: add the anti-aligned counts of the owned colour-0 sites of the state
+// entering sweep t (stage A) / sweep t+1 (stage C).
+template <int V, bool CA, bool CC>
+__global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
+{
+    extern __shared__ uint32_t lds[];
+    const uint32_t L = A.L, W = A.W, E = A.E;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t e = tid / A.R;               // held row
+    const uint32_t w0 = (tid % A.R) * V;        // first word of this lane
+
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t ty = tile % A.nty, tz = tile / A.nty;
+    const uint32_t y0 = ty * A.Ty, z0 = tz * A.Tz;
+    const uint32_t Tya = min(A.Ty, L - y0), Tza = min(A.Tz, L - z0);
+    const uint32_t Ea = Tya + 8;
+
+    const bool held = e < Ea;
+    const bool rowA = held && e >= 1 && e + 1 < Ea;
+    const bool rowB = held && e >= 2 && e + 2 < Ea;
+    const bool rowC = held && e >= 3 && e + 3 < Ea;
+    const bool rowD = held && e >= 4 && e + 4 < Ea;   // owned rows
+    const uint32_t y = (y0 + L - 4 + e) % L;
+    const uint32_t em = e - 1, ep = e + 1;
+    const uint32_t wprev = (w0 + W - 1) % W, wnext = (w0 + V) % W;
+    const size_t plane_words = (size_t)L * W;
+    auto off = [&](uint32_t z) -> size_t { return (size_t)z * plane_words + (size_t)y * W + w0; };
+
+    // register rings, named by plane relative to the step's plane q
+    uint32_t c1m[V], c1c[V], c1p[V], pf1[V];   // old colour 1: q-1, q, q+1; prefetch q+2
+    uint32_t c0o[V], pf0[V];                   // old colour 0: q; prefetch q+1
+    uint32_t n0a[V], n0b[V], n0n[V];           // colour 0 after sweep t: q-1, q-2; new q
+    uint32_t n1a[V], n1b[V], n1n[V];           // colour 1 after sweep t: q-2, q-3; new q-1
+    uint32_t m0a[V], m0b[V], m0n[V];           // colour 0 after sweep t+1: q-3, q-4; new q-2
+    uint32_t m1n[V];                           // colour 1 after sweep t+1: new q-3
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        c1m[v] = c1c[v] = c1p[v] = pf1[v] = c0o[v] = pf0[v] = 0u;
+        n0a[v] = n0b[v] = n0n[v] = n1a[v] = n1b[v] = n1n[v] = 0u;
+        m0a[v] = m0b[v] = m0n[v] = m1n[v] = 0u;
+    }
+    if (held) {
+        load_words<V>(A.S1 + off((z0 + L - 4) % L), c1m);
+        load_words<V>(A.S1 + off((z0 + L - 3) % L), c1c);
+        load_words<V>(A.S1 + off((z0 + L - 2) % L), c1p);
+    }
+    if (rowA)
+        load_words<V>(A.S0 + off((z0 + L - 3) % L), c0o);
+
+    int bonds_a = 0, bonds_c = 0;
+    const size_t set = (size_t)E * W;   // words of one row set in LDS
+
+    for (int qi = -3; qi <= (int)Tza + 2; ++qi) {
+        const uint32_t zq = (z0 + 2 * L + qi) % L;
+        if (qi < (int)Tza + 2) {
+            if (held)
+                load_words<V>(A.S1 + off((zq + 2) % L), pf1);
+            if (rowA)
+                load_words<V>(A.S0 + off((zq + 1) % L), pf0);
+        }
+        uint32_t *X1 = lds + (size_t)(qi & 1) * 4 * set;   // old colour 1, plane q
+        uint32_t *X0 = X1 + set;                            // A's colour 0, plane q-1
+        uint32_t *Y1 = X0 + set;                            // B's colour 1, plane q-2
+        uint32_t *Y0 = Y1 + set;                            // C's colour 0, plane q-3
+        if (held) {
+            store_words<V>(X1 + e * W + w0, c1c);
+            store_words<V>(X0 + e * W + w0, n0a);
+            store_words<V>(Y1 + e * W + w0, n1a);
+            store_words<V>(Y0 + e * W + w0, m0a);
+        }
+        __syncthreads();
+
+        // all four stages update sites with the same x parity in this row
+        const uint32_t pi = (y + zq) & 1u;
+        const uint32_t wadj = pi == 0u ? wprev : wnext;
+        // A: sweep t, colour 0, plane q
+        if (rowA) {
+            uint32_t ym[V], yp[V];
+            load_words<V>(X1 + em * W + w0, ym);
+            load_words<V>(X1 + ep * W + w0, yp);
+            const uint32_t adj = X1[e * W + wadj];
+            const uint32_t g = (uint32_t)(((size_t)zq * L + y) * W + w0);
+            int a_sum = 0;
+            update_words<V, CA>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, A.k0, A.k1, g, g & 3u, A.t,
+                                0u, n0n, a_sum);
+            if constexpr (CA)
+                if (rowD && qi >= 0 && qi < (int)Tza)
+                    bonds_a += a_sum;
+        }
+        // B: sweep t, colour 1, plane q-1
+        if (rowB && qi >= -1) {
+            const uint32_t zb = (zq + L - 1) % L;
+            uint32_t ym[V], yp[V];
+            load_words<V>(X0 + em * W + w0, ym);
+            load_words<V>(X0 + ep * W + w0, yp);
+            const uint32_t adj = X0[e * W + wadj];
+            const uint32_t g = (uint32_t)(((size_t)zb * L + y) * W + w0);
+            int unused = 0;
+            update_words<V, false>(c1m, n0a, adj, pi, ym, yp, n0b, n0n, A.k0, A.k1, g, g & 3u,
+                                   A.t, 1u, n1n, unused);
+        }
+        // C: sweep t+1, colour 0, plane q-2
+        if (rowC && qi >= 1) {
+            const uint32_t zc = (zq + L - 2) % L;
+            uint32_t ym[V], yp[V];
+            load_words<V>(Y1 + em * W + w0, ym);
+            load_words<V>(Y1 + ep * W + w0, yp);
+            const uint32_t adj = Y1[e * W + wadj];
+            const uint32_t g = (uint32_t)(((size_t)zc * L + y) * W + w0);
+            int a_sum = 0;
+            update_words<V, CC>(n0b, n1a, adj, pi, ym, yp, n1b, n1n, A.k0, A.k1, g, g & 3u,
+                                A.t + 1u, 0u, m0n, a_sum);
+            if (rowD && qi >= 2 && qi < (int)Tza + 2) {
+                if constexpr (CC)
+                    bonds_c += a_sum;
+                store_words_nt<V>(A.D0 + off(zc), m0n);
+            }
+        }
+        // D: sweep t+1, colour 1, plane q-3
+        if (rowD && qi >= 3) {
+            const uint32_t zd = (zq + L - 3) % L;
+            uint32_t ym[V], yp[V];
+            load_words<V>(Y0 + em * W + w0, ym);
+            load_words<V>(Y0 + ep * W + w0, yp);
+            const uint32_t adj = Y0[e * W + wadj];
+            const uint32_t g = (uint32_t)(((size_t)zd * L + y) * W + w0);
+            int unused = 0;
+            update_words<V, false>(n1b, m0a, adj, pi, ym, yp, m0b, m0n, A.k0, A.k1, g, g & 3u,
+                                   A.t + 1u, 1u, m1n, unused);
+            store_words_nt<V>(A.D1 + off(zd), m1n);
+        }
+        // advance the rings by one plane
+        copy_words<V>(c1m, c1c);
+        copy_words<V>(c1c, c1p);
+        copy_words<V>(c1p, pf1);
+        copy_words<V>(c0o, pf0);
+        copy_words<V>(n0b, n0a);
+        copy_words<V>(n0a, n0n);
+        copy_words<V>(n1b, n1a);
+        copy_words<V>(n1a, n1n);
+        copy_words<V>(m0b, m0a);
+        copy_words<V>(m0a, m0n);
+    }
+
+    if constexpr (CA || CC) {
+        __shared__ unsigned long long part[2][16];
+        const unsigned long long wa = wave_sum_u64((unsigned long long)bonds_a);
+        const unsigned long long wc = wave_sum_u64((unsigned long long)bonds_c);
+        const uint32_t nw = (blockDim.x + 63) / 64;
+        if ((tid & 63) == 0) {
+            part[0][tid >> 6] = wa;
+            part[1][tid >> 6] = wc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long ta = 0, tc = 0;
+            for (uint32_t k = 0; k < nw; ++k) {
+                ta += part[0][k];
+                tc += part[1][k];
+            }
+            if constexpr (CA)
+                atomicAdd(A.acc_a, ta);
+            if constexpr (CC)
+                atomicAdd(A.acc_c, tc);
+        }
+    }
+}
+
+template <int V>
+void launch2(hipStream_t st, const Sweep2Args &a, dim3 grid, dim3 block, size_t lds)
+{
+    const bool ca = a.acc_a != nullptr, cc = a.acc_c != nullptr;
+    if (ca && cc) {
+        hipLaunchKernelGGL((k_bit_sweep2<V, true, true>), grid, block, lds, st, a);
+    } else if (ca) {
+        hipLaunchKernelGGL((k_bit_sweep2<V, true, false>), grid, block, lds, st, a);
+    } else if (cc) {
+        hipLaunchKernelGGL((k_bit_sweep2<V, false, true>), grid, block, lds, st, a);
+    } else {
+        hipLaunchKernelGGL((k_bit_sweep2<V, false, false>), grid, block, lds, st, a);
+    }
+}
+
+}  // namespace
+
+bool bit_tuning2_valid(uint32_t L, const BitTuning &t)
+{
+    if (L < 64 || L % 64)
+        return false;
+    const uint32_t W = L / 64;
+    if (t.V != 1 && t.V != 2 && t.V != 4)
+        return false;
+    if (W % (uint32_t)t.V)
+        return false;
+    if (t.Tz < 1 || (uint32_t)t.Tz > L || t.Ty < 1 || (uint32_t)t.Ty > L)
+        return false;
+    const uint32_t R = W / t.V;
+    const uint32_t E = (uint32_t)t.Ty + 8;
+    const uint32_t threads = ((E * R + 63) / 64) * 64;
+    if (threads > 1024)
+        return false;
+    const size_t lds = (size_t)2 * 4 * E * W * 4;
+    return lds <= 60 * 1024;
+}
+
+BitTuning bit_tuning2_default(uint32_t L)
+{
+    const uint32_t W = L / 64;
+    BitTuning t;
+    t.V = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
+    const uint32_t R = W / t.V;
+    uint32_t E = 16;
+    while (E * 2 * R <= 256 && (size_t)2 * 4 * (E * 2) * W * 4 <= 60 * 1024)
+        E *= 2;
+    t.Ty = (int)std::min<uint32_t>(E - 8, L);
+    t.Tz = (int)std::min<uint32_t>(32, L);
+    return t;
+}
+
+hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
+                      const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
+                      unsigned long long *acc_a, unsigned long long *acc_c)
+{
+    if (!bit_tuning2_valid(L, tu))
+        return hipErrorInvalidValue;
+    Sweep2Args a;
+    a.S0 = S0; a.S1 = S1; a.D0 = D0; a.D1 = D1;
+    a.acc_a = acc_a;
+    a.acc_c = acc_c;
+    a.L = L;
+    a.W = L / 64;
+    a.R = a.W / tu.V;
+    a.Ty = (uint32_t)tu.Ty;
+    a.E = a.Ty + 8;
+    a.Tz = (uint32_t)tu.Tz;
+    a.nty = (L + a.Ty - 1) / a.Ty;
+    const uint32_t ntz = (L + a.Tz - 1) / a.Tz;
+    a.k0 = (uint32_t)seed;
+    a.k1 = (uint32_t)(seed >> 32);
+    a.t = t;
+    const uint32_t threads = ((a.E * a.R + 63) / 64) * 64;
+    const size_t lds = (size_t)2 * 4 * a.E * a.W * 4;
+    const dim3 grid(a.nty * ntz), block(threads);
+    switch (tu.V) {
+    case 4: launch2<4>(st, a, grid, block, lds); break;
+    case 2: launch2<2>(st, a, grid, block, lds); break;
+    default: launch2<1>(st, a, grid, block, lds); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qz

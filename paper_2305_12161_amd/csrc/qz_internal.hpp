@@ -33,6 +33,9 @@ struct BitTuning {
 };
 bool bit_tuning_valid(uint32_t L, const BitTuning &t);
 BitTuning bit_tuning_default(uint32_t L);
+// Tuning of the two-sweep pass (qz_bit2.hip): Ty owned rows, E = Ty + 8 held.
+bool bit_tuning2_valid(uint32_t L, const BitTuning &t);
+BitTuning bit_tuning2_default(uint32_t L);
 
 // ----- int8 layout -----
 hipError_t i8_init(hipStream_t st, uint32_t L, uint64_t seed, int8_t *s);
@@ -50,6 +53,11 @@ hipError_t bit_init(hipStream_t st, uint32_t L, uint64_t seed, uint32_t *P0, uin
 hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                      const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
                      unsigned long long *bond_acc, bool mixed);
+// Sweeps t and t+1 of the 01 cycle in one pass (copy S -> copy D); acc_a /
+// acc_c (nullable) receive the bond counts of the states entering them.
+hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
+                      const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
+                      unsigned long long *acc_a, unsigned long long *acc_c);
 hipError_t bit_bonds(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
                      unsigned long long *acc3);
 hipError_t bit_bonds_total(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,

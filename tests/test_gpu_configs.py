@@ -111,6 +111,28 @@ def test_config3_window_replays_L2048(qz, orc):
     assert lat_t == 218 and int(tr[0]) >= int(B.sum())  # energy never rises
 
 
+def test_config3_two_sweep_pass_L2048(qz, orc):
+    """L=2048, seed 3, with two sweeps per pass: identical to the one-sweep pass
+    (bond trace and state), and replayed windows against the oracle."""
+    c = wl.CONFIG3
+    one = qz.Lattice(c.L, c.seed, "bit")
+    two = qz.Lattice(c.L, c.seed, "bit")
+    two.set_pass(2)
+    print("config3 two-sweep", two.pass_config(), flush=True)
+    tr1 = one.run(24, 3)
+    tr2 = two.run(24, 3)
+    assert np.array_equal(tr1, tr2)
+    for o in ((0, 0, 0), (1500, 7, 2040), (2047, 1023, 511)):
+        assert np.array_equal(one.window(o, 64), two.window(o, 64))
+    del one
+    rng = np.random.default_rng(33)
+    o = [int(v) for v in rng.integers(0, c.L, size=3)]
+    print("config3 two-sweep replay", o, flush=True)
+    assert replay(orc, two, c.L, c.seed, o, 128 + 4 * 10, 10)
+    S, M = two.corr()
+    check_identities(two, S, M, c.L ** 3)
+
+
 def test_same_tuning_full_run_L256(qz, orc):
     """The L=2048 kernel configuration (V=4, Ty=28, Tz=32) on a full L=256 run."""
     L, seed, n = 256, 3, 60

@@ -113,6 +113,67 @@ def test_bit_tunings_match_oracle(qz, orc, L):
         assert np.array_equal(lat.download(), s), (V, Ty, Tz)
 
 
+# (V, Ty, Tz) of the two-sweep pass: ragged y and z tiles, one-plane tiles,
+# tiles whose held rows wrap past L
+TUNINGS2 = {
+    64: [(1, 24, 64), (1, 8, 5), (1, 56, 7), (1, 64, 3)],
+    128: [(2, 24, 11), (1, 56, 128), (2, 120, 6), (2, 8, 1)],
+    192: [(1, 24, 20), (1, 56, 7)],
+    256: [(4, 24, 32), (2, 56, 10), (4, 24, 256), (4, 8, 9)],
+}
+
+
+@pytest.mark.parametrize("L", sorted(TUNINGS2))
+def test_two_sweep_pass_matches_oracle(qz, orc, L):
+    """Two sweeps per pass: same trajectory and bond trace (every sweep traced,
+    so both counters of a pass are used; an odd count ends with one sweep)."""
+    seed = 500 + L
+    n = 7
+    s, want = oracle_run(orc, L, seed, n, 1)
+    for V, Ty, Tz in [(0, 0, 0)] + TUNINGS2[L]:
+        say("two-sweep pass", L, (V, Ty, Tz))
+        lat = qz.Lattice(L, seed, "bit")
+        lat.set_pass(2, V, Ty, Tz)
+        assert lat.pass_config()[0] == 2
+        tr = lat.run(n, 1)
+        assert np.array_equal(tr.astype(np.int64), want), (V, Ty, Tz)
+        assert np.array_equal(lat.download(), s), (V, Ty, Tz)
+
+
+@pytest.mark.parametrize("every,n", [(2, 8), (3, 9), (5, 10)])
+def test_two_sweep_pass_trace_alignment(qz, orc, every, n):
+    """Start at an odd time from an uploaded state: pairs straddle the traced
+    sweeps, so a pass carries the count in its first sweep, its second, or none."""
+    L, seed, t0 = 128, 61, 5
+    s = wl.random_state(L, 9)
+    lat = qz.Lattice(L, seed, "bit")
+    lat.upload(s, t0)
+    lat.set_pass(2)
+    say("two-sweep alignment", every, n)
+    tr = lat.run(n, every)
+    want = orc.run(s, seed, t0, n, every)
+    assert np.array_equal(tr.astype(np.int64), want)
+    assert np.array_equal(lat.download(), s)
+    assert lat.t == t0 + n
+
+
+def test_two_sweep_pass_falls_back_and_rejects(qz, orc):
+    L, seed = 64, 8
+    lat = qz.Lattice(L, seed, "bit")
+    lat.set_pass(2)
+    lat.set_cycle(True)        # the mixed cycle runs one sweep per pass
+    tr = lat.run(5, 1)
+    s = orc.init(L, seed)
+    want = orc.run(s, seed, 0, 5, 1, mixed=True)
+    assert np.array_equal(tr.astype(np.int64), want)
+    assert np.array_equal(lat.download(), s)
+    for bad in ((3, 0, 0, 0), (0, 0, 0, 0), (2, 3, 24, 8), (2, 1, 2000, 8), (2, 1, 24, 0)):
+        with pytest.raises(qz.QuenchError):
+            lat.set_pass(*bad)
+    with pytest.raises(qz.QuenchError):
+        qz.Lattice(16, 1, "i8").set_pass(2)
+
+
 @pytest.mark.parametrize("L", [64, 128])
 def test_bit_equals_i8(qz, L):
     seed = 5 + L
