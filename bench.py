@@ -29,7 +29,8 @@ if ROOT not in sys.path:
 METRIC = "spin-flip attempts/ns + % HBM roofline at L=2048; batched vs plain flips/ns"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_bit_L2048.json")
-KERNEL_SOURCES = ["paper_2305_12161_amd/csrc/qz_bit.hip", "paper_2305_12161_amd/csrc/qz_device.hpp"]
+KERNEL_SOURCES = ["paper_2305_12161_amd/csrc/qz_bit.hip", "paper_2305_12161_amd/csrc/qz_bit2.hip",
+                  "paper_2305_12161_amd/csrc/qz_bitops.hpp", "paper_2305_12161_amd/csrc/qz_device.hpp"]
 
 
 def kernel_sha() -> str:
