@@ -28,7 +28,9 @@ if ROOT not in sys.path:
 
 METRIC = "spin-flip attempts/ns + % HBM roofline at L=2048; batched vs plain flips/ns"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_bit_L2048.json")
+# HBM bytes per launch from rocprofv3 counters, per kernel (one or two sweeps per launch)
+TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "traffic_sweep_bit_L2048.json"),
+                 2: os.path.join(ROOT, "profiles", "traffic_sweep2_bit_L2048.json")}
 KERNEL_SOURCES = ["paper_2305_12161_amd/csrc/qz_bit.hip", "paper_2305_12161_amd/csrc/qz_bit2.hip",
                   "paper_2305_12161_amd/csrc/qz_bitops.hpp", "paper_2305_12161_amd/csrc/qz_device.hpp"]
 
@@ -48,7 +50,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--L", type=int, default=2048)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--tuning", type=str, default="", help="V,Ty,Tz for the sweep kernel")
+    ap.add_argument("--tuning", type=str, default="", help="V,Ty,Tz for the one-sweep kernel")
+    ap.add_argument("--pass", dest="sweeps_per_pass", type=int, default=0,
+                    help="sweeps per pass over memory (1 or 2; 0 = the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-corr", action="store_true", help="skip the correlation measurements")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-replica workload")
@@ -87,6 +91,21 @@ def batched_workload(binding, torch, workloads):
     wall = time.perf_counter() - t0
     sites = sum(L ** 3 for L, _ in specs)
     rate = sites * t_max / (wall * 1e9)
+    # the batch's 2 x sites/8 bytes of spins fit in the last-level cache: price
+    # it against a device copy of the same footprint rather than HBM
+    foot = 2 * sites // 8
+    src = torch.ones(foot // 2, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    reps = 200
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    copy_gbs = foot * reps / ((time.perf_counter() - c0) * 1e9)
+    del src, dst
     # the plain single-lattice kernel on one lattice of each size, for comparison
     plain = {L: plain_rate(binding, torch, L, 400) for L in sorted({L for L, _ in specs})}
     plain_wall = sum(L ** 3 * t_max / (plain[L] * 1e9) for L, _ in specs)
@@ -98,6 +117,9 @@ def batched_workload(binding, torch, workloads):
         "plain_one_lattice_attempts_per_ns": {str(L): round(v, 2) for L, v in plain.items()},
         "plain_sequential_wall_s": round(plain_wall, 3),
         "batched_over_plain": round(plain_wall / wall, 2),
+        "alg_GBs": round(sites / 4 * t_max / (wall * 1e9), 1),
+        "copy_same_footprint_GBs": round(copy_gbs, 1),
+        "footprint_MiB": round(foot / 2 ** 20, 1),
         "trace_points_per_replica": t_max // 10,
     }
 
@@ -168,7 +190,11 @@ def main():
     lat = binding.Lattice(L, seed, "bit", stream=stream)
     if args.tuning:
         lat.set_tuning(*[int(v) for v in args.tuning.split(",")])
+    if args.sweeps_per_pass:
+        lat.set_pass(args.sweeps_per_pass)
     tune = lat.tuning()
+    pcfg = lat.pass_config()
+    per_launch = pcfg[0]   # sweeps carried by one launch of the dominant kernel
     ntrace = (W + K) // every + 2
     trace = torch.zeros(ntrace, dtype=torch.int64, device="cuda")
     print(f"# L={L} seed={seed} tuning={tune} warmup={W} steps={K} corr_times={len(corr_times)}",
@@ -189,7 +215,7 @@ def main():
                 lat.run_device(n, ev, sl)
                 if timing is not None:
                     b.record(stream)
-                    timing.append((a, b, n))
+                    timing.append((a, b, n, t))
             else:
                 n = min(t_to - t, every - t % every)
                 lat.run_device(n, 0, None)
@@ -218,16 +244,25 @@ def main():
     wall = time.perf_counter() - t0
     assert lat.t == W + K
 
-    sweep_ms = sum(a.elapsed_time(b) for a, b, _ in timing)
-    n_timed = sum(n for _, _, n in timing)
+    sweep_ms = sum(a.elapsed_time(b) for a, b, _, _ in timing)
+    n_timed = sum(n for _, _, n, _ in timing)
     avg_sweep_s = sweep_ms / 1e3 / max(1, n_timed)
+    # the same average over the late part of the run only (t >= 1e4), where few
+    # sites tie and the kernel is furthest from the ALU side
+    late = [(a, b, n) for a, b, n, t_start in timing if t_start >= 10_000]
+    late_s = (sum(a.elapsed_time(b) for a, b, _ in late) / 1e3 / sum(n for _, _, n in late)
+              if late else None)
     value = N * K / (wall * 1e9)
-    alg_bytes = N // 4
-    achieved = alg_bytes / avg_sweep_s / 1e9
+    # algorithmic bytes: N/4 per sweep (each 1-bit spin read once and written
+    # once); a launch of the two-sweep kernel carries two sweeps
+    alg_bytes = per_launch * (N // 4)
+    launch_s = per_launch * avg_sweep_s
+    achieved = alg_bytes / launch_s / 1e9
 
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
+    tfile = TRAFFIC_FILES.get(per_launch)
+    if tfile and os.path.exists(tfile):
+        with open(tfile) as f:
             tr = json.load(f)
         if tr.get("kernel_sha") == kernel_sha() and tr.get("L") == L:
             traffic = tr.get("bytes_per_launch")
@@ -253,7 +288,8 @@ def main():
                         f"unsatisfied-bond count every {every} MCS, axis C(r<=L/2) at the "
                         f"{len(corr_times)} of 40 log-spaced times in the timed window",
             "L": L, "layout": "bit", "seed": seed, "t_window": [W, W + K],
-            "tuning_V_Ty_Tz": list(tune), "parallelism": "single GPU",
+            "tuning_V_Ty_Tz": list(tune), "sweeps_per_pass": pcfg[0],
+            "pass2_tuning_V_Ty_Tz": list(pcfg[1:]), "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm",
@@ -262,9 +298,15 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_bit_sweep (fused two-colour sweep, bond count fused)",
+            "kernel": ("k_bit_sweep2 (two fused two-colour sweeps per pass, bond count fused)"
+                       if per_launch == 2 else
+                       "k_bit_sweep (fused two-colour sweep, bond count fused)"),
+            "sweeps_per_launch": per_launch,
             "alg_bytes_per_launch": alg_bytes,
-            "avg_launch_ms": round(avg_sweep_s * 1e3, 5),
+            "avg_launch_ms": round(launch_s * 1e3, 5),
+            "frac_t_ge_1e4": (round((N // 4) / late_s / 1e9 / HBM_PEAK_GBS, 4)
+                              if late_s else None),
+            "avg_ms_per_sweep_t_ge_1e4": round(late_s * 1e3, 5) if late_s else None,
         },
         "sweep_only_attempts_per_ns": round(N / avg_sweep_s / 1e9, 2),
         "corr_ms_mean": round(sum(corr_ms) / len(corr_ms), 3) if corr_ms else None,
