@@ -111,6 +111,17 @@ int qz_run(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64_t *hos
  * never synchronises. */
 int qz_run_device(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64_t *dev_trace);
 
+/* As qz_run / qz_run_device, with a second trace: flips[k] receives the number
+ * of spins that sweep t0 + k*trace_every flipped (accepted moves, the physics
+ * output beside the attempts; each site is proposed once per sweep, Methods
+ * "Checkerboard update", so this is also the Hamming distance between the
+ * states before and after that sweep).  B or flips may be null (not both when
+ * trace_every > 0).  The batch engine does not trace flips. */
+int qz_run_traced(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64_t *host_B,
+                  uint64_t *host_flips);
+int qz_run_device_traced(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64_t *dev_B,
+                         uint64_t *dev_flips);
+
 /* Per-axis unsatisfied-bond counts [B_x, B_y, B_z] of the current state. */
 int qz_bonds(qz_lattice *q, uint64_t out_B_axes[3]);
 

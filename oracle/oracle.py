@@ -181,6 +181,31 @@ def run(s: np.ndarray, seed: int, t0: int, n: int, every: int = 0,
     return tr
 
 
+def run_traced(s: np.ndarray, seed: int, t0: int, n: int, every: int, mixed: bool = False,
+               double_B: int = 0):
+    """n sweeps in place from t0; at every `every`-th sweep record the bond count
+    of the state entering it and the number of sites it flips.  double_B > 0
+    runs the double checkerboard with cubes of that side."""
+    L = s.shape[0]
+    _check_L(L)
+    lib = _load()
+    B, F = [], []
+    for k in range(n):
+        t = t0 + k
+        traced = every > 0 and k % every == 0
+        if traced:
+            B.append(int(bonds(s).sum()))
+        if double_B:
+            f = sweep_double(s, double_B, seed, t, mixed)
+        elif mixed:
+            f = int(lib.or_sweep_mixed(L, seed, t, _i8(s)))
+        else:
+            f = int(lib.or_sweep(L, seed, t, _i8(s)))
+        if traced:
+            F.append(f)
+    return np.array(B, dtype=np.int64), np.array(F, dtype=np.int64)
+
+
 def first_colour(seed: int, t: int) -> int:
     """Mixed cycle: the colour updated first in sweep t."""
     return int(_load().or_first_colour(seed, t))

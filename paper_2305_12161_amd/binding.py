@@ -36,6 +36,8 @@ def _load():
         "qz_destroy": ([vp], i32),
         "qz_run": ([vp, u64, u64, c.POINTER(u64)], i32),
         "qz_run_device": ([vp, u64, u64, vp], i32),
+        "qz_run_traced": ([vp, u64, u64, c.POINTER(u64), c.POINTER(u64)], i32),
+        "qz_run_device_traced": ([vp, u64, u64, vp, vp], i32),
         "qz_bonds": ([vp, c.POINTER(u64)], i32),
         "qz_corr": ([vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64)], i32),
         "qz_time": ([vp, c.POINTER(u64)], i32),
@@ -135,6 +137,23 @@ class Lattice:
         """Asynchronous run; dev_trace is a torch int64/uint64 device tensor."""
         ptr = ctypes.c_void_p(dev_trace.data_ptr()) if dev_trace is not None else None
         _check(lib.qz_run_device(self._h, n, trace_every, ptr))
+
+    def run_traced(self, n: int, trace_every: int):
+        """Run n sweeps; returns (B, flips) at every trace_every-th sweep: the bond
+        count entering the sweep and the number of spins it flipped."""
+        if trace_every <= 0:
+            raise ValueError("trace_every must be positive")
+        B = np.zeros(n // trace_every, dtype=np.uint64)
+        F = np.zeros(n // trace_every, dtype=np.uint64)
+        P = ctypes.POINTER(ctypes.c_uint64)
+        _check(lib.qz_run_traced(self._h, n, trace_every, B.ctypes.data_as(P), F.ctypes.data_as(P)))
+        return B.astype(np.int64), F.astype(np.int64)
+
+    def run_device_traced(self, n: int, trace_every: int, dev_B, dev_flips) -> None:
+        """Asynchronous run with device traces of B and of the accepted flips."""
+        pb = ctypes.c_void_p(dev_B.data_ptr()) if dev_B is not None else None
+        pf = ctypes.c_void_p(dev_flips.data_ptr()) if dev_flips is not None else None
+        _check(lib.qz_run_device_traced(self._h, n, trace_every, pb, pf))
 
     def bonds(self) -> np.ndarray:
         out = np.zeros(3, dtype=np.uint64)

@@ -101,26 +101,29 @@ int check_handle(qz_lattice *q)
     return QZ_OK;
 }
 
-// One sweep of the current state; bond_acc (device, may be null) receives the
-// bond count of the state entering the sweep.
-int sweep_once(qz_lattice *q, unsigned long long *bond_acc)
+// One sweep of the current state; bond_acc / flip_acc (device, may be null)
+// receive the bond count of the state entering the sweep and the number of
+// spins the sweep flips.
+int sweep_once(qz_lattice *q, unsigned long long *bond_acc, unsigned long long *flip_acc)
 {
     const uint32_t t = (uint32_t)q->t;
     if (q->layout == QZ_LAYOUT_I8) {
-        QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 0, q->mixed, i8_spins(q), bond_acc));
-        QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 1, q->mixed, i8_spins(q), nullptr));
+        QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 0, q->mixed, i8_spins(q), bond_acc,
+                                    flip_acc));
+        QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 1, q->mixed, i8_spins(q), nullptr,
+                                    flip_acc));
     } else if (q->dcb > 0) {
         const int c = q->cur;
         if (bond_acc)
             QZ_HIP(q, qz::bit_bonds_total(q->st, q->L, bit_plane(q, c, 0), bit_plane(q, c, 1),
                                           bond_acc));
         QZ_HIP(q, qz::bit_double_sweep(q->st, q->L, q->dcb, q->seed, t, bit_plane(q, c, 0),
-                                       bit_plane(q, c, 1), q->mixed));
+                                       bit_plane(q, c, 1), q->mixed, flip_acc));
     } else {
         const int a = q->cur, b = 1 - q->cur;
         QZ_HIP(q, qz::bit_sweep(q->st, q->L, q->seed, t, q->tune, bit_plane(q, a, 0),
                                 bit_plane(q, a, 1), bit_plane(q, b, 0), bit_plane(q, b, 1),
-                                bond_acc, q->mixed));
+                                bond_acc, q->mixed, flip_acc));
         q->cur = b;
     }
     q->t += 1;
@@ -128,31 +131,36 @@ int sweep_once(qz_lattice *q, unsigned long long *bond_acc)
 }
 
 // Sweeps t and t+1 in one pass (bit layout, plain checkerboard, 01 cycle).
-int sweep_pair(qz_lattice *q, unsigned long long *acc_a, unsigned long long *acc_c)
+int sweep_pair(qz_lattice *q, unsigned long long *acc_a, unsigned long long *acc_c,
+               unsigned long long *flip_a, unsigned long long *flip_c)
 {
     const int a = q->cur, b = 1 - q->cur;
     QZ_HIP(q, qz::bit_sweep2(q->st, q->L, q->seed, (uint32_t)q->t, q->tune2, bit_plane(q, a, 0),
                              bit_plane(q, a, 1), bit_plane(q, b, 0), bit_plane(q, b, 1), acc_a,
-                             acc_c));
+                             acc_c, flip_a, flip_c));
     q->cur = b;
     q->t += 2;
     return QZ_OK;
 }
 
-int run_impl(qz_lattice *q, uint64_t n, uint64_t every, unsigned long long *dev_trace)
+// n sweeps; with every > 0, sweep k (k % every == 0) adds its entering bond
+// count to dev_trace[k / every] and its accepted flips to dev_flips[k / every]
+// (either pointer may be null).
+int run_impl(qz_lattice *q, uint64_t n, uint64_t every, unsigned long long *dev_trace,
+             unsigned long long *dev_flips)
 {
     const bool pairs = q->pass == 2 && q->layout == QZ_LAYOUT_BIT && !q->mixed && q->dcb == 0;
-    auto acc_at = [&](uint64_t k) -> unsigned long long * {
-        return (every > 0 && dev_trace != nullptr && k % every == 0) ? dev_trace + k / every
-                                                                      : nullptr;
+    auto slot = [&](unsigned long long *base, uint64_t k) -> unsigned long long * {
+        return (every > 0 && base != nullptr && k % every == 0) ? base + k / every : nullptr;
     };
     for (uint64_t k = 0; k < n;) {
         int rc;
         if (pairs && n - k >= 2) {
-            rc = sweep_pair(q, acc_at(k), acc_at(k + 1));
+            rc = sweep_pair(q, slot(dev_trace, k), slot(dev_trace, k + 1), slot(dev_flips, k),
+                            slot(dev_flips, k + 1));
             k += 2;
         } else {
-            rc = sweep_once(q, acc_at(k));
+            rc = sweep_once(q, slot(dev_trace, k), slot(dev_flips, k));
             k += 1;
         }
         if (rc != QZ_OK)
@@ -180,6 +188,8 @@ bool state_map(uint32_t L, int layout, StateMap *m)
     m->corr_off = off;
     off = align256(off + (size_t)(3 * (L / 2 + 1) + 1) * 8);
     m->trace_off = off;
+    off = align256(off + kTraceCap * 8);
+    m->flips_off = off;
     off = align256(off + kTraceCap * 8);
     m->stage_off = off;
     m->stage_bytes = std::min<size_t>((size_t)N, kStageMax);
@@ -265,50 +275,80 @@ QZ_EXPORT int qz_destroy(qz_lattice *q)
     return QZ_OK;
 }
 
-QZ_EXPORT int qz_run(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64_t *host_trace)
+QZ_EXPORT int qz_run_traced(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every,
+                            uint64_t *host_B, uint64_t *host_flips)
 {
     int rc = check_handle(q);
     if (rc != QZ_OK)
         return rc;
     if (trace_every == 0)
-        return run_impl(q, n_sweeps, 0, nullptr);
-    if (!host_trace)
-        return fail(QZ_EINVAL, "null trace buffer");
+        return run_impl(q, n_sweeps, 0, nullptr, nullptr);
+    if (!host_B && !host_flips)
+        return fail(QZ_EINVAL, "null trace buffers");
     if (n_sweeps % trace_every)
         return fail(QZ_EINVAL, "n_sweeps must be a multiple of trace_every");
     unsigned long long *slots =
         reinterpret_cast<unsigned long long *>(q->base + q->map.trace_off);
+    unsigned long long *fslots =
+        reinterpret_cast<unsigned long long *>(q->base + q->map.flips_off);
     const uint64_t points = n_sweeps / trace_every;
     uint64_t done = 0;
     while (done < points) {
         const uint64_t chunk = std::min<uint64_t>(points - done, qz::kTraceCap);
-        QZ_HIP(q, qz::fill_u64(q->st, slots, chunk, 0ull));
-        rc = run_impl(q, chunk * trace_every, trace_every, slots);
+        if (host_B)
+            QZ_HIP(q, qz::fill_u64(q->st, slots, chunk, 0ull));
+        if (host_flips)
+            QZ_HIP(q, qz::fill_u64(q->st, fslots, chunk, 0ull));
+        rc = run_impl(q, chunk * trace_every, trace_every, host_B ? slots : nullptr,
+                      host_flips ? fslots : nullptr);
         if (rc != QZ_OK)
             return rc;
-        QZ_HIP(q, hipMemcpyAsync(host_trace + done, slots, chunk * 8, hipMemcpyDeviceToHost,
-                                 q->st));
+        if (host_B)
+            QZ_HIP(q, hipMemcpyAsync(host_B + done, slots, chunk * 8, hipMemcpyDeviceToHost,
+                                     q->st));
+        if (host_flips)
+            QZ_HIP(q, hipMemcpyAsync(host_flips + done, fslots, chunk * 8,
+                                     hipMemcpyDeviceToHost, q->st));
         QZ_HIP(q, hipStreamSynchronize(q->st));
         done += chunk;
     }
     return QZ_OK;
 }
 
-QZ_EXPORT int qz_run_device(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every,
-                            uint64_t *dev_trace)
+QZ_EXPORT int qz_run(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64_t *host_trace)
+{
+    if (q && trace_every > 0 && !host_trace)
+        return fail(QZ_EINVAL, "null trace buffer");
+    return qz_run_traced(q, n_sweeps, trace_every, host_trace, nullptr);
+}
+
+QZ_EXPORT int qz_run_device_traced(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every,
+                                   uint64_t *dev_B, uint64_t *dev_flips)
 {
     int rc = check_handle(q);
     if (rc != QZ_OK)
         return rc;
     if (trace_every == 0)
-        return run_impl(q, n_sweeps, 0, nullptr);
-    if (!dev_trace)
-        return fail(QZ_EINVAL, "null trace buffer");
+        return run_impl(q, n_sweeps, 0, nullptr, nullptr);
+    if (!dev_B && !dev_flips)
+        return fail(QZ_EINVAL, "null trace buffers");
     if (n_sweeps % trace_every)
         return fail(QZ_EINVAL, "n_sweeps must be a multiple of trace_every");
-    unsigned long long *slots = reinterpret_cast<unsigned long long *>(dev_trace);
-    QZ_HIP(q, qz::fill_u64(q->st, slots, n_sweeps / trace_every, 0ull));
-    return run_impl(q, n_sweeps, trace_every, slots);
+    unsigned long long *slots = reinterpret_cast<unsigned long long *>(dev_B);
+    unsigned long long *fslots = reinterpret_cast<unsigned long long *>(dev_flips);
+    if (slots)
+        QZ_HIP(q, qz::fill_u64(q->st, slots, n_sweeps / trace_every, 0ull));
+    if (fslots)
+        QZ_HIP(q, qz::fill_u64(q->st, fslots, n_sweeps / trace_every, 0ull));
+    return run_impl(q, n_sweeps, trace_every, slots, fslots);
+}
+
+QZ_EXPORT int qz_run_device(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every,
+                            uint64_t *dev_trace)
+{
+    if (q && trace_every > 0 && !dev_trace)
+        return fail(QZ_EINVAL, "null trace buffer");
+    return qz_run_device_traced(q, n_sweeps, trace_every, dev_trace, nullptr);
 }
 
 QZ_EXPORT int qz_bonds(qz_lattice *q, uint64_t out_B_axes[3])

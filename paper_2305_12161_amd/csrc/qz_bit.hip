@@ -35,6 +35,7 @@ struct SweepArgs {
     const uint32_t *S0, *S1;   // read copy, colour planes 0 and 1
     uint32_t *D0, *D1;         // write copy
     unsigned long long *bond_acc;
+    unsigned long long *flip_acc;   // accepted flips of this sweep (COUNT only, nullable)
     uint32_t L, W, R;          // R = W / V lanes per row
     uint32_t Ty, E, Tz, nty;   // E = rows held per tile (Ty + 4, or L for whole planes)
     uint32_t whole;            // 1 when a tile is a whole plane (no y halo)
@@ -100,7 +101,8 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
     if (c0_row)
         load_words<V>(SF + off((z0 + L - 1) % L), c0o);
 
-    int bonds = 0;   // sum of a over owned colour-0 sites (COUNT only)
+    int bonds = 0;       // sum of a over owned colour-0 sites (COUNT only)
+    uint32_t flips = 0;  // accepted flips over owned sites (COUNT only)
 
     for (int qi = -1; qi <= (int)Tza; ++qi) {
         const uint32_t zq = (z0 + L + qi) % L;            // plane of this step
@@ -132,8 +134,12 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
             update_words<V, COUNT>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, A.k0, A.k1, g0, g0 & 3u,
                                    A.t, f, n0c, a_sum);
             if (mine) {
-                if constexpr (COUNT)
+                if constexpr (COUNT) {
                     bonds += a_sum;
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        flips = popc_acc(c0o[v] ^ n0c[v], flips);
+                }
                 store_words_nt<V>(DF + off(zq), n0c);
             }
         }
@@ -146,6 +152,11 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
             int unused = 0;
             update_words<V, false>(c1m, n0m1, adj, pi, ym, yp, n0m2, n0c, A.k0, A.k1, g1, g1 & 3u,
                                    A.t, 1u - f, c1n, unused);
+            if constexpr (COUNT) {
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    flips = popc_acc(c1m[v] ^ c1n[v], flips);
+            }
             store_words_nt<V>(DS + off(zm), c1n);
         }
 #pragma unroll
@@ -160,17 +171,25 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
     }
 
     if constexpr (COUNT) {
-        __shared__ unsigned long long part[16];
+        __shared__ unsigned long long part[2][16];
         const unsigned long long ws = wave_sum_u64((unsigned long long)bonds);
+        const unsigned long long wf = wave_sum_u64((unsigned long long)flips);
         const uint32_t nw = (blockDim.x + 63) / 64;
-        if ((tid & 63) == 0)
-            part[tid >> 6] = ws;
+        if ((tid & 63) == 0) {
+            part[0][tid >> 6] = ws;
+            part[1][tid >> 6] = wf;
+        }
         __syncthreads();
         if (tid == 0) {
-            unsigned long long tot = 0;
-            for (uint32_t k = 0; k < nw; ++k)
-                tot += part[k];
-            atomicAdd(A.bond_acc, tot);
+            unsigned long long tot = 0, ftot = 0;
+            for (uint32_t k = 0; k < nw; ++k) {
+                tot += part[0][k];
+                ftot += part[1][k];
+            }
+            if (A.bond_acc != nullptr)
+                atomicAdd(A.bond_acc, tot);
+            if (A.flip_acc != nullptr)
+                atomicAdd(A.flip_acc, ftot);
         }
     }
 }
@@ -217,8 +236,9 @@ __device__ __forceinline__ uint32_t cube_order_mask(uint32_t w, uint32_t y, uint
 __global__ void __launch_bounds__(256)
     k_bit_phase(uint32_t L, uint32_t W, uint32_t sB, uint32_t kc, uint32_t p, uint32_t k0,
                 uint32_t k1, uint32_t t, uint32_t *Pp, const uint32_t *Po, uint32_t mixed,
-                uint32_t step)
+                uint32_t step, unsigned long long *flip_acc)
 {
+    uint32_t flips = 0;
     const uint64_t nwords = (uint64_t)L * L * W;
     const size_t plane = (size_t)L * W;
     const uint32_t cc = mixed ? (kc ^ (philox10(0u, t, 3u, 0u, k0, k1).w[0] & 1u)) : kc;
@@ -260,6 +280,12 @@ __global__ void __launch_bounds__(256)
         }
         const uint32_t nw = up_rule(own, u, r);
         Pp[g] = (own & ~mask) | (nw & mask);
+        flips = popc_acc((own ^ nw) & mask, flips);
+    }
+    if (flip_acc != nullptr) {
+        const unsigned long long ws = wave_sum_u64((unsigned long long)flips);
+        if ((threadIdx.x & 63) == 0 && ws)
+            atomicAdd(flip_acc, ws);
     }
 }
 
@@ -485,13 +511,14 @@ hipError_t bit_init(hipStream_t st, uint32_t L, uint64_t seed, uint32_t *P0, uin
 
 hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                      const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
-                     unsigned long long *bond_acc, bool mixed)
+                     unsigned long long *bond_acc, bool mixed, unsigned long long *flip_acc)
 {
     if (!bit_tuning_valid(L, tu))
         return hipErrorInvalidValue;
     SweepArgs a;
     a.S0 = S0; a.S1 = S1; a.D0 = D0; a.D1 = D1;
     a.bond_acc = bond_acc;
+    a.flip_acc = flip_acc;
     a.L = L;
     a.W = L / 64;
     a.R = a.W / tu.V;
@@ -508,7 +535,7 @@ hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, cons
     const uint32_t threads = ((a.E * a.R + 63) / 64) * 64;
     const size_t lds = (size_t)2 * 2 * a.E * a.W * 4;
     const dim3 grid(a.nty * ntz), block(threads);
-    const bool count = bond_acc != nullptr;
+    const bool count = bond_acc != nullptr || flip_acc != nullptr;
     switch (tu.V * 2 + (count ? 1 : 0)) {
     case 9: hipLaunchKernelGGL((k_bit_sweep<4, true>), grid, block, lds, st, a); break;
     case 8: hipLaunchKernelGGL((k_bit_sweep<4, false>), grid, block, lds, st, a); break;
@@ -541,7 +568,7 @@ hipError_t bit_bonds_total(hipStream_t st, uint32_t L, const uint32_t *P0, const
 }
 
 hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
-                            uint32_t *P0, uint32_t *P1, bool mixed)
+                            uint32_t *P0, uint32_t *P1, bool mixed, unsigned long long *flip_acc)
 {
     uint32_t sB = 0;
     while ((1u << sB) < B)
@@ -558,7 +585,7 @@ hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t see
             for (uint32_t p = 0; p < 2; ++p) {
                 hipLaunchKernelGGL(k_bit_phase, dim3(grid_cap(nw, 8192)), dim3(256), 0, st, L, W,
                                    sB, kc, p, (uint32_t)seed, (uint32_t)(seed >> 32), t,
-                                   p ? P1 : P0, p ? P0 : P1, mixed ? 1u : 0u, step);
+                                   p ? P1 : P0, p ? P0 : P1, mixed ? 1u : 0u, step, flip_acc);
                 const hipError_t e = hipGetLastError();
                 if (e != hipSuccess)
                     return e;

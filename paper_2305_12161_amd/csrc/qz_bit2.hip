@@ -32,6 +32,7 @@ struct Sweep2Args {
     const uint32_t *S0, *S1;            // read copy, colour planes 0 and 1
     uint32_t *D0, *D1;                  // write copy
     unsigned long long *acc_a, *acc_c;  // bond counts entering sweeps t and t+1
+    unsigned long long *flip_a, *flip_c;  // accepted flips in sweeps t and t+1
     uint32_t L, W, R;                   // R = W / V lanes per row
     uint32_t Ty, E, Tz, nty;            // E = Ty + 8 rows held per tile
     uint32_t k0, k1, t;
@@ -95,6 +96,7 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
         load_words<V>(A.S0 + off((z0 + L - 3) % L), c0o);
 
     int bonds_a = 0, bonds_c = 0;
+    uint32_t flips_a = 0, flips_c = 0;   // accepted flips over owned sites
     const size_t set = (size_t)E * W;   // words of one row set in LDS
 
     for (int qi = -3; qi <= (int)Tza + 2; ++qi) {
@@ -131,8 +133,12 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             update_words<V, CA>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, A.k0, A.k1, g, g & 3u, A.t,
                                 0u, n0n, a_sum);
             if constexpr (CA)
-                if (rowD && qi >= 0 && qi < (int)Tza)
+                if (rowD && qi >= 0 && qi < (int)Tza) {
                     bonds_a += a_sum;
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        flips_a = popc_acc(c0o[v] ^ n0n[v], flips_a);
+                }
         }
         // B: sweep t, colour 1, plane q-1
         if (rowB && qi >= -1) {
@@ -145,6 +151,12 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             int unused = 0;
             update_words<V, false>(c1m, n0a, adj, pi, ym, yp, n0b, n0n, A.k0, A.k1, g, g & 3u,
                                    A.t, 1u, n1n, unused);
+            if constexpr (CA)
+                if (rowD && qi >= 1 && qi <= (int)Tza) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        flips_a = popc_acc(c1m[v] ^ n1n[v], flips_a);
+                }
         }
         // C: sweep t+1, colour 0, plane q-2
         if (rowC && qi >= 1) {
@@ -158,8 +170,12 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             update_words<V, CC>(n0b, n1a, adj, pi, ym, yp, n1b, n1n, A.k0, A.k1, g, g & 3u,
                                 A.t + 1u, 0u, m0n, a_sum);
             if (rowD && qi >= 2 && qi < (int)Tza + 2) {
-                if constexpr (CC)
+                if constexpr (CC) {
                     bonds_c += a_sum;
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        flips_c = popc_acc(n0b[v] ^ m0n[v], flips_c);
+                }
                 store_words_nt<V>(A.D0 + off(zc), m0n);
             }
         }
@@ -174,6 +190,11 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             int unused = 0;
             update_words<V, false>(n1b, m0a, adj, pi, ym, yp, m0b, m0n, A.k0, A.k1, g, g & 3u,
                                    A.t + 1u, 1u, m1n, unused);
+            if constexpr (CC) {
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    flips_c = popc_acc(n1b[v] ^ m1n[v], flips_c);
+            }
             store_words_nt<V>(A.D1 + off(zd), m1n);
         }
         // advance the rings by one plane
@@ -190,25 +211,32 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
     }
 
     if constexpr (CA || CC) {
-        __shared__ unsigned long long part[2][16];
+        __shared__ unsigned long long part[4][16];
         const unsigned long long wa = wave_sum_u64((unsigned long long)bonds_a);
         const unsigned long long wc = wave_sum_u64((unsigned long long)bonds_c);
+        const unsigned long long fa = wave_sum_u64((unsigned long long)flips_a);
+        const unsigned long long fc = wave_sum_u64((unsigned long long)flips_c);
         const uint32_t nw = (blockDim.x + 63) / 64;
         if ((tid & 63) == 0) {
             part[0][tid >> 6] = wa;
             part[1][tid >> 6] = wc;
+            part[2][tid >> 6] = fa;
+            part[3][tid >> 6] = fc;
         }
         __syncthreads();
         if (tid == 0) {
-            unsigned long long ta = 0, tc = 0;
-            for (uint32_t k = 0; k < nw; ++k) {
-                ta += part[0][k];
-                tc += part[1][k];
-            }
-            if constexpr (CA)
-                atomicAdd(A.acc_a, ta);
-            if constexpr (CC)
-                atomicAdd(A.acc_c, tc);
+            unsigned long long tot[4] = {0, 0, 0, 0};
+            for (uint32_t k = 0; k < nw; ++k)
+                for (int c = 0; c < 4; ++c)
+                    tot[c] += part[c][k];
+            if (CA && A.acc_a != nullptr)
+                atomicAdd(A.acc_a, tot[0]);
+            if (CC && A.acc_c != nullptr)
+                atomicAdd(A.acc_c, tot[1]);
+            if (CA && A.flip_a != nullptr)
+                atomicAdd(A.flip_a, tot[2]);
+            if (CC && A.flip_c != nullptr)
+                atomicAdd(A.flip_c, tot[3]);
         }
     }
 }
@@ -216,7 +244,8 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
 template <int V>
 void launch2(hipStream_t st, const Sweep2Args &a, dim3 grid, dim3 block, size_t lds)
 {
-    const bool ca = a.acc_a != nullptr, cc = a.acc_c != nullptr;
+    const bool ca = a.acc_a != nullptr || a.flip_a != nullptr;
+    const bool cc = a.acc_c != nullptr || a.flip_c != nullptr;
     if (ca && cc) {
         hipLaunchKernelGGL((k_bit_sweep2<V, true, true>), grid, block, lds, st, a);
     } else if (ca) {
@@ -266,7 +295,8 @@ BitTuning bit_tuning2_default(uint32_t L)
 
 hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                       const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
-                      unsigned long long *acc_a, unsigned long long *acc_c)
+                      unsigned long long *acc_a, unsigned long long *acc_c,
+                      unsigned long long *flip_a, unsigned long long *flip_c)
 {
     if (!bit_tuning2_valid(L, tu))
         return hipErrorInvalidValue;
@@ -274,6 +304,8 @@ hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, con
     a.S0 = S0; a.S1 = S1; a.D0 = D0; a.D1 = D1;
     a.acc_a = acc_a;
     a.acc_c = acc_c;
+    a.flip_a = flip_a;
+    a.flip_c = flip_c;
     a.L = L;
     a.W = L / 64;
     a.R = a.W / tu.V;

@@ -63,12 +63,13 @@ __global__ void __launch_bounds__(kThreads) k_i8_init(uint64_t N, uint32_t k0, u
 // (0, t, 2, 0) (Supplementary Methods I B: order drawn per sweep).
 __global__ void __launch_bounds__(kThreads)
     k_i8_half(uint32_t L, uint64_t half_n, uint32_t k0, uint32_t k1, uint32_t t, uint32_t which,
-              uint32_t mixed, int8_t *s, unsigned long long *bond_acc)
+              uint32_t mixed, int8_t *s, unsigned long long *bond_acc,
+              unsigned long long *flip_acc)
 {
     const uint32_t first = mixed ? (philox10(0u, t, 2u, 0u, k0, k1).w[0] & 1u) : 0u;
     const uint32_t p = which ^ first;
     const uint32_t H = L >> 1;
-    unsigned long long acc = 0;
+    unsigned long long acc = 0, flips = 0;
     for (uint64_t j = (uint64_t)blockIdx.x * kThreads + threadIdx.x; j < half_n;
          j += (uint64_t)gridDim.x * kThreads) {
         const uint32_t xh = (uint32_t)(j % H);
@@ -92,11 +93,15 @@ __global__ void __launch_bounds__(kThreads)
             const Words4 r = philox10((uint32_t)(j >> 7), t, p, 0u, k0, k1);
             flip = (r.w[(j >> 5) & 3] >> (j & 31)) & 1u;
         }
-        if (flip)
+        if (flip) {
             s[i] = (int8_t)-me;
+            ++flips;
+        }
     }
     if (bond_acc != nullptr)
         block_add_u64(acc, bond_acc);
+    if (flip_acc != nullptr)
+        block_add_u64(flips, flip_acc);
 }
 
 // Per-axis unsatisfied bonds: [s_i != s_{i+e_x}], [.. e_y], [.. e_z].
@@ -200,12 +205,13 @@ hipError_t i8_init(hipStream_t st, uint32_t L, uint64_t seed, int8_t *s)
 }
 
 hipError_t i8_half_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, int which,
-                         bool mixed, int8_t *s, unsigned long long *bond_acc)
+                         bool mixed, int8_t *s, unsigned long long *bond_acc,
+                         unsigned long long *flip_acc)
 {
     const uint64_t half_n = (uint64_t)L * L * L / 2;
     hipLaunchKernelGGL(k_i8_half, dim3(grid_for(half_n, 8192)), dim3(kThreads), 0, st, L, half_n,
                        (uint32_t)seed, (uint32_t)(seed >> 32), t, (uint32_t)which,
-                       mixed ? 1u : 0u, s, bond_acc);
+                       mixed ? 1u : 0u, s, bond_acc, flip_acc);
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@ struct StateMap {
     size_t counter_off;   // 64 uint64 counters for measurements
     size_t corr_off;      // 3*(L/2+1) + 1 int64 correlation accumulators
     size_t trace_off;     // kTraceCap uint64 trace slots for host-trace runs
+    size_t flips_off;     // kTraceCap uint64 accepted-flip slots for host-trace runs
     size_t stage_off;     // staging bytes for host copies
     size_t stage_bytes;
     size_t total;
@@ -41,8 +42,11 @@ BitTuning bit_tuning2_default(uint32_t L);
 hipError_t i8_init(hipStream_t st, uint32_t L, uint64_t seed, int8_t *s);
 // which = 0: first half-sweep of sweep t (colour 0, or the drawn colour in the
 // mixed cycle), which = 1: the second.
+// bond_acc / flip_acc (nullable): bond count of the state entering the pass,
+// accepted flips of the pass.
 hipError_t i8_half_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, int which,
-                         bool mixed, int8_t *s, unsigned long long *bond_acc);
+                         bool mixed, int8_t *s, unsigned long long *bond_acc,
+                         unsigned long long *flip_acc);
 hipError_t i8_bonds(hipStream_t st, uint32_t L, const int8_t *s, unsigned long long *acc3);
 hipError_t i8_corr(hipStream_t st, uint32_t L, const int8_t *s, long long *S, long long *M);
 hipError_t i8_check_pm1(hipStream_t st, size_t n, const int8_t *s, unsigned long long *bad);
@@ -52,19 +56,22 @@ hipError_t i8_check_pm1(hipStream_t st, size_t n, const int8_t *s, unsigned long
 hipError_t bit_init(hipStream_t st, uint32_t L, uint64_t seed, uint32_t *P0, uint32_t *P1);
 hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                      const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
-                     unsigned long long *bond_acc, bool mixed);
+                     unsigned long long *bond_acc, bool mixed,
+                     unsigned long long *flip_acc = nullptr);
 // Sweeps t and t+1 of the 01 cycle in one pass (copy S -> copy D); acc_a /
 // acc_c (nullable) receive the bond counts of the states entering them.
 hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                       const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
-                      unsigned long long *acc_a, unsigned long long *acc_c);
+                      unsigned long long *acc_a, unsigned long long *acc_c,
+                      unsigned long long *flip_a = nullptr, unsigned long long *flip_c = nullptr);
 hipError_t bit_bonds(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
                      unsigned long long *acc3);
 hipError_t bit_bonds_total(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
                            unsigned long long *acc);
 // Double-checkerboard sweep in place (B a power of two >= 2, L % 2B == 0).
 hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
-                            uint32_t *P0, uint32_t *P1, bool mixed);
+                            uint32_t *P0, uint32_t *P1, bool mixed,
+                            unsigned long long *flip_acc = nullptr);
 hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
                     unsigned long long *anti /* 3*(L/2+1) */, unsigned long long *ones);
 // Unpack planes z in [z0, z0+nz) to int8 (index (z-z0)*L*L + y*L + x).

@@ -398,3 +398,56 @@ def test_double_checkerboard_rejects(qz):
     i8 = qz.Lattice(16, 1, "i8")
     with pytest.raises(qz.QuenchError):
         i8.set_double_checkerboard(4)
+
+
+# --------------------------------------------------------------------------
+# accepted flips traced beside the bond count
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("layout,L,mode", [("i8", 16, "01"), ("i8", 34, "mixed"),
+                                           ("bit", 64, "01"), ("bit", 128, "mixed"),
+                                           ("bit", 128, "pass2"), ("bit", 192, "pass2"),
+                                           ("bit", 64, "dcb"), ("bit", 128, "dcb-mixed")])
+def test_flip_trace_matches_oracle(qz, orc, layout, L, mode):
+    seed = 300 + L
+    say("flips", layout, L, mode)
+    lat = qz.Lattice(L, seed, layout)
+    mixed = mode in ("mixed", "dcb-mixed")
+    double_B = 4 if mode.startswith("dcb") else 0
+    if mixed:
+        lat.set_cycle(True)
+    if double_B:
+        lat.set_double_checkerboard(double_B)
+    if mode == "pass2":
+        lat.set_pass(2)
+    for every, n in ((1, 5), (3, 9)):
+        B, F = lat.run_traced(n, every)
+        s = lat.download()
+        t0 = lat.t - n
+        # replay the same sweeps with the oracle from the state before them
+        lat2 = qz.Lattice(L, seed, layout)
+        if mixed:
+            lat2.set_cycle(True)
+        if double_B:
+            lat2.set_double_checkerboard(double_B)
+        lat2.run(t0)
+        s0 = lat2.download()
+        wantB, wantF = orc.run_traced(s0, seed, t0, n, every, mixed=mixed, double_B=double_B)
+        assert np.array_equal(B, wantB), (every, n)
+        assert np.array_equal(F, wantF), (every, n)
+        assert np.array_equal(s0, s)
+
+
+def test_run_device_traced_matches_host(qz):
+    import torch
+    L, seed = 128, 17
+    a = qz.Lattice(L, seed, "bit")
+    b = qz.Lattice(L, seed, "bit")
+    b.set_pass(2)
+    B, F = a.run_traced(20, 2)
+    dB = torch.zeros(10, dtype=torch.int64, device="cuda")
+    dF = torch.zeros(10, dtype=torch.int64, device="cuda")
+    b.run_device_traced(20, 2, dB, dF)
+    torch.cuda.synchronize()
+    assert np.array_equal(dB.cpu().numpy(), B)
+    assert np.array_equal(dF.cpu().numpy(), F)
+    assert np.array_equal(a.download(), b.download())

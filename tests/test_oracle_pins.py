@@ -679,3 +679,27 @@ def test_double_checkerboard_reduces_to_plain_when_blocks_cover(orc):
     u = np.ones((L, L, L), dtype=np.int8)
     orc.sweep_double(u, 2, 2, 0)
     assert np.all(u == 1)
+
+
+# --------------------------------------------------------------------------
+# accepted flips per sweep (the physics output beside the attempts)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mixed,double_B", [(False, 0), (True, 0), (False, 2), (True, 4)])
+def test_flip_counts_are_hamming_distances(orc, mixed, double_B):
+    """Each site is proposed once per sweep, so the flips of a sweep equal the
+    number of sites that differ before and after it; the bond trace equals the
+    plain run's."""
+    L, seed = 16, 12
+    s = orc.init(L, seed)
+    ref = s.copy()
+    B, F = orc.run_traced(s, seed, 0, 9, 1, mixed=mixed, double_B=double_B)
+    for k in range(9):
+        before = ref.copy()
+        if double_B:
+            orc.sweep_double(ref, double_B, seed, k, mixed)
+        else:
+            orc.run(ref, seed, k, 1, mixed=mixed)
+        assert F[k] == int((before != ref).sum())
+        assert B[k] == int(orc.bonds(before).sum())
+    assert np.array_equal(s, ref)
+    assert F[0] > 0
