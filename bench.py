@@ -197,6 +197,7 @@ def main():
     per_launch = pcfg[0]   # sweeps carried by one launch of the dominant kernel
     ntrace = (W + K) // every + 2
     trace = torch.zeros(ntrace, dtype=torch.int64, device="cuda")
+    flips = torch.zeros(ntrace, dtype=torch.int64, device="cuda")
     print(f"# L={L} seed={seed} tuning={tune} warmup={W} steps={K} corr_times={len(corr_times)}",
           file=sys.stderr, flush=True)
 
@@ -208,11 +209,12 @@ def main():
                 n = t_to - t if t_to - t < every else ((t_to - t) // every) * every
                 ev = every if n % every == 0 else n
                 sl = trace[t // every: t // every + n // ev]
+                fl = flips[t // every: t // every + n // ev]
                 if timing is not None:
                     a = torch.cuda.Event(enable_timing=True)
                     b = torch.cuda.Event(enable_timing=True)
                     a.record(stream)
-                lat.run_device(n, ev, sl)
+                lat.run_device_traced(n, ev, sl, fl)
                 if timing is not None:
                     b.record(stream)
                     timing.append((a, b, n, t))
@@ -312,6 +314,12 @@ def main():
         "corr_ms_mean": round(sum(corr_ms) / len(corr_ms), 3) if corr_ms else None,
         "corr_count": len(corr_ms),
         "ell_E_final": round(measure.energy_length(B_last, N), 4),
+        # accepted moves (a physics output, not the work unit): flips per site in
+        # the traced sweeps of the timed window, and in the last one
+        "accepted_flips_per_site_window_mean": round(
+            float(flips[W // every:(W + K - 1) // every + 1].double().mean().item()) / N, 7),
+        "accepted_flips_per_site_last": round(
+            int(flips[(W + K - 1) // every].item()) / N, 7),
         "ell_C_final": (round(measure.crossing_length(ells[-1][1], ells[-1][2], N), 4)
                         if ells else None),
     }
