@@ -176,6 +176,17 @@ int push_reps(qz_batch *b)
     return QZ_OK;
 }
 
+// Most sweeps one group may span: the group clears its traced ring entries
+// before its sweeps, so it may hold at most `cap` trace points per replica (a
+// longer group would reuse an entry inside the group and add two counts).
+uint32_t group_limit(const qz_batch *b)
+{
+    if (b->every == 0)
+        return 0xFFFFFFFFu;
+    const uint64_t lim = (uint64_t)b->cap * b->every;
+    return lim > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)lim;
+}
+
 // Enqueue one group of k sweeps on stream s: clear the traced slots, k sweep
 // launches (step = 0..k-1), then advance every active replica by k.
 hipError_t enqueue_group(qz_batch *b, hipStream_t s, uint32_t k)
@@ -310,7 +321,7 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
     b->stage_bytes = lay.stage_bytes;
     b->counters = reinterpret_cast<unsigned long long *>(b->base + lay.counters_off);
     b->corr = reinterpret_cast<unsigned long long *>(b->base + lay.corr_off);
-    b->graph_sweeps = 16;
+    b->graph_sweeps = std::min<uint32_t>(16u, group_limit(b));
     b->graph_ok = false;
     b->failed = false;
     b->host_reps.resize(n);
@@ -369,7 +380,7 @@ QZ_EXPORT int qz_batch_set_tuning(qz_batch *b, uint32_t L, uint32_t Tz, uint32_t
             return fail(QZ_EINVAL, "Tz must divide L and be >= 8");
         b->tz[L] = Tz;
     }
-    b->graph_sweeps = graph_sweeps;
+    b->graph_sweeps = std::min<uint32_t>(graph_sweeps, group_limit(b));
     drop_graph(b);
     return build_tables(b);
 }
@@ -394,8 +405,11 @@ QZ_EXPORT int qz_batch_run(qz_batch *b, uint64_t n_sweeps)
             left -= b->graph_sweeps;
         }
     }
-    if (left > 0)
-        BZ_HIP(b, enqueue_group(b, b->st, (uint32_t)left));
+    while (left > 0) {
+        const uint32_t k = (uint32_t)std::min<uint64_t>(left, group_limit(b));
+        BZ_HIP(b, enqueue_group(b, b->st, k));
+        left -= k;
+    }
     return QZ_OK;
 }
 

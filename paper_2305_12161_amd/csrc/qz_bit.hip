@@ -485,9 +485,11 @@ BitTuning bit_tuning_default(uint32_t L)
     BitTuning t;
     t.V = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
     const uint32_t R = W / t.V;
-    if (L * R <= 256 || (L * R <= 1024 && L <= 512)) {
-        t.Ty = (int)L;   // whole planes
-        t.Tz = (int)((L <= 128) ? 8 : 16);
+    BitTuning whole = t;
+    whole.Ty = (int)L;   // whole planes
+    whole.Tz = (int)std::min<uint32_t>((L <= 128) ? 8 : 16, L);
+    if ((L * R <= 256 || (L * R <= 1024 && L <= 512)) && bit_tuning_valid(L, whole)) {
+        t = whole;
     } else {
         uint32_t E = 8;
         while (E * 2 * R <= 256 && E * 2 <= L)

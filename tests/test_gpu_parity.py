@@ -90,6 +90,21 @@ def test_bit_default_tuning(qz, orc, L):
     assert np.array_equal(lat.download(), s)
 
 
+def test_default_tunings_run_at_every_size(qz):
+    """Every L % 64 == 0 up to 1024 gets a default one-sweep and two-sweep
+    configuration that launches, and the two agree on the trajectory."""
+    for L in range(64, 1025, 64):
+        say("default tuning", L)
+        a = qz.Lattice(L, 7, "bit")
+        b = qz.Lattice(L, 7, "bit")
+        b.set_pass(2)
+        ta = a.run(4, 2)
+        tb = b.run(4, 2)
+        assert np.array_equal(ta, tb), (L, a.tuning(), b.pass_config())
+        assert np.array_equal(a.window((1, 2, 3), 16), b.window((1, 2, 3), 16)), L
+        del a, b
+
+
 # (V, Ty, Tz) triples covering whole planes, halo tiles, ragged y and z tiles
 TUNINGS = {
     64: [(1, 64, 64), (1, 64, 5), (1, 28, 7), (1, 12, 64), (1, 60, 3)],
