@@ -325,16 +325,21 @@ def main():
     }
     del lat
     torch.cuda.empty_cache()
+    # the secondary legs report their own failure instead of hiding the main line
+    def leg(name, fn):
+        print(f"# {name}", file=sys.stderr, flush=True)
+        try:
+            out[name] = fn()
+        except Exception as e:  # noqa: BLE001
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+            print(f"# {name} failed: {e}", file=sys.stderr, flush=True)
     if not args.no_batch:
-        print("# batched workload", file=sys.stderr, flush=True)
-        out["batched"] = batched_workload(binding, torch, workloads)
+        leg("batched", lambda: batched_workload(binding, torch, workloads))
     if not args.no_serve:
-        print("# served workload", file=sys.stderr, flush=True)
         rate = args.serve_rate if args.serve_rate else workloads.SERVE_RATE_PER_S
-        out["served"] = served_workload(binding, torch, workloads, args.serve_requests, rate)
+        leg("served", lambda: served_workload(binding, torch, workloads, args.serve_requests, rate))
     if not args.no_cpu_baseline:
-        print("# cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(L, seed)
+        leg("cpu_baseline", lambda: cpu_baseline(L, seed))
     print(json.dumps(out), flush=True)
 
 
