@@ -86,8 +86,12 @@ def batched_workload(binding, torch, workloads):
     b.set_tuning(64, 0, 100)
     b.sync()
     t0 = time.perf_counter()
-    b.run(t_max)
-    b.sync()
+    piece = 1000
+    for t in range(0, t_max, piece):
+        b.run(min(piece, t_max - t))
+        b.sync()
+        print(f"# batched t={t + piece} at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
     wall = time.perf_counter() - t0
     sites = sum(L ** 3 for L, _ in specs)
     rate = sites * t_max / (wall * 1e9)
@@ -131,8 +135,11 @@ def served_workload(binding, torch, workloads, n_req, rate):
     be = serve.GpuBackend(budget_bytes=workloads.SERVE_BUDGET_BYTES,
                           batch_slots=workloads.SERVE_BATCH_SLOTS, every=every, chunk=chunk)
     srv = serve.Server(be, chunk=chunk)
+    def progress(done, total, secs):
+        if done % 100 == 0 or done == total:
+            print(f"# served {done}/{total} at {secs:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    res = srv.serve(reqs)
+    res = srv.serve(reqs, progress=progress)
     wall = time.perf_counter() - t0
     st = serve.summarize(res, wall)
     st.update({
@@ -242,6 +249,7 @@ def main():
             S, M = lat.corr()
             corr_ms.append((time.perf_counter() - c0) * 1e3)
             ells.append((tc, S, M))
+            print(f"# t={tc} at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert lat.t == W + K

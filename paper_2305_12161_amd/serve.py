@@ -152,9 +152,11 @@ class Server:
         self.backend = backend
         self.chunk = chunk
 
-    def serve(self, requests, clock=time.perf_counter, time_scale: float = 1.0) -> List[Result]:
+    def serve(self, requests, clock=time.perf_counter, time_scale: float = 1.0,
+              progress=None) -> List[Result]:
         """Serve `requests` (objects with idx, L, seed, t_max, arrival_s), arrivals
-        replayed in real time (arrival_s * time_scale after the start)."""
+        replayed in real time (arrival_s * time_scale after the start).
+        progress(done, total, seconds) is called after each retirement."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
         waiting: collections.deque = collections.deque()
         results: Dict[int, Result] = {}
@@ -193,6 +195,8 @@ class Server:
                 res.final_B = out["final_B"]
                 res.done_s = clock() - t_start
                 done += 1
+                if progress is not None:
+                    progress(done, total, res.done_s)
         return [results[k] for k in sorted(results)]
 
 
