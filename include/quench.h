@@ -153,8 +153,8 @@ int qz_download_window(qz_lattice *q, const uint32_t origin[3], uint32_t W, int8
 int qz_set_tuning(qz_lattice *q, int V, int Ty, int Tz);
 int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
 
-/* Sweeps per pass over memory (bit layout).  sweeps = 1 (the default): every
- * sweep reads and writes the lattice once.  sweeps = 2: sweeps t and t+1 run
+/* Sweeps per pass over memory (bit layout).  sweeps = 1: every sweep reads
+ * and writes the lattice once.  sweeps = 2: sweeps t and t+1 run
  * in one pass that keeps the state after sweep t on chip, halving the memory
  * traffic per sweep; the trajectory, the bond trace and every measurement are
  * identical to sweeps = 1 (Methods, "Checkerboard update": the 01 cycle is
@@ -165,7 +165,8 @@ int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
  * all three 0 selects the default for L.  QZ_EINVAL for another sweep count
  * or a tuning that does not fit (at most 1024 threads and 60 KiB of LDS per
  * workgroup); QZ_EUNSUPPORTED for the int8 layout.  qz_get_pass reports
- * (sweeps, V, Ty, Tz). */
+ * (sweeps, V, Ty, Tz).  Default: 2 for L >= 1280 (where the one-sweep pass is
+ * bound by HBM bandwidth), else 1. */
 int qz_set_pass(qz_lattice *q, int sweeps, int V, int Ty, int Tz);
 int qz_get_pass(const qz_lattice *q, int out_sweeps_V_Ty_Tz[4]);
 

@@ -248,6 +248,7 @@ QZ_EXPORT int qz_create(uint32_t L, uint64_t seed, int layout, void *dev_mem, si
     if (layout == QZ_LAYOUT_BIT) {
         q->tune = qz::bit_tuning_default(L);
         q->tune2 = qz::bit_tuning2_default(L);
+        q->pass = qz::bit_pass_default(L);
     }
     hipError_t e;
     if (layout == QZ_LAYOUT_I8)

@@ -481,24 +481,24 @@ bool bit_tuning_valid(uint32_t L, const BitTuning &t)
 
 BitTuning bit_tuning_default(uint32_t L)
 {
+    // Measured on MI355X: whole planes only pay off for L <= 128; above that,
+    // tiles of E = 32 held rows (or fewer when a row needs many lanes) and
+    // Tz = 8 planes give the most workgroups in flight and the best times
+    // from L = 192 to L = 2048.
     const uint32_t W = L / 64;
     BitTuning t;
     t.V = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
     const uint32_t R = W / t.V;
     BitTuning whole = t;
-    whole.Ty = (int)L;   // whole planes
-    whole.Tz = (int)std::min<uint32_t>((L <= 128) ? 8 : 16, L);
-    if ((L * R <= 256 || (L * R <= 1024 && L <= 512)) && bit_tuning_valid(L, whole)) {
-        t = whole;
-    } else {
-        uint32_t E = 8;
-        while (E * 2 * R <= 256 && E * 2 <= L)
-            E *= 2;
-        t.Ty = (int)(E - 4);
-        t.Tz = 32;   // measured best at L = 2048 (E = 32 rows, V = 4)
-    }
-    if ((uint32_t)t.Tz > L)
-        t.Tz = (int)L;
+    whole.Ty = (int)L;
+    whole.Tz = (int)std::min<uint32_t>(8, L);
+    if (L <= 128 && bit_tuning_valid(L, whole))
+        return whole;
+    uint32_t E = 8;
+    while (E * 2 <= 32 && E * 2 * R <= 256 && E * 2 <= L)
+        E *= 2;
+    t.Ty = (int)(E - 4);
+    t.Tz = (int)std::min<uint32_t>(8, L);
     return t;
 }
 

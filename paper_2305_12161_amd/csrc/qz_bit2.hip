@@ -281,17 +281,24 @@ bool bit_tuning2_valid(uint32_t L, const BitTuning &t)
 
 BitTuning bit_tuning2_default(uint32_t L)
 {
+    // Measured on MI355X: E = 32 held rows (24 owned); Tz = 32 planes where the
+    // lattice is far larger than the caches (L >= 1536), else Tz = 8.
     const uint32_t W = L / 64;
     BitTuning t;
     t.V = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
     const uint32_t R = W / t.V;
     uint32_t E = 16;
-    while (E * 2 * R <= 256 && (size_t)2 * 4 * (E * 2) * W * 4 <= 60 * 1024)
+    while (E * 2 <= 32 && E * 2 * R <= 256 && (size_t)2 * 4 * (E * 2) * W * 4 <= 60 * 1024)
         E *= 2;
     t.Ty = (int)std::min<uint32_t>(E - 8, L);
-    t.Tz = (int)std::min<uint32_t>(32, L);
+    t.Tz = (int)std::min<uint32_t>(L >= 1536 ? 32 : 8, L);
     return t;
 }
+
+// Sweeps per pass chosen by default for a bit lattice of side L: two where the
+// one-sweep kernel is bound by HBM bandwidth (two copies of the lattice far
+// beyond the last-level cache), one otherwise.
+int bit_pass_default(uint32_t L) { return L >= 1280 ? 2 : 1; }
 
 hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                       const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,

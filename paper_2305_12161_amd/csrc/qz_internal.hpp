@@ -37,6 +37,7 @@ BitTuning bit_tuning_default(uint32_t L);
 // Tuning of the two-sweep pass (qz_bit2.hip): Ty owned rows, E = Ty + 8 held.
 bool bit_tuning2_valid(uint32_t L, const BitTuning &t);
 BitTuning bit_tuning2_default(uint32_t L);
+int bit_pass_default(uint32_t L);
 
 // ----- int8 layout -----
 hipError_t i8_init(hipStream_t st, uint32_t L, uint64_t seed, int8_t *s);

@@ -88,11 +88,14 @@ def test_config2_trace_and_recount(qz, orc):
     assert np.array_equal(lat.bonds(), orc.bonds(s))
 
 
-def test_config3_window_replays_L2048(qz, orc):
-    """L=2048 bit, seed 3, in the tuning bench.py times; replayed windows."""
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_config3_window_replays_L2048(qz, orc, sweeps):
+    """L=2048 bit, seed 3, with the default tunings bench.py times (one and two
+    sweeps per pass); replayed windows."""
     c = wl.CONFIG3
     lat = qz.Lattice(c.L, c.seed, "bit")
-    print("config3 tuning", lat.tuning(), flush=True)
+    lat.set_pass(sweeps)
+    print("config3 tuning", lat.tuning(), lat.pass_config(), flush=True)
     # the start itself, at a few windows, against the oracle's start
     for o in ((0, 0, 0), (2000, 1000, 5), (1024, 2047, 2047)):
         assert np.array_equal(lat.window(o, 48), orc.init_window(c.L, c.seed, o, 48))
@@ -116,8 +119,10 @@ def test_config3_two_sweep_pass_L2048(qz, orc):
     (bond trace and state), and replayed windows against the oracle."""
     c = wl.CONFIG3
     one = qz.Lattice(c.L, c.seed, "bit")
+    one.set_pass(1)
     two = qz.Lattice(c.L, c.seed, "bit")
     two.set_pass(2)
+    assert one.pass_config()[0] == 1 and two.pass_config()[0] == 2
     print("config3 two-sweep", two.pass_config(), flush=True)
     tr1 = one.run(24, 3)
     tr2 = two.run(24, 3)
@@ -133,11 +138,17 @@ def test_config3_two_sweep_pass_L2048(qz, orc):
     check_identities(two, S, M, c.L ** 3)
 
 
-def test_same_tuning_full_run_L256(qz, orc):
-    """The L=2048 kernel configuration (V=4, Ty=28, Tz=32) on a full L=256 run."""
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_same_tuning_full_run_L256(qz, orc, sweeps):
+    """The L=2048 kernel configurations (one sweep: V=4, Ty=28, Tz=8; two
+    sweeps: V=4, Ty=24, Tz=32) on a full L=256 run against the oracle."""
     L, seed, n = 256, 3, 60
     lat = qz.Lattice(L, seed, "bit")
-    lat.set_tuning(4, 28, 32)
+    if sweeps == 1:
+        lat.set_pass(1)
+        lat.set_tuning(4, 28, 8)
+    else:
+        lat.set_pass(2, 4, 24, 32)
     tr = lat.run(n, 5)
     s = orc.init(L, seed)
     want = orc.run(s, seed, 0, n, 5)
