@@ -161,14 +161,15 @@ def cpu_baseline(L, seed, budget_s=15.0):
     used = oracle.set_threads(cores)
     W = 256 if L >= 256 else L
     w = oracle.init_window(L, seed, (0, 0, 0), W)
-    # calibrate on one sweep, then run for about budget_s
-    t0 = time.perf_counter()
-    oracle.window_advance(L, seed, (0, 0, 0), w, 0, 1)
-    one = time.perf_counter() - t0
-    T = max(1, int(budget_s / max(one, 1e-6)))
-    t0 = time.perf_counter()
-    oracle.window_advance(L, seed, (0, 0, 0), w, 1, T)
-    dt = time.perf_counter() - t0
+    # run chunks of sweeps until about budget_s of CPU time has passed
+    oracle.window_advance(L, seed, (0, 0, 0), w, 0, 1)   # warm up
+    T, dt, chunk = 0, 0.0, 8
+    while dt < budget_s:
+        t0 = time.perf_counter()
+        oracle.window_advance(L, seed, (0, 0, 0), w, 1 + T, chunk)
+        dt += time.perf_counter() - t0
+        T += chunk
+        chunk = min(chunk * 2, 512)
     attempts = (W - 2) ** 3 * T
     return {"value": attempts / (dt * 1e9), "unit": "attempts/ns", "cores": used, "kind": "oracle",
             "sample": f"oracle window replay: {W}^3 cube of the L={L} seed-{seed} start, "
@@ -245,6 +246,7 @@ def main():
         advance(t, tc, timing)
         t = tc
         if tc in corr_times:
+            torch.cuda.synchronize()   # time the measurement alone, not the queued sweeps
             c0 = time.perf_counter()
             S, M = lat.corr()
             corr_ms.append((time.perf_counter() - c0) * 1e3)

@@ -163,7 +163,7 @@ int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
  * sweep per pass.  V, Ty, Tz tune the two-sweep kernel as in qz_set_tuning
  * (V words per lane, Ty owned rows per tile, Ty + 8 rows held, Tz planes);
  * all three 0 selects the default for L.  QZ_EINVAL for another sweep count
- * or a tuning that does not fit (at most 1024 threads and 60 KiB of LDS per
+ * or a tuning that does not fit (at most 1024 threads and 64 KiB of LDS per
  * workgroup); QZ_EUNSUPPORTED for the int8 layout.  qz_get_pass reports
  * (sweeps, V, Ty, Tz).  Default: 2 for L >= 1280 (where the one-sweep pass is
  * bound by HBM bandwidth), else 1. */

@@ -211,7 +211,10 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
     }
 
     if constexpr (CA || CC) {
-        __shared__ unsigned long long part[4][16];
+        // the row sets are no longer needed: reuse the start of LDS for the
+        // per-wave partial sums (at most 16 waves x 4 counters)
+        __syncthreads();
+        unsigned long long(*part)[16] = reinterpret_cast<unsigned long long(*)[16]>(lds);
         const unsigned long long wa = wave_sum_u64((unsigned long long)bonds_a);
         const unsigned long long wc = wave_sum_u64((unsigned long long)bonds_c);
         const unsigned long long fa = wave_sum_u64((unsigned long long)flips_a);
@@ -276,7 +279,7 @@ bool bit_tuning2_valid(uint32_t L, const BitTuning &t)
     if (threads > 1024)
         return false;
     const size_t lds = (size_t)2 * 4 * E * W * 4;
-    return lds <= 60 * 1024;
+    return lds <= 64 * 1024 && lds >= 4 * 16 * 8;
 }
 
 BitTuning bit_tuning2_default(uint32_t L)
@@ -288,7 +291,7 @@ BitTuning bit_tuning2_default(uint32_t L)
     t.V = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
     const uint32_t R = W / t.V;
     uint32_t E = 16;
-    while (E * 2 <= 32 && E * 2 * R <= 256 && (size_t)2 * 4 * (E * 2) * W * 4 <= 60 * 1024)
+    while (E * 2 <= 32 && E * 2 * R <= 256 && (size_t)2 * 4 * (E * 2) * W * 4 <= 64 * 1024)
         E *= 2;
     t.Ty = (int)std::min<uint32_t>(E - 8, L);
     t.Tz = (int)std::min<uint32_t>(L >= 1536 ? 32 : 8, L);
