@@ -75,15 +75,17 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
     auto off = [&](uint32_t z) -> size_t { return (size_t)z * plane_words + (size_t)y * W + w0; };
 
     // register rings, named by plane relative to the step's plane q
-    uint32_t c1m[V], c1c[V], c1p[V], pf1[V];   // old colour 1: q-1, q, q+1; prefetch q+2
-    uint32_t c0o[V], pf0[V];                   // old colour 0: q; prefetch q+1
+    // old colour 1 of planes q-1, q, q+1 and prefetches of q+2, q+3; old colour
+    // 0 of plane q and prefetches of q+1, q+2 (two steps of loads in flight)
+    uint32_t c1m[V], c1c[V], c1p[V], pf1[V], pg1[V];
+    uint32_t c0o[V], pf0[V], pg0[V];
     uint32_t n0a[V], n0b[V], n0n[V];           // colour 0 after sweep t: q-1, q-2; new q
     uint32_t n1a[V], n1b[V], n1n[V];           // colour 1 after sweep t: q-2, q-3; new q-1
     uint32_t m0a[V], m0b[V], m0n[V];           // colour 0 after sweep t+1: q-3, q-4; new q-2
     uint32_t m1n[V];                           // colour 1 after sweep t+1: new q-3
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        c1m[v] = c1c[v] = c1p[v] = pf1[v] = c0o[v] = pf0[v] = 0u;
+        c1m[v] = c1c[v] = c1p[v] = pf1[v] = c0o[v] = pf0[v] = pg1[v] = pg0[v] = 0u;
         n0a[v] = n0b[v] = n0n[v] = n1a[v] = n1b[v] = n1n[v] = 0u;
         m0a[v] = m0b[v] = m0n[v] = m1n[v] = 0u;
     }
@@ -91,9 +93,12 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
         load_words<V>(A.S1 + off((z0 + L - 4) % L), c1m);
         load_words<V>(A.S1 + off((z0 + L - 3) % L), c1c);
         load_words<V>(A.S1 + off((z0 + L - 2) % L), c1p);
+        load_words<V>(A.S1 + off((z0 + L - 1) % L), pf1);
     }
-    if (rowA)
+    if (rowA) {
         load_words<V>(A.S0 + off((z0 + L - 3) % L), c0o);
+        load_words<V>(A.S0 + off((z0 + L - 2) % L), pf0);
+    }
 
     int bonds_a = 0, bonds_c = 0;
     uint32_t flips_a = 0, flips_c = 0;   // accepted flips over owned sites
@@ -101,11 +106,11 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
 
     for (int qi = -3; qi <= (int)Tza + 2; ++qi) {
         const uint32_t zq = (z0 + 2 * L + qi) % L;
-        if (qi < (int)Tza + 2) {
+        if (qi + 1 < (int)Tza + 2) {
             if (held)
-                load_words<V>(A.S1 + off((zq + 2) % L), pf1);
+                load_words<V>(A.S1 + off((zq + 3) % L), pg1);
             if (rowA)
-                load_words<V>(A.S0 + off((zq + 1) % L), pf0);
+                load_words<V>(A.S0 + off((zq + 2) % L), pg0);
         }
         uint32_t *X1 = lds + (size_t)(qi & 1) * 4 * set;   // old colour 1, plane q
         uint32_t *X0 = X1 + set;                            // A's colour 0, plane q-1
@@ -202,6 +207,8 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
         copy_words<V>(c1c, c1p);
         copy_words<V>(c1p, pf1);
         copy_words<V>(c0o, pf0);
+        copy_words<V>(pf1, pg1);
+        copy_words<V>(pf0, pg0);
         copy_words<V>(n0b, n0a);
         copy_words<V>(n0a, n0n);
         copy_words<V>(n1b, n1a);
