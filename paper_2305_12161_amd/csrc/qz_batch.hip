@@ -90,29 +90,63 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
     auto update = [&](const uint32_t *Xo, const uint32_t (&own)[4], const uint32_t (&same)[4],
                       const uint32_t (&zmn)[4], const uint32_t (&zpn)[4], uint32_t zp_plane,
                       uint32_t colour, uint32_t (&out)[4], bool count) {
-        UpCount c[4];
-        uint32_t ties = 0;
+        // the two neighbour triples: (same, shifted, y-1) and (y+1, z-1, z+1)
+        uint32_t n0[4], n1[4], n2[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const uint32_t pi = (colour + yv[v] + zp_plane) & 1u;
             const uint32_t adj = Xo[pi ? gnx[v] : gpr[v]];
-            const uint32_t sh = pi ? funnel(adj, same[v], 1) : funnel(same[v], adj, 31);
-            c[v] = count_up(same[v], sh, Xo[gym[v]], Xo[gyp[v]], zmn[v], zpn[v]);
-            ties |= up_tie(c[v]);
+            n0[v] = pi ? funnel(adj, same[v], 1) : funnel(same[v], adj, 31);
+            n1[v] = Xo[gym[v]];
+            n2[v] = Xo[gyp[v]];
         }
-        uint32_t r[4] = {0u, 0u, 0u, 0u};
-        if (ties != 0u) {
+        auto tie_bits = [&](uint32_t (&r)[4]) {
             const uint32_t blk = (zp_plane * PW + g0) >> 2;      // Philox block = word index / 4
             const Words4 rb = philox10(blk, t, colour, 0u, k0, k1);
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 r[v] = rb.w[v];
-        }
+        };
+        if (count) {
+            // the three-bit up count, also summed into the bond count
+            UpCount c[4];
+            uint32_t ties = 0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            out[v] = up_rule(own[v], c[v], r[v]);
-            if (count)
+            for (int v = 0; v < 4; ++v) {
+                c[v] = count_up(same[v], n0[v], n1[v], n2[v], zmn[v], zpn[v]);
+                ties |= up_tie(c[v]);
+            }
+            uint32_t r[4] = {0u, 0u, 0u, 0u};
+            if (ties != 0u)
+                tie_bits(r);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                out[v] = up_rule(own[v], c[v], r[v]);
                 bonds += up_antialigned_sum(own[v], c[v]);
+            }
+        } else {
+            // majority of seven (the neighbours and s ^ r), as in the lattice kernels
+            uint32_t xa[4], ma[4], xb[4], mb[4], w[4];
+            uint32_t ties = 0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                xa[v] = xor3(same[v], n0[v], n1[v]);
+                ma[v] = maj3(same[v], n0[v], n1[v]);
+                xb[v] = xor3(n2[v], zmn[v], zpn[v]);
+                mb[v] = maj3(n2[v], zmn[v], zpn[v]);
+                ties |= (xa[v] ^ xb[v]) & (ma[v] ^ mb[v]);
+                w[v] = own[v];
+            }
+            if (ties != 0u) {
+                uint32_t r[4];
+                tie_bits(r);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    w[v] ^= r[v];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                out[v] = maj3(ma[v], mb[v], maj3(xa[v], xb[v], w[v]));
         }
     };
 

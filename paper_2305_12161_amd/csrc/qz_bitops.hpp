@@ -53,11 +53,58 @@ __device__ __forceinline__ void store_words_nt(uint32_t *p, const uint32_t (&r)[
         __builtin_nontemporal_store(r[v], p + v);
 }
 
+// The x-neighbour word on the side given by pi: pi = 0 takes site k-1 (bits
+// move up by one, bit 0 from the word below), pi = 1 takes site k+1 (bits move
+// down by one, bit 31 from the word above); adj is the word beyond the lane's V.
+template <int V>
+__device__ __forceinline__ uint32_t shifted_word(const uint32_t (&same)[V], uint32_t adj,
+                                                 uint32_t pi, int v)
+{
+    if (pi == 0u) {
+        const uint32_t lo = (v > 0) ? same[v > 0 ? v - 1 : 0] : adj;
+        return funnel(same[v], lo, 31);
+    }
+    const uint32_t hi = (v < V - 1) ? same[v < V - 1 ? v + 1 : 0] : adj;
+    return funnel(hi, same[v], 1);
+}
+
+// The tie words of this lane: word (sub + v) of Philox block ctr0 / 4 of
+// (t, p), chosen without a dynamically indexed array (which would live in
+// scratch memory).  With V = 4 the lane's words start a block (sub = 0); with
+// V = 2, sub is 0 or 2.
+template <int V>
+__device__ __forceinline__ void tie_words(uint32_t k0, uint32_t k1, uint32_t ctr0, uint32_t sub,
+                                          uint32_t t, uint32_t p, uint32_t (&r)[V])
+{
+    const Words4 rb = philox10(ctr0 >> 2, t, p, 0u, k0, k1);
+    if constexpr (V == 4) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            r[v] = rb.w[v];
+    } else if constexpr (V == 2) {
+        const bool hi = (sub & 2u) != 0u;
+        r[0] = hi ? rb.w[2] : rb.w[0];
+        r[1] = hi ? rb.w[3] : rb.w[1];
+    } else {
+        const uint32_t lo = (sub & 1u) ? rb.w[1] : rb.w[0];
+        const uint32_t hi = (sub & 1u) ? rb.w[3] : rb.w[2];
+        r[0] = (sub & 2u) ? hi : lo;
+    }
+}
+
 // Update V words of one colour.  own = the words being updated; same = the
 // other colour's same-row words (x-neighbour at the same index); adj = the
 // word just outside the lane's range on the side given by pi; ym/yp/zm/zp the
 // other colour's rows y-1, y+1 and planes z-1, z+1.
-// COUNT: also add the sites' anti-aligned counts (sum a) to `acc`.
+//
+// Without counting, the rule runs as a majority of seven: with U the number
+// of up neighbours and w = s ^ r, the new spin is up iff U + w >= 4 (U >= 4
+// always up, U == 3 takes w, U <= 2 always down).  Split the neighbours into
+// two triples with parities xa, xb and majorities ma, mb (U = xa + xb +
+// 2(ma + mb)); then U + w >= 4 iff maj(ma, mb, maj(xa, xb, w)), and U == 3
+// iff (xa ^ xb) & (ma ^ mb), which decides whether the lane needs its tie
+// bits.  COUNT: the full three-bit count U instead, for the sum of a over the
+// sites (added to acc).
 template <int V, bool COUNT>
 __device__ __forceinline__ void update_words(const uint32_t (&own)[V], const uint32_t (&same)[V],
                                              uint32_t adj, uint32_t pi, const uint32_t (&ym)[V],
@@ -66,51 +113,52 @@ __device__ __forceinline__ void update_words(const uint32_t (&own)[V], const uin
                                              uint32_t ctr0, uint32_t sub, uint32_t t, uint32_t p,
                                              uint32_t (&out)[V], int &acc)
 {
-    UpCount c[V];
-    uint32_t ties = 0;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        uint32_t shifted;
-        if (pi == 0u) {
-            // neighbour at k-1: bits move up by one, bit 0 from the word below
-            const uint32_t lo = (v > 0) ? same[v > 0 ? v - 1 : 0] : adj;
-            shifted = funnel(same[v], lo, 31);
-        } else {
-            // neighbour at k+1: bits move down by one, bit 31 from the word above
-            const uint32_t hi = (v < V - 1) ? same[v < V - 1 ? v + 1 : 0] : adj;
-            shifted = funnel(hi, same[v], 1);
-        }
-        c[v] = count_up(same[v], shifted, ym[v], yp[v], zm[v], zp[v]);
-        ties |= up_tie(c[v]);
-    }
     uint32_t r[V];
 #pragma unroll
     for (int v = 0; v < V; ++v)
         r[v] = 0u;
-    if (ties != 0u) {
-        const Words4 rb = philox10(ctr0 >> 2, t, p, 0u, k0, k1);
-        // Word (sub + v) of the block, chosen without a dynamically indexed
-        // array (which would live in scratch memory).  With V = 4 the lane's
-        // words start a block (sub = 0); with V = 2, sub is 0 or 2.
-        if constexpr (V == 4) {
+    if constexpr (COUNT) {
+        UpCount c[V];
+        uint32_t ties = 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            c[v] = count_up(same[v], shifted_word<V>(same, adj, pi, v), ym[v], yp[v], zm[v], zp[v]);
+            ties |= up_tie(c[v]);
+        }
+        if (ties != 0u)
+            tie_words<V>(k0, k1, ctr0, sub, t, p, r);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            out[v] = up_rule(own[v], c[v], r[v]);
+            acc += up_antialigned_sum(own[v], c[v]);
+        }
+    } else {
+        uint32_t xa[V], ma[V], xb[V], mb[V];
+        uint32_t ties = 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint32_t sh = shifted_word<V>(same, adj, pi, v);
+            xa[v] = xor3(same[v], sh, ym[v]);
+            ma[v] = maj3(same[v], sh, ym[v]);
+            xb[v] = xor3(yp[v], zm[v], zp[v]);
+            mb[v] = maj3(yp[v], zm[v], zp[v]);
+            ties |= (xa[v] ^ xb[v]) & (ma[v] ^ mb[v]);
+        }
+        // w = own ^ r, formed only where some lane has a tie
+        uint32_t w[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            w[v] = own[v];
+        if (ties != 0u) {
+            tie_words<V>(k0, k1, ctr0, sub, t, p, r);
 #pragma unroll
             for (int v = 0; v < V; ++v)
-                r[v] = rb.w[v];
-        } else if constexpr (V == 2) {
-            const bool hi = (sub & 2u) != 0u;
-            r[0] = hi ? rb.w[2] : rb.w[0];
-            r[1] = hi ? rb.w[3] : rb.w[1];
-        } else {
-            const uint32_t lo = (sub & 1u) ? rb.w[1] : rb.w[0];
-            const uint32_t hi = (sub & 1u) ? rb.w[3] : rb.w[2];
-            r[0] = (sub & 2u) ? hi : lo;
+                w[v] ^= r[v];
         }
-    }
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-        out[v] = up_rule(own[v], c[v], r[v]);
-        if constexpr (COUNT)
-            acc += up_antialigned_sum(own[v], c[v]);
+        for (int v = 0; v < V; ++v)
+            out[v] = maj3(ma[v], mb[v], maj3(xa[v], xb[v], w[v]));
+        (void)acc;
     }
 }
 
