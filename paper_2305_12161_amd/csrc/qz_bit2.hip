@@ -48,13 +48,24 @@ __device__ __forceinline__ void copy_words(uint32_t (&d)[V], const uint32_t (&s)
 
 // CA / CC: add the anti-aligned counts of the owned colour-0 sites of the state
 // entering sweep t (stage A) / sweep t+1 (stage C).
-template <int V, bool CA, bool CC>
+// PAIRED (needs 64 % R == 0 and E a multiple of 128 / R): waves come in pairs
+// over 2 * (64 / R) consecutive rows, the even wave holding the even rows and
+// the odd wave the odd ones.  Every wave's rows then share the parity of y, so
+// the x parity pi of all four stages is the same across the wave and the
+// x-neighbour shift takes one uniform branch instead of both.
+template <int V, bool CA, bool CC, bool PAIRED>
 __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
 {
     extern __shared__ uint32_t lds[];
     const uint32_t L = A.L, W = A.W, E = A.E;
     const uint32_t tid = threadIdx.x;
-    const uint32_t e = tid / A.R;               // held row
+    uint32_t e;                                  // held row
+    if constexpr (PAIRED) {
+        const uint32_t rpw = 64u / A.R, wv = tid >> 6, j = (tid & 63u) / A.R;
+        e = 2u * rpw * (wv >> 1) + 2u * j + (wv & 1u);
+    } else {
+        e = tid / A.R;
+    }
     const uint32_t w0 = (tid % A.R) * V;        // first word of this lane
 
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -125,7 +136,9 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
         __syncthreads();
 
         // all four stages update sites with the same x parity in this row
-        const uint32_t pi = (y + zq) & 1u;
+        uint32_t pi = (y + zq) & 1u;
+        if constexpr (PAIRED)
+            pi = __builtin_amdgcn_readfirstlane(pi);   // the same in every lane of the wave
         const uint32_t wadj = pi == 0u ? wprev : wnext;
         // A: sweep t, colour 0, plane q
         if (rowA) {
@@ -251,19 +264,19 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
     }
 }
 
-template <int V>
+template <int V, bool P>
 void launch2(hipStream_t st, const Sweep2Args &a, dim3 grid, dim3 block, size_t lds)
 {
     const bool ca = a.acc_a != nullptr || a.flip_a != nullptr;
     const bool cc = a.acc_c != nullptr || a.flip_c != nullptr;
     if (ca && cc) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, true, true>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, true, true, P>), grid, block, lds, st, a);
     } else if (ca) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, true, false>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P>), grid, block, lds, st, a);
     } else if (cc) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, false, true>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, false, true, P>), grid, block, lds, st, a);
     } else {
-        hipLaunchKernelGGL((k_bit_sweep2<V, false, false>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P>), grid, block, lds, st, a);
     }
 }
 
@@ -341,10 +354,17 @@ hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, con
     const uint32_t threads = ((a.E * a.R + 63) / 64) * 64;
     const size_t lds = (size_t)2 * 4 * a.E * a.W * 4;
     const dim3 grid(a.nty * ntz), block(threads);
+    // paired row mapping (wave-uniform x parity) where the tile shape allows it
+    const bool paired = tu.V == 4 && 64 % a.R == 0 && a.E % (128 / a.R) == 0;
     switch (tu.V) {
-    case 4: launch2<4>(st, a, grid, block, lds); break;
-    case 2: launch2<2>(st, a, grid, block, lds); break;
-    default: launch2<1>(st, a, grid, block, lds); break;
+    case 4:
+        if (paired)
+            launch2<4, true>(st, a, grid, block, lds);
+        else
+            launch2<4, false>(st, a, grid, block, lds);
+        break;
+    case 2: launch2<2, false>(st, a, grid, block, lds); break;
+    default: launch2<1, false>(st, a, grid, block, lds); break;
     }
     return hipGetLastError();
 }

@@ -129,12 +129,14 @@ def test_bit_tunings_match_oracle(qz, orc, L):
 
 
 # (V, Ty, Tz) of the two-sweep pass: ragged y and z tiles, one-plane tiles,
-# tiles whose held rows wrap past L
+# tiles whose held rows wrap past L, and the paired row mapping
 TUNINGS2 = {
     64: [(1, 24, 64), (1, 8, 5), (1, 56, 7), (1, 64, 3)],
     128: [(2, 24, 11), (1, 56, 128), (2, 120, 6), (2, 8, 1)],
     192: [(1, 24, 20), (1, 56, 7)],
-    256: [(4, 24, 32), (2, 56, 10), (4, 24, 256), (4, 8, 9)],
+    256: [(4, 24, 32), (2, 56, 10), (4, 24, 256), (4, 8, 9), (4, 120, 5)],
+    # paired row mapping (wave-uniform x parity): V = 4 with E a multiple of 128 / R
+    512: [(4, 56, 7), (4, 120, 32)],
 }
 
 
