@@ -16,8 +16,6 @@
 // each side, so the tile owns rows [4, E-4) and recomputes the rest, and it
 // recomputes three planes at each z end.  Reads copy A, writes copy B, so
 // tiles never race.  The results are identical to two one-sweep passes.
-#include <type_traits>
-
 #include "qz_bitops.hpp"
 #include "qz_device.hpp"
 #include "qz_internal.hpp"
@@ -39,6 +37,14 @@ struct Sweep2Args {
     uint32_t Ty, E, Tz, nty;            // E = Ty + 8 rows held per tile
     uint32_t k0, k1, t;
 };
+
+template <int V>
+__device__ __forceinline__ void copy_words(uint32_t (&d)[V], const uint32_t (&s)[V])
+{
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        d[v] = s[v];
+}
 
 // CA / CC: add the anti-aligned counts of the owned colour-0 sites of the state
 // entering sweep t (stage A) / sweep t+1 (stage C).
@@ -79,67 +85,53 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
     const size_t plane_words = (size_t)L * W;
     auto off = [&](uint32_t z) -> size_t { return (size_t)z * plane_words + (size_t)y * W + w0; };
 
-    // Register rings.  A step works on plane q = z0 - 3 + s (s = 0, 1, ...);
-    // plane p of a ring sits in slot (p - base) mod size, so no value moves
-    // between registers: the loop is unrolled six times (the ring sizes 6 and
-    // 3 divide 6) and every slot index is a compile-time constant.
-    //   c1r[6]: old colour 1, planes q-1 .. q+3 (q+2, q+3 are loads in flight)
-    //   c0r[3]: old colour 0, planes q .. q+2
-    //   n0r[3]: colour 0 after sweep t, planes q-2 .. q
-    //   n1r[3]: colour 1 after sweep t, planes q-3 .. q-1
-    //   m0r[3]: colour 0 after sweep t+1, planes q-4 .. q-2
-    uint32_t c1r[6][V], c0r[3][V], n0r[3][V], n1r[3][V], m0r[3][V];
+    // register rings, named by plane relative to the step's plane q
+    // old colour 1 of planes q-1, q, q+1 and prefetches of q+2, q+3; old colour
+    // 0 of plane q and prefetches of q+1, q+2 (two steps of loads in flight)
+    uint32_t c1m[V], c1c[V], c1p[V], pf1[V], pg1[V];
+    uint32_t c0o[V], pf0[V], pg0[V];
+    uint32_t n0a[V], n0b[V], n0n[V];           // colour 0 after sweep t: q-1, q-2; new q
+    uint32_t n1a[V], n1b[V], n1n[V];           // colour 1 after sweep t: q-2, q-3; new q-1
+    uint32_t m0a[V], m0b[V], m0n[V];           // colour 0 after sweep t+1: q-3, q-4; new q-2
+    uint32_t m1n[V];                           // colour 1 after sweep t+1: new q-3
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            c1r[k][v] = 0u;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            c0r[k][v] = n0r[k][v] = n1r[k][v] = m0r[k][v] = 0u;
+        c1m[v] = c1c[v] = c1p[v] = pf1[v] = c0o[v] = pf0[v] = pg1[v] = pg0[v] = 0u;
+        n0a[v] = n0b[v] = n0n[v] = n1a[v] = n1b[v] = n1n[v] = 0u;
+        m0a[v] = m0b[v] = m0n[v] = m1n[v] = 0u;
     }
-    if (held) {   // colour 1 planes z0-4 .. z0-1 -> slots 0 .. 3
-        load_words<V>(A.S1 + off((z0 + L - 4) % L), c1r[0]);
-        load_words<V>(A.S1 + off((z0 + L - 3) % L), c1r[1]);
-        load_words<V>(A.S1 + off((z0 + L - 2) % L), c1r[2]);
-        load_words<V>(A.S1 + off((z0 + L - 1) % L), c1r[3]);
+    if (held) {
+        load_words<V>(A.S1 + off((z0 + L - 4) % L), c1m);
+        load_words<V>(A.S1 + off((z0 + L - 3) % L), c1c);
+        load_words<V>(A.S1 + off((z0 + L - 2) % L), c1p);
+        load_words<V>(A.S1 + off((z0 + L - 1) % L), pf1);
     }
-    if (rowA) {   // colour 0 planes z0-3, z0-2 -> slots 0, 1
-        load_words<V>(A.S0 + off((z0 + L - 3) % L), c0r[0]);
-        load_words<V>(A.S0 + off((z0 + L - 2) % L), c0r[1]);
+    if (rowA) {
+        load_words<V>(A.S0 + off((z0 + L - 3) % L), c0o);
+        load_words<V>(A.S0 + off((z0 + L - 2) % L), pf0);
     }
 
     int bonds_a = 0, bonds_c = 0;
     uint32_t flips_a = 0, flips_c = 0;   // accepted flips over owned sites
     const size_t set = (size_t)E * W;   // words of one row set in LDS
-    const int last = (int)Tza + 2;
 
-    // one plane step; PH = (qi + 3) mod 6 fixes the ring slots
-    auto step = [&](auto phase, int qi) {
-        constexpr int PH = decltype(phase)::value;
-        constexpr int S3 = PH % 3;
-        constexpr int c1_m = PH, c1_c = (PH + 1) % 6, c1_p = (PH + 2) % 6, c1_ld = (PH + 4) % 6;
-        constexpr int c0_q = S3, c0_ld = (S3 + 2) % 3;
-        constexpr int n0_q = S3, n0_q1 = (S3 + 2) % 3, n0_q2 = (S3 + 1) % 3;
-        constexpr int n1_q1 = (S3 + 2) % 3, n1_q2 = (S3 + 1) % 3, n1_q3 = S3;
-        constexpr int m0_q2 = (S3 + 1) % 3, m0_q3 = S3, m0_q4 = (S3 + 2) % 3;
-
+    for (int qi = -3; qi <= (int)Tza + 2; ++qi) {
         const uint32_t zq = (z0 + 2 * L + qi) % L;
-        if (qi + 1 < last) {   // two steps ahead: colour 1 plane q+3, colour 0 plane q+2
+        if (qi + 1 < (int)Tza + 2) {
             if (held)
-                load_words<V>(A.S1 + off((zq + 3) % L), c1r[c1_ld]);
+                load_words<V>(A.S1 + off((zq + 3) % L), pg1);
             if (rowA)
-                load_words<V>(A.S0 + off((zq + 2) % L), c0r[c0_ld]);
+                load_words<V>(A.S0 + off((zq + 2) % L), pg0);
         }
         uint32_t *X1 = lds + (size_t)(qi & 1) * 4 * set;   // old colour 1, plane q
         uint32_t *X0 = X1 + set;                            // A's colour 0, plane q-1
         uint32_t *Y1 = X0 + set;                            // B's colour 1, plane q-2
         uint32_t *Y0 = Y1 + set;                            // C's colour 0, plane q-3
         if (held) {
-            store_words<V>(X1 + e * W + w0, c1r[c1_c]);
-            store_words<V>(X0 + e * W + w0, n0r[n0_q1]);
-            store_words<V>(Y1 + e * W + w0, n1r[n1_q2]);
-            store_words<V>(Y0 + e * W + w0, m0r[m0_q3]);
+            store_words<V>(X1 + e * W + w0, c1c);
+            store_words<V>(X0 + e * W + w0, n0a);
+            store_words<V>(Y1 + e * W + w0, n1a);
+            store_words<V>(Y0 + e * W + w0, m0a);
         }
         __syncthreads();
 
@@ -156,14 +148,14 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             const uint32_t adj = X1[e * W + wadj];
             const uint32_t g = (uint32_t)(((size_t)zq * L + y) * W + w0);
             int a_sum = 0;
-            update_words<V, CA>(c0r[c0_q], c1r[c1_c], adj, pi, ym, yp, c1r[c1_m], c1r[c1_p], A.k0,
-                                A.k1, g, g & 3u, A.t, 0u, n0r[n0_q], a_sum);
+            update_words<V, CA>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, A.k0, A.k1, g, g & 3u, A.t,
+                                0u, n0n, a_sum);
             if constexpr (CA)
                 if (rowD && qi >= 0 && qi < (int)Tza) {
                     bonds_a += a_sum;
 #pragma unroll
                     for (int v = 0; v < V; ++v)
-                        flips_a = popc_acc(c0r[c0_q][v] ^ n0r[n0_q][v], flips_a);
+                        flips_a = popc_acc(c0o[v] ^ n0n[v], flips_a);
                 }
         }
         // B: sweep t, colour 1, plane q-1
@@ -175,13 +167,13 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             const uint32_t adj = X0[e * W + wadj];
             const uint32_t g = (uint32_t)(((size_t)zb * L + y) * W + w0);
             int unused = 0;
-            update_words<V, false>(c1r[c1_m], n0r[n0_q1], adj, pi, ym, yp, n0r[n0_q2], n0r[n0_q],
-                                   A.k0, A.k1, g, g & 3u, A.t, 1u, n1r[n1_q1], unused);
+            update_words<V, false>(c1m, n0a, adj, pi, ym, yp, n0b, n0n, A.k0, A.k1, g, g & 3u,
+                                   A.t, 1u, n1n, unused);
             if constexpr (CA)
                 if (rowD && qi >= 1 && qi <= (int)Tza) {
 #pragma unroll
                     for (int v = 0; v < V; ++v)
-                        flips_a = popc_acc(c1r[c1_m][v] ^ n1r[n1_q1][v], flips_a);
+                        flips_a = popc_acc(c1m[v] ^ n1n[v], flips_a);
                 }
         }
         // C: sweep t+1, colour 0, plane q-2
@@ -193,55 +185,49 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             const uint32_t adj = Y1[e * W + wadj];
             const uint32_t g = (uint32_t)(((size_t)zc * L + y) * W + w0);
             int a_sum = 0;
-            update_words<V, CC>(n0r[n0_q2], n1r[n1_q2], adj, pi, ym, yp, n1r[n1_q3], n1r[n1_q1],
-                                A.k0, A.k1, g, g & 3u, A.t + 1u, 0u, m0r[m0_q2], a_sum);
+            update_words<V, CC>(n0b, n1a, adj, pi, ym, yp, n1b, n1n, A.k0, A.k1, g, g & 3u,
+                                A.t + 1u, 0u, m0n, a_sum);
             if (rowD && qi >= 2 && qi < (int)Tza + 2) {
                 if constexpr (CC) {
                     bonds_c += a_sum;
 #pragma unroll
                     for (int v = 0; v < V; ++v)
-                        flips_c = popc_acc(n0r[n0_q2][v] ^ m0r[m0_q2][v], flips_c);
+                        flips_c = popc_acc(n0b[v] ^ m0n[v], flips_c);
                 }
-                store_words_nt<V>(A.D0 + off(zc), m0r[m0_q2]);
+                store_words_nt<V>(A.D0 + off(zc), m0n);
             }
         }
         // D: sweep t+1, colour 1, plane q-3
         if (rowD && qi >= 3) {
             const uint32_t zd = (zq + L - 3) % L;
-            uint32_t ym[V], yp[V], m1n[V];
+            uint32_t ym[V], yp[V];
             load_words<V>(Y0 + em * W + w0, ym);
             load_words<V>(Y0 + ep * W + w0, yp);
             const uint32_t adj = Y0[e * W + wadj];
             const uint32_t g = (uint32_t)(((size_t)zd * L + y) * W + w0);
             int unused = 0;
-            update_words<V, false>(n1r[n1_q3], m0r[m0_q3], adj, pi, ym, yp, m0r[m0_q4], m0r[m0_q2],
-                                   A.k0, A.k1, g, g & 3u, A.t + 1u, 1u, m1n, unused);
+            update_words<V, false>(n1b, m0a, adj, pi, ym, yp, m0b, m0n, A.k0, A.k1, g, g & 3u,
+                                   A.t + 1u, 1u, m1n, unused);
             if constexpr (CC) {
 #pragma unroll
                 for (int v = 0; v < V; ++v)
-                    flips_c = popc_acc(n1r[n1_q3][v] ^ m1n[v], flips_c);
+                    flips_c = popc_acc(n1b[v] ^ m1n[v], flips_c);
             }
             store_words_nt<V>(A.D1 + off(zd), m1n);
         }
-    };
-
-    for (int qi = -3; qi <= last; qi += 6) {
-        step(std::integral_constant<int, 0>{}, qi);
-        if (qi + 1 > last)
-            break;
-        step(std::integral_constant<int, 1>{}, qi + 1);
-        if (qi + 2 > last)
-            break;
-        step(std::integral_constant<int, 2>{}, qi + 2);
-        if (qi + 3 > last)
-            break;
-        step(std::integral_constant<int, 3>{}, qi + 3);
-        if (qi + 4 > last)
-            break;
-        step(std::integral_constant<int, 4>{}, qi + 4);
-        if (qi + 5 > last)
-            break;
-        step(std::integral_constant<int, 5>{}, qi + 5);
+        // advance the rings by one plane
+        copy_words<V>(c1m, c1c);
+        copy_words<V>(c1c, c1p);
+        copy_words<V>(c1p, pf1);
+        copy_words<V>(c0o, pf0);
+        copy_words<V>(pf1, pg1);
+        copy_words<V>(pf0, pg0);
+        copy_words<V>(n0b, n0a);
+        copy_words<V>(n0a, n0n);
+        copy_words<V>(n1b, n1a);
+        copy_words<V>(n1a, n1n);
+        copy_words<V>(m0b, m0a);
+        copy_words<V>(m0a, m0n);
     }
 
     if constexpr (CA || CC) {
