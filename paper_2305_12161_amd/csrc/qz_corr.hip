@@ -27,6 +27,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kG = 8;             // separations per register block
 constexpr int kItems = 2;         // work items per thread in k_corr_lines
+constexpr int kFill = 8;          // loads in flight per thread while filling LDS
 constexpr size_t kLineLds = 56 * 1024;
 
 struct LineGeom {
@@ -90,17 +91,44 @@ __global__ void __launch_bounds__(kBlock) k_corr_lines(LineGeom g, const uint32_
         const uint32_t o = tile / ytiles;
         const uint32_t Y = (tile % ytiles) * Cy;
         __syncthreads();
-        // fill: this thread always loads column fcw; rows advance by frows
+        // fill: this thread always loads column fcw; rows advance by frows.
+        // Loads go out in batches of kFill before any is stored, so a wave
+        // has kFill loads in flight instead of one.
         if (fill_active) {
             const uint32_t *col = fP + (AX == 1 ? (size_t)o * plane : (size_t)o * W);
-            for (uint32_t s = fs0; s < Cy; s += frows)          // A: rows Y .. Y+Cy-1, no wrap
-                A[fcw * PA + s] = col[(size_t)(Y + s) * ustride];
-            uint32_t u = (Y + r_base + fs0) % L;                  // B: rows from Y + r_base, wrapping
-            for (uint32_t s = fs0; s < Cy + g.Rr; s += frows) {
-                B[fcw * PB + s] = col[(size_t)u * ustride];
-                u += frows;
-                while (u >= L)   // frows may exceed L for small lattices
-                    u -= L;
+            for (uint32_t s = fs0; s < Cy; s += kFill * frows) {   // A: rows Y .. Y+Cy-1
+                uint32_t v[kFill];
+#pragma unroll
+                for (int j = 0; j < kFill; ++j) {
+                    const uint32_t sj = s + j * frows;
+                    v[j] = sj < Cy ? col[(size_t)(Y + sj) * ustride] : 0u;
+                }
+#pragma unroll
+                for (int j = 0; j < kFill; ++j) {
+                    const uint32_t sj = s + j * frows;
+                    if (sj < Cy)
+                        A[fcw * PA + sj] = v[j];
+                }
+            }
+            const uint32_t nb = Cy + g.Rr;                       // B: rows from Y + r_base, wrapping
+            const uint32_t fr = frows % L;
+            for (uint32_t s = fs0; s < nb; s += kFill * frows) {
+                uint32_t v[kFill];
+                uint32_t u = (Y + r_base + s) % L;
+#pragma unroll
+                for (int j = 0; j < kFill; ++j) {
+                    const uint32_t sj = s + j * frows;
+                    v[j] = sj < nb ? col[(size_t)u * ustride] : 0u;
+                    u += fr;
+                    if (u >= L)
+                        u -= L;
+                }
+#pragma unroll
+                for (int j = 0; j < kFill; ++j) {
+                    const uint32_t sj = s + j * frows;
+                    if (sj < nb)
+                        B[fcw * PB + sj] = v[j];
+                }
             }
         }
         __syncthreads();
