@@ -28,6 +28,8 @@ constexpr int kBlock = 256;
 constexpr int kG = 8;             // separations per register block
 constexpr int kItems = 2;         // work items per thread in k_corr_lines
 constexpr int kFill = 8;          // loads in flight per thread while filling LDS
+constexpr int kPipeA = 16;        // prefetched rows of region A per thread
+constexpr int kPipeB = 32;        // prefetched rows of region B per thread
 constexpr size_t kLineLds = 56 * 1024;
 
 struct LineGeom {
@@ -87,51 +89,90 @@ __global__ void __launch_bounds__(kBlock) k_corr_lines(LineGeom g, const uint32_
         for (int d = 0; d < kG; ++d)
             acc[k][d] = 0u;
 
+    // The LDS fill of tile t+1 is loaded into registers while tile t is being
+    // counted (kPipeA + kPipeB words per thread), so the loads' latency hides
+    // behind the arithmetic; larger fills fall back to batched loads.
+    const uint32_t nb = Cy + g.Rr;                       // rows of region B
+    const uint32_t fr = frows % L;
+    const uint32_t na = fill_active ? (Cy > fs0 ? (Cy - fs0 + frows - 1) / frows : 0u) : 0u;
+    const uint32_t nbb = fill_active ? (nb > fs0 ? (nb - fs0 + frows - 1) / frows : 0u) : 0u;
+    const bool pipelined = __syncthreads_and(na <= (uint32_t)kPipeA && nbb <= (uint32_t)kPipeB);
+    uint32_t va[kPipeA], vb[kPipeB];
+    auto fetch = [&](uint32_t tile) {
+        const uint32_t o = tile / ytiles;
+        const uint32_t Y = (tile % ytiles) * Cy;
+        const uint32_t *col = fP + (AX == 1 ? (size_t)o * plane : (size_t)o * W);
+#pragma unroll
+        for (int j = 0; j < kPipeA; ++j)
+            va[j] = (uint32_t)j < na ? col[(size_t)(Y + fs0 + j * frows) * ustride] : 0u;
+        uint32_t u = (Y + r_base + fs0) % L;
+#pragma unroll
+        for (int j = 0; j < kPipeB; ++j) {
+            vb[j] = (uint32_t)j < nbb ? col[(size_t)u * ustride] : 0u;
+            u += fr;
+            if (u >= L)
+                u -= L;
+        }
+    };
+    if (pipelined && split < ntiles)
+        fetch(split);
+
     for (uint32_t tile = split; tile < ntiles; tile += g.nsplit) {
         const uint32_t o = tile / ytiles;
         const uint32_t Y = (tile % ytiles) * Cy;
         __syncthreads();
-        // fill: this thread always loads column fcw; rows advance by frows.
-        // Loads go out in batches of kFill before any is stored, so a wave
-        // has kFill loads in flight instead of one.
-        if (fill_active) {
-            const uint32_t *col = fP + (AX == 1 ? (size_t)o * plane : (size_t)o * W);
-            for (uint32_t s = fs0; s < Cy; s += kFill * frows) {   // A: rows Y .. Y+Cy-1
-                uint32_t v[kFill];
+        if (pipelined) {
 #pragma unroll
-                for (int j = 0; j < kFill; ++j) {
-                    const uint32_t sj = s + j * frows;
-                    v[j] = sj < Cy ? col[(size_t)(Y + sj) * ustride] : 0u;
+            for (int j = 0; j < kPipeA; ++j)
+                if ((uint32_t)j < na)
+                    A[fcw * PA + fs0 + j * frows] = va[j];
+#pragma unroll
+            for (int j = 0; j < kPipeB; ++j)
+                if ((uint32_t)j < nbb)
+                    B[fcw * PB + fs0 + j * frows] = vb[j];
+            __syncthreads();
+            if (tile + g.nsplit < ntiles)
+                fetch(tile + g.nsplit);
+        } else {
+            // fill: this thread always loads column fcw; rows advance by frows,
+            // in batches of kFill loads before any is stored
+            if (fill_active) {
+                const uint32_t *col = fP + (AX == 1 ? (size_t)o * plane : (size_t)o * W);
+                for (uint32_t s = fs0; s < Cy; s += kFill * frows) {   // A: rows Y .. Y+Cy-1
+                    uint32_t v[kFill];
+#pragma unroll
+                    for (int j = 0; j < kFill; ++j) {
+                        const uint32_t sj = s + j * frows;
+                        v[j] = sj < Cy ? col[(size_t)(Y + sj) * ustride] : 0u;
+                    }
+#pragma unroll
+                    for (int j = 0; j < kFill; ++j) {
+                        const uint32_t sj = s + j * frows;
+                        if (sj < Cy)
+                            A[fcw * PA + sj] = v[j];
+                    }
                 }
+                for (uint32_t s = fs0; s < nb; s += kFill * frows) {   // B: from Y + r_base, wrapping
+                    uint32_t v[kFill];
+                    uint32_t u = (Y + r_base + s) % L;
 #pragma unroll
-                for (int j = 0; j < kFill; ++j) {
-                    const uint32_t sj = s + j * frows;
-                    if (sj < Cy)
-                        A[fcw * PA + sj] = v[j];
+                    for (int j = 0; j < kFill; ++j) {
+                        const uint32_t sj = s + j * frows;
+                        v[j] = sj < nb ? col[(size_t)u * ustride] : 0u;
+                        u += fr;
+                        if (u >= L)
+                            u -= L;
+                    }
+#pragma unroll
+                    for (int j = 0; j < kFill; ++j) {
+                        const uint32_t sj = s + j * frows;
+                        if (sj < nb)
+                            B[fcw * PB + sj] = v[j];
+                    }
                 }
             }
-            const uint32_t nb = Cy + g.Rr;                       // B: rows from Y + r_base, wrapping
-            const uint32_t fr = frows % L;
-            for (uint32_t s = fs0; s < nb; s += kFill * frows) {
-                uint32_t v[kFill];
-                uint32_t u = (Y + r_base + s) % L;
-#pragma unroll
-                for (int j = 0; j < kFill; ++j) {
-                    const uint32_t sj = s + j * frows;
-                    v[j] = sj < nb ? col[(size_t)u * ustride] : 0u;
-                    u += fr;
-                    if (u >= L)
-                        u -= L;
-                }
-#pragma unroll
-                for (int j = 0; j < kFill; ++j) {
-                    const uint32_t sj = s + j * frows;
-                    if (sj < nb)
-                        B[fcw * PB + sj] = v[j];
-                }
-            }
+            __syncthreads();
         }
-        __syncthreads();
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
             const uint32_t it = threadIdx.x + k * kBlock;
