@@ -171,9 +171,27 @@ def cpu_baseline(L, seed, budget_s=15.0):
         T += chunk
         chunk = min(chunk * 2, 512)
     attempts = (W - 2) ** 3 * T
+    # the same replay on one thread, for a shorter time
+    oracle.set_threads(1)
+    T1, dt1, chunk = 0, 0.0, 1
+    while dt1 < budget_s / 4:
+        t0 = time.perf_counter()
+        oracle.window_advance(L, seed, (0, 0, 0), w, 1 + T + T1, chunk)
+        dt1 += time.perf_counter() - t0
+        T1 += chunk
+        chunk = min(chunk * 2, 64)
+    oracle.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": attempts / (dt * 1e9), "unit": "attempts/ns", "cores": used, "kind": "oracle",
+            "value_1_thread": (W - 2) ** 3 * T1 / (dt1 * 1e9), "cpu_model": model,
             "sample": f"oracle window replay: {W}^3 cube of the L={L} seed-{seed} start, "
-                      f"sweeps 1..{T}, {(W - 2) ** 3} sites updated per sweep, {dt:.1f} s"}
+                      f"sweeps 1..{T}, {(W - 2) ** 3} sites updated per sweep, {dt:.1f} s on "
+                      f"{used} threads; then {T1} more sweeps on 1 thread, {dt1:.1f} s"}
 
 
 def main():

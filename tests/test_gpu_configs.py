@@ -176,3 +176,53 @@ def test_physics_band_ell_L256(qz):
     mean = float(np.mean(ells))
     print("ell_C at t =", t, ells, "mean", mean, flush=True)
     assert 0.7 * band["mean_ell_checkerboard"] < mean < 1.3 * band["mean_ell_checkerboard"]
+
+
+def test_config4_batch_all_replicas(qz, orc):
+    """The 584-replica batch (512 x L64 + 64 x L128 + 8 x L256, seeds
+    0x40000000 + r, B every 10 MCS): after 10^3 MCS every replica equals the
+    same (L, seed) run alone on the GPU; after 10^4 MCS 16 L64 and 2 L128
+    replicas equal the oracle's full runs, and one L256 replica equals the
+    oracle at 10^3 MCS and in a window replay at 10^4 MCS."""
+    specs = [(r.L, r.seed) for r in wl.batch_config4()]
+    every, t1, t2 = 10, 1000, 10_000
+    b = qz.Batch(specs, trace_every=every, trace_cap=t2 // every + 8)
+    b.set_tuning(64, 0, 100)
+    b.run(t1)
+    b.sync()
+    print("config4 batch at t=1000: checking", len(specs), "replicas", flush=True)
+    at_t1 = {}
+    for slot, (L, seed) in enumerate(specs):
+        lat = qz.Lattice(L, seed, "bit")
+        tr = lat.run(t1, every)
+        assert np.array_equal(b.trace(slot, 0, t1 // every), tr), (slot, L)
+        s = b.download(slot)
+        assert np.array_equal(s, lat.download()), (slot, L)
+        if L == 256 and slot == len(specs) - 1:
+            at_t1[slot] = s
+        del lat
+    b.run(t2 - t1)
+    b.sync()
+    print("config4 batch at t=1e4: oracle comparisons", flush=True)
+    picks = [k * 32 for k in range(16)] + [512, 575]          # 16 L64, 2 L128
+    for slot in picks:
+        L, seed = specs[slot]
+        s = orc.init(L, seed)
+        want = orc.run(s, seed, 0, t2, every)
+        assert np.array_equal(b.trace(slot, 0, t2 // every).astype(np.int64), want), slot
+        assert np.array_equal(b.download(slot), s), slot
+    slot = len(specs) - 1
+    L, seed = specs[slot]
+    s = orc.init(L, seed)
+    orc.run(s, seed, 0, t1)
+    assert np.array_equal(at_t1[slot], s)
+    # window replay of 8 more sweeps of the L256 replica from t = 1e4
+    o, W, T = (17, 200, 90), 64, 8
+    idx = [(np.arange(W) + c) % L for c in o]
+    w = np.ascontiguousarray(b.download(slot)[np.ix_(idx[2], idx[1], idx[0])])
+    orc.window_advance(L, seed, o, w, t2, T)
+    b.run(T)
+    b.sync()
+    got_w = b.download(slot)[np.ix_(idx[2], idx[1], idx[0])]
+    m = 2 * T
+    assert np.array_equal(w[m:W - m, m:W - m, m:W - m], got_w[m:W - m, m:W - m, m:W - m])
