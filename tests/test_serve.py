@@ -100,3 +100,40 @@ def test_served_results_equal_alone():
         tr = lat.run(r.t_max, every).astype(np.int64)
         assert np.array_equal(r.trace, tr), (r.idx, r.L)
         assert r.final_B == int(lat.bonds().sum())
+
+
+@pytest.mark.gpu
+def test_served_config5_stream_prefix(orc):
+    """The first 120 requests of the served stream (L uniform in {64, 96, 128,
+    192, 256, 384, 512}, t_max in {1e3, 1e4}, seeds 0x50000000 + idx), all
+    queued at once on the configured memory budget and batch slots: every
+    result equals the request run alone, and 20 of those with L <= 128 equal
+    the oracle."""
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_12161_amd import binding
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    reqs = wl.request_stream(n=2000, rate_per_s=wl.SERVE_RATE_PER_S)[:120]
+    every, chunk = 100, 100
+    be = serve.GpuBackend(budget_bytes=wl.SERVE_BUDGET_BYTES, batch_slots=wl.SERVE_BATCH_SLOTS,
+                          every=every, chunk=chunk)
+    res = serve.Server(be, chunk=chunk).serve(reqs, time_scale=0.0)
+    assert [r.idx for r in res] == [q.idx for q in reqs]
+    small = []
+    for r in res:
+        layout = "bit" if r.L % 64 == 0 else "i8"
+        lat = binding.Lattice(r.L, r.seed, layout)
+        tr = lat.run(r.t_max, every).astype(np.int64)
+        assert np.array_equal(r.trace, tr), (r.idx, r.L)
+        assert r.final_B == int(lat.bonds().sum()), r.idx
+        if r.L <= 128 and len(small) < 20:
+            small.append(r)
+        del lat
+    print("served prefix: oracle on", len(small), "requests", flush=True)
+    for r in small:
+        s = orc.init(r.L, r.seed)
+        want = orc.run(s, r.seed, 0, r.t_max, every)
+        assert np.array_equal(r.trace, want), (r.idx, r.L)
+        assert r.final_B == int(orc.bonds(s).sum()), r.idx
