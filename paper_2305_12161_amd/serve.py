@@ -11,7 +11,8 @@ Backends:
   * GpuBackend -- the HIP library: lattice sizes the batched engine takes
     (L % 64 == 0, L <= 256) live in fixed batch slots advanced by one graph
     replay per chunk; other sizes run as single lattices (the 1-bit layout when
-    L % 64 == 0, else int8), all on one stream.
+    L % 64 == 0, else int8) spread over a few streams so that their short
+    sweeps overlap.
   * Any object with the same methods (tests use a CPU one).
 
 Results never depend on what else is running: every lattice follows exactly
@@ -52,7 +53,8 @@ class GpuBackend:
     """
 
     def __init__(self, budget_bytes: int, batch_slots: Dict[int, int], every: int, chunk: int,
-                 t_max_cap: int = 10_000, device=None, graph_sweeps: Optional[int] = None):
+                 t_max_cap: int = 10_000, device=None, graph_sweeps: Optional[int] = None,
+                 single_streams: int = 4):
         import torch
         from . import binding
         self.qz = binding
@@ -60,6 +62,10 @@ class GpuBackend:
         self.every, self.chunk = every, chunk
         self.device = torch.device("cuda") if device is None else torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
+        # single lattices are spread over a few streams (default priority) so
+        # that the short sweeps of mid-size lattices overlap on the GPU
+        self.single_streams = [torch.cuda.Stream(device=self.device) for _ in range(single_streams)]
+        self._next_stream = 0
         specs = []
         for L in sorted(batch_slots):
             for _ in range(batch_slots[L]):
@@ -102,9 +108,14 @@ class GpuBackend:
             self.batch.reset(slot, req.seed)
             self.live[req.idx] = {"kind": "batch", "slot": slot, "t": 0, "t_max": req.t_max}
             return
+        st = self.single_streams[self._next_stream % len(self.single_streams)] \
+            if self.single_streams else self.stream
+        self._next_stream += 1
+        # the library zeroes each trace chunk on the lattice's stream before
+        # writing it; every earlier use of this memory ended at the last sync()
+        tr = self.torch.empty(req.t_max // self.every, dtype=self.torch.int64, device=self.device)
         lat = self.qz.Lattice(req.L, req.seed, self.layout_for(req.L), device=self.device,
-                              stream=self.stream)
-        tr = self.torch.zeros(req.t_max // self.every, dtype=self.torch.int64, device=self.device)
+                              stream=st)
         self.single_used += self.single_bytes(req.L)
         self.live[req.idx] = {"kind": "single", "lat": lat, "trace": tr, "t": 0,
                               "t_max": req.t_max, "bytes": self.single_bytes(req.L)}
