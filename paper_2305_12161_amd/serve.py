@@ -54,7 +54,7 @@ class GpuBackend:
 
     def __init__(self, budget_bytes: int, batch_slots: Dict[int, int], every: int, chunk: int,
                  t_max_cap: int = 10_000, device=None, graph_sweeps: Optional[int] = None,
-                 single_streams: int = 4):
+                 single_streams: int = 8, single_pass: int = 2):
         import torch
         from . import binding
         self.qz = binding
@@ -66,6 +66,9 @@ class GpuBackend:
         # that the short sweeps of mid-size lattices overlap on the GPU
         self.single_streams = [torch.cuda.Stream(device=self.device) for _ in range(single_streams)]
         self._next_stream = 0
+        # sweeps per pass of the single bit lattices (two halves the launches
+        # per chunk; the trajectories are the same)
+        self.single_pass = single_pass
         specs = []
         for L in sorted(batch_slots):
             for _ in range(batch_slots[L]):
@@ -116,6 +119,8 @@ class GpuBackend:
         tr = self.torch.empty(req.t_max // self.every, dtype=self.torch.int64, device=self.device)
         lat = self.qz.Lattice(req.L, req.seed, self.layout_for(req.L), device=self.device,
                               stream=st)
+        if self.layout_for(req.L) == "bit" and self.single_pass:
+            lat.set_pass(self.single_pass)
         self.single_used += self.single_bytes(req.L)
         self.live[req.idx] = {"kind": "single", "lat": lat, "trace": tr, "t": 0,
                               "t_max": req.t_max, "bytes": self.single_bytes(req.L)}
