@@ -277,8 +277,8 @@ int qz_batch_download(qz_batch *b, size_t slot, int8_t *host);
 int qz_batch_bonds(qz_batch *b, size_t slot, uint64_t out_B_axes[3]);
 int qz_batch_corr(qz_batch *b, size_t slot, int64_t *out_S, int64_t *out_M);
 
-/* Planes per sub-tile for slots of side L (Tz divides L, Tz >= 8; 0 keeps the
- * current value) and sweeps per captured graph (0 = no graph; at most
+/* Planes per sub-tile for slots of side L (Tz divides L; 0 keeps the current
+ * value; default 8) and sweeps per captured graph (0 = no graph; at most
  * trace_cap * trace_every, larger values are reduced to that, so that one
  * graph never reuses a ring entry).  Results never depend on it. */
 int qz_batch_set_tuning(qz_batch *b, uint32_t L, uint32_t Tz, uint32_t graph_sweeps);

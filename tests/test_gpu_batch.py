@@ -51,7 +51,7 @@ def test_batch_tunings_agree(qz):
     ref = qz.Batch(MIX[:5], trace_every=2, trace_cap=16)
     ref.run(n)
     ref.sync()
-    for tz in ((64, 8), (128, 32), (256, 64), (192, 16)):
+    for tz in ((64, 8), (128, 32), (256, 64), (192, 16), (64, 2), (128, 4), (256, 1), (192, 3)):
         b = qz.Batch(MIX[:5], trace_every=2, trace_cap=16)
         b.set_tuning(tz[0], tz[1], 5)
         b.run(n)
@@ -129,3 +129,6 @@ def test_batch_rejects_bad_sizes(qz):
         qz.Batch([(96, 1)])
     with pytest.raises(qz.QuenchError):
         qz.Batch([(320, 1)])
+    b = qz.Batch([(64, 1)])
+    with pytest.raises(qz.QuenchError):
+        b.set_tuning(64, 3, 5)       # Tz must divide L
