@@ -30,6 +30,7 @@ struct qz_batch {
     qz::BatchTile *d_tiles;
     qz::BatchGroup *d_groups;
     uint32_t ntiles, ngroups;
+    size_t max_tiles, max_groups;            // capacity of the device tile / group tables
     size_t lds_bytes;
     int8_t *stage;
     size_t stage_bytes;
@@ -80,8 +81,9 @@ struct Layout {
     size_t max_tiles, max_groups;
 };
 
-// Device layout for a slot list; sizes of the tile/group tables are bounded by
-// the smallest plane count per sub-tile (8).
+// Device layout for a slot list.  The tile and group tables are sized for the
+// smallest plane count per sub-tile (one plane): L tiles per replica at most,
+// and never more groups than tiles.
 bool plan(const qz_replica_spec *specs, size_t n, uint32_t cap, Layout *lay)
 {
     size_t off = 0;
@@ -95,7 +97,7 @@ bool plan(const qz_replica_spec *specs, size_t n, uint32_t cap, Layout *lay)
         lay->rep_off[i] = off;
         off += replica_bytes(L);
         lay->max_L = std::max(lay->max_L, L);
-        lay->max_tiles += (L + 7) / 8;
+        lay->max_tiles += L;
     }
     lay->max_groups = lay->max_tiles;
     lay->reps_off = off;
@@ -146,6 +148,8 @@ int build_tables(qz_batch *b)
             groups.push_back(g);
         }
     }
+    if (tiles.size() > b->max_tiles || groups.size() > b->max_groups)
+        return fail(QZ_EINVAL, "tile tables exceed their capacity");
     b->ntiles = (uint32_t)tiles.size();
     b->ngroups = (uint32_t)groups.size();
     BZ_HIP(b, hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(qz::BatchTile),
@@ -313,6 +317,8 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
     b->d_reps = reinterpret_cast<qz::BatchReplica *>(b->base + lay.reps_off);
     b->d_tiles = reinterpret_cast<qz::BatchTile *>(b->base + lay.tiles_off);
     b->d_groups = reinterpret_cast<qz::BatchGroup *>(b->base + lay.groups_off);
+    b->max_tiles = lay.max_tiles;
+    b->max_groups = lay.max_groups;
     b->stage = reinterpret_cast<int8_t *>(b->base + lay.stage_off);
     b->stage_bytes = lay.stage_bytes;
     b->counters = reinterpret_cast<unsigned long long *>(b->base + lay.counters_off);
