@@ -111,15 +111,16 @@ __device__ __forceinline__ uint32_t up_rule(uint32_t s, const UpCount &u, uint32
     return (up_tie(u) & (s ^ r)) | u.u2;
 }
 
-// Sum of the anti-aligned counts a over the 32 sites:
-// sum a = sum over down sites of U + sum over up sites of (6 - U)
-//       = 6 popc(s) + sum_j 2^j (popc(u_j) - 2 popc(s & u_j)).
+// Sum of the anti-aligned counts a over the 32 sites.  A down site has a = U,
+// an up site a = 6 - U; bit-sliced, a = (a2 a1 a0) with a0 = u0 (U and 6 - U
+// have the same parity), a1 = u1 ^ (s & ~u0) and a2 = u2 ^ (s & ~(u1 & u0))
+// (6 - U = ~U - 1 on three bits), so sum a = popc(a0) + 2 popc(a1) + 4 popc(a2).
 __device__ __forceinline__ int up_antialigned_sum(uint32_t s, const UpCount &u)
 {
-    const int p0 = __builtin_popcount(u.u0) - 2 * __builtin_popcount(s & u.u0);
-    const int p1 = __builtin_popcount(u.u1) - 2 * __builtin_popcount(s & u.u1);
-    const int p2 = __builtin_popcount(u.u2) - 2 * __builtin_popcount(s & u.u2);
-    return 6 * __builtin_popcount(s) + p0 + 2 * p1 + 4 * p2;
+    const uint32_t a1 = u.u1 ^ (s & ~u.u0);
+    const uint32_t a2 = u.u2 ^ (s & ~(u.u1 & u.u0));
+    return (int)(__builtin_popcount(u.u0) + 2 * __builtin_popcount(a1) +
+                 4 * __builtin_popcount(a2));
 }
 
 // ---------------------------------------------------------------------------
