@@ -1,11 +1,13 @@
 """Autotuner for the sweep kernels: times candidate tilings on the device and
 keeps the fastest.  Results never depend on the tuning, only speed does.
 
-    python -m paper_2305_12161_amd.tune --L 2048            # single lattice
+    python -m paper_2305_12161_amd.tune --L 2048            # single lattice, both passes
     python -m paper_2305_12161_amd.tune --batch-config4     # batched replicas
 
-Winners are written to tuned.json next to this file; `best_single(L)` and
-`best_batch(L)` read them back (None when a size was never tuned).
+Winners are written to tuned.json next to this file; `best_single(L)`,
+`best_pass2(L)` and `best_batch(L)` read them back (None when a size was never
+tuned).  The library's own defaults come from the same measurements and need
+no cache.
 """
 import argparse
 import json
@@ -35,6 +37,11 @@ def best_single(L: int):
     return tuple(v["tuning"]) if v else None
 
 
+def best_pass2(L: int):
+    v = _load().get("pass2", {}).get(str(L))
+    return tuple(v["tuning"]) if v else None
+
+
 def best_batch(L: int):
     v = _load()["batch"].get(str(L))
     return (v["Tz"], v["graph_sweeps"]) if v else None
@@ -54,10 +61,53 @@ def single_candidates(L: int):
                 rows.append(E - 4)
             E *= 2
         for Ty in rows:
-            for Tz in (16, 32, 64, 128):
+            for Tz in (4, 8, 16, 32, 64):
                 if Tz <= L:
                     out.append((V, Ty, Tz))
     return out
+
+
+def pass2_candidates(L: int):
+    """(V, Ty, Tz) of the two-sweep pass: Ty + 8 rows held per tile."""
+    W = L // 64
+    out = []
+    for V in (4, 2, 1):
+        if W % V:
+            continue
+        for Ty in (8, 24, 56, 120):
+            for Tz in (8, 16, 32, 64):
+                if Ty <= L and Tz <= L:
+                    out.append((V, Ty, Tz))
+    return out
+
+
+def tune_pass2(L: int, sweeps: int = 30, verbose: bool = True):
+    import torch
+    from . import binding
+    st = torch.cuda.current_stream()
+    best = None
+    lat = binding.Lattice(L, 11, "bit")
+    for cand in pass2_candidates(L):
+        try:
+            lat.set_pass(2, *cand)
+        except binding.QuenchError:
+            continue
+        lat.run(4)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        lat.run(sweeps)
+        b.record(st)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / sweeps
+        if verbose:
+            print(json.dumps({"L": L, "pass2": cand, "ms_per_sweep": round(ms, 5)}), flush=True)
+        if best is None or ms < best[1]:
+            best = (cand, ms)
+    d = _load()
+    d.setdefault("pass2", {})[str(L)] = {"tuning": list(best[0]), "ms_per_sweep": round(best[1], 5)}
+    _save(d)
+    return best
 
 
 def tune_single(L: int, sweeps: int = 30, verbose: bool = True):
@@ -66,6 +116,7 @@ def tune_single(L: int, sweeps: int = 30, verbose: bool = True):
     st = torch.cuda.current_stream()
     best = None
     lat = binding.Lattice(L, 11, "bit")
+    lat.set_pass(1)
     for cand in single_candidates(L):
         try:
             lat.set_tuning(*cand)
@@ -97,7 +148,7 @@ def tune_batch(specs, sweeps: int = 200, verbose: bool = True):
     chosen = {L: None for L in sizes}
     results = {}
     for L in sizes:
-        for Tz in (8, 16, 32, 64):
+        for Tz in (2, 4, 8, 16, 32):
             if Tz > L or L % Tz:
                 continue
             b = binding.Batch(specs)
@@ -148,7 +199,8 @@ def main():
     ap.add_argument("--batch-config4", action="store_true")
     args = ap.parse_args()
     for L in args.L:
-        print(json.dumps({"L": L, "best": tune_single(L)}), flush=True)
+        print(json.dumps({"L": L, "best_one_sweep": tune_single(L)}), flush=True)
+        print(json.dumps({"L": L, "best_two_sweep": tune_pass2(L)}), flush=True)
     if args.batch_config4:
         from . import workloads
         specs = [(r.L, r.seed) for r in workloads.batch_config4()]
