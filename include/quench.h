@@ -38,7 +38,8 @@
  * Conventions for every entry point:
  *   Memory   -- device memory is owned by the caller (e.g. a torch tensor) and
  *               must outlive the handle; the library allocates no device
- *               memory.  Host arrays are caller-allocated.
+ *               memory of its own (the FFT plans made by qz_fft_prepare hold
+ *               hipFFT's internal tables).  Host arrays are caller-allocated.
  *   Streams  -- all device work is enqueued on the stream given at creation.
  *               Calls that return host data synchronise that stream; the others
  *               are asynchronous.
@@ -148,8 +149,9 @@ int qz_download_window(qz_lattice *q, const uint32_t origin[3], uint32_t W, int8
  * lane along x (1, 2 or 4, dividing L/64), Ty rows of y per tile (Ty == L
  * means whole planes with no halo rows) and Tz planes of z per tile.  Results
  * never depend on the tuning.  QZ_EINVAL if the triple does not fit this L
- * (at most 1024 threads and 64 KiB of LDS per workgroup); QZ_EUNSUPPORTED for
- * the int8 layout, which has no tuning. */
+ * (at most 1024 threads and 60 KiB of LDS per workgroup); QZ_EUNSUPPORTED for
+ * the int8 layout, which has no tuning.  Default: whole planes (Tz = 8) up to
+ * L = 128, else tiles of 28 owned rows (fewer for long rows) and Tz = 8. */
 int qz_set_tuning(qz_lattice *q, int V, int Ty, int Tz);
 int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
 
