@@ -260,7 +260,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t = W
-    for tc in corr_times + [W + K]:
+    for tc in sorted(set(corr_times + [W + K])):
         advance(t, tc, timing)
         t = tc
         if tc in corr_times:
