@@ -226,3 +226,28 @@ def test_config4_batch_all_replicas(qz, orc):
     got_w = b.download(slot)[np.ix_(idx[2], idx[1], idx[0])]
     m = 2 * T
     assert np.array_equal(w[m:W - m, m:W - m, m:W - m], got_w[m:W - m, m:W - m, m:W - m])
+
+
+def test_largest_lattice_L4096(qz, orc):
+    """The largest side the bit layout takes (L = 4096, 6.9e10 sites): one- and
+    two-sweep passes agree on the bond trace and the state, and windows of
+    the start and of t = 6 equal the oracle's."""
+    L, seed, n = 4096, 41, 6
+    two = qz.Lattice(L, seed, "bit")
+    print("L4096 defaults", two.tuning(), two.pass_config(), flush=True)
+    o, W = (4000, 17, 2050), 48
+    w = orc.init_window(L, seed, o, W)
+    assert np.array_equal(two.window(o, W), w)
+    tr2 = two.run(n, 2)
+    orc.window_advance(L, seed, o, w, 0, n)
+    got = two.window(o, W)
+    m = 2 * n
+    assert np.array_equal(w[m:W - m, m:W - m, m:W - m], got[m:W - m, m:W - m, m:W - m])
+    one = qz.Lattice(L, seed, "bit")
+    one.set_pass(1)
+    tr1 = one.run(n, 2)
+    assert np.array_equal(tr1, tr2)
+    for oo in ((0, 0, 0), (4095, 4095, 4095), (1234, 2345, 3456)):
+        assert np.array_equal(one.window(oo, 32), two.window(oo, 32))
+    S, M = two.corr()
+    check_identities(two, S, M, L ** 3)
