@@ -26,7 +26,8 @@ namespace {
 using bitops::load_words;
 using bitops::store_words;
 using bitops::store_words_nt;
-using bitops::update_words;
+using bitops::rule_words;
+using bitops::tie_words;
 
 struct Sweep2Args {
     const uint32_t *S0, *S1;            // read copy, colour planes 0 and 1
@@ -84,6 +85,8 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
     const uint32_t wprev = (w0 + W - 1) % W, wnext = (w0 + V) % W;
     const size_t plane_words = (size_t)L * W;
     auto off = [&](uint32_t z) -> size_t { return (size_t)z * plane_words + (size_t)y * W + w0; };
+    // first word of the lane in the colour-index order that keys the tie bits
+    auto gword = [&](uint32_t z) -> uint32_t { return (uint32_t)(((size_t)z * L + y) * W + w0); };
 
     // register rings, named by plane relative to the step's plane q
     // old colour 1 of planes q-1, q, q+1 and prefetches of q+2, q+3; old colour
@@ -115,6 +118,23 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
     uint32_t flips_a = 0, flips_c = 0;   // accepted flips over owned sites
     const size_t set = (size_t)E * W;   // words of one row set in LDS
 
+    // The tie words of the four stages depend only on the sites and the time,
+    // so they are drawn one plane step ahead: the Philox evaluations then
+    // overlap the current step's loads, barrier and stage chain A -> B -> C
+    // -> D instead of lengthening it.  They are drawn unconditionally; late
+    // in a quench nearly every wave still has a tie in every stage.
+    auto draw_step = [&](uint32_t z, uint32_t (&a)[V], uint32_t (&b)[V], uint32_t (&c)[V],
+                         uint32_t (&d)[V]) {
+        const uint32_t ga = gword(z), gb = gword((z + L - 1) % L);
+        const uint32_t gc = gword((z + L - 2) % L), gd = gword((z + L - 3) % L);
+        tie_words<V>(A.k0, A.k1, ga, ga & 3u, A.t, 0u, a);
+        tie_words<V>(A.k0, A.k1, gb, gb & 3u, A.t, 1u, b);
+        tie_words<V>(A.k0, A.k1, gc, gc & 3u, A.t + 1u, 0u, c);
+        tie_words<V>(A.k0, A.k1, gd, gd & 3u, A.t + 1u, 1u, d);
+    };
+    uint32_t sA[V], sB[V], sC[V], sD[V];   // tie words of the next step's stages
+    draw_step((z0 + L - 3) % L, sA, sB, sC, sD);
+
     for (int qi = -3; qi <= (int)Tza + 2; ++qi) {
         const uint32_t zq = (z0 + 2 * L + qi) % L;
         if (qi + 1 < (int)Tza + 2) {
@@ -123,6 +143,15 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             if (rowA)
                 load_words<V>(A.S0 + off((zq + 2) % L), pg0);
         }
+        const uint32_t zc = (zq + L - 2) % L, zd = (zq + L - 3) % L;
+        // this step's tie words, and the next step's drawn now (on the last
+        // step for a plane no stage reaches: harmless)
+        uint32_t rA[V], rB[V], rC[V], rD[V];
+        copy_words<V>(rA, sA);
+        copy_words<V>(rB, sB);
+        copy_words<V>(rC, sC);
+        copy_words<V>(rD, sD);
+        draw_step((zq + 1) % L, sA, sB, sC, sD);
         uint32_t *X1 = lds + (size_t)(qi & 1) * 4 * set;   // old colour 1, plane q
         uint32_t *X0 = X1 + set;                            // A's colour 0, plane q-1
         uint32_t *Y1 = X0 + set;                            // B's colour 1, plane q-2
@@ -146,10 +175,8 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             load_words<V>(X1 + em * W + w0, ym);
             load_words<V>(X1 + ep * W + w0, yp);
             const uint32_t adj = X1[e * W + wadj];
-            const uint32_t g = (uint32_t)(((size_t)zq * L + y) * W + w0);
             int a_sum = 0;
-            update_words<V, CA>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, A.k0, A.k1, g, g & 3u, A.t,
-                                0u, n0n, a_sum);
+            rule_words<V, CA>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, rA, n0n, a_sum);
             if constexpr (CA)
                 if (rowD && qi >= 0 && qi < (int)Tza) {
                     bonds_a += a_sum;
@@ -160,15 +187,12 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
         }
         // B: sweep t, colour 1, plane q-1
         if (rowB && qi >= -1) {
-            const uint32_t zb = (zq + L - 1) % L;
             uint32_t ym[V], yp[V];
             load_words<V>(X0 + em * W + w0, ym);
             load_words<V>(X0 + ep * W + w0, yp);
             const uint32_t adj = X0[e * W + wadj];
-            const uint32_t g = (uint32_t)(((size_t)zb * L + y) * W + w0);
             int unused = 0;
-            update_words<V, false>(c1m, n0a, adj, pi, ym, yp, n0b, n0n, A.k0, A.k1, g, g & 3u,
-                                   A.t, 1u, n1n, unused);
+            rule_words<V, false>(c1m, n0a, adj, pi, ym, yp, n0b, n0n, rB, n1n, unused);
             if constexpr (CA)
                 if (rowD && qi >= 1 && qi <= (int)Tza) {
 #pragma unroll
@@ -178,15 +202,12 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
         }
         // C: sweep t+1, colour 0, plane q-2
         if (rowC && qi >= 1) {
-            const uint32_t zc = (zq + L - 2) % L;
             uint32_t ym[V], yp[V];
             load_words<V>(Y1 + em * W + w0, ym);
             load_words<V>(Y1 + ep * W + w0, yp);
             const uint32_t adj = Y1[e * W + wadj];
-            const uint32_t g = (uint32_t)(((size_t)zc * L + y) * W + w0);
             int a_sum = 0;
-            update_words<V, CC>(n0b, n1a, adj, pi, ym, yp, n1b, n1n, A.k0, A.k1, g, g & 3u,
-                                A.t + 1u, 0u, m0n, a_sum);
+            rule_words<V, CC>(n0b, n1a, adj, pi, ym, yp, n1b, n1n, rC, m0n, a_sum);
             if (rowD && qi >= 2 && qi < (int)Tza + 2) {
                 if constexpr (CC) {
                     bonds_c += a_sum;
@@ -199,15 +220,12 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
         }
         // D: sweep t+1, colour 1, plane q-3
         if (rowD && qi >= 3) {
-            const uint32_t zd = (zq + L - 3) % L;
             uint32_t ym[V], yp[V];
             load_words<V>(Y0 + em * W + w0, ym);
             load_words<V>(Y0 + ep * W + w0, yp);
             const uint32_t adj = Y0[e * W + wadj];
-            const uint32_t g = (uint32_t)(((size_t)zd * L + y) * W + w0);
             int unused = 0;
-            update_words<V, false>(n1b, m0a, adj, pi, ym, yp, m0b, m0n, A.k0, A.k1, g, g & 3u,
-                                   A.t + 1u, 1u, m1n, unused);
+            rule_words<V, false>(n1b, m0a, adj, pi, ym, yp, m0b, m0n, rD, m1n, unused);
             if constexpr (CC) {
 #pragma unroll
                 for (int v = 0; v < V; ++v)

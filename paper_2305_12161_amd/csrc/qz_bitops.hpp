@@ -162,5 +162,32 @@ __device__ __forceinline__ void update_words(const uint32_t (&own)[V], const uin
     }
 }
 
+// The same rule with the tie words r already drawn: the new words with no
+// branch on whether any lane ties.  The two-sweep kernel draws the tie words
+// of all its stages up front, so that the Philox evaluations do not sit on the
+// chain from one stage's result to the next.
+template <int V, bool COUNT>
+__device__ __forceinline__ void rule_words(const uint32_t (&own)[V], const uint32_t (&same)[V],
+                                           uint32_t adj, uint32_t pi, const uint32_t (&ym)[V],
+                                           const uint32_t (&yp)[V], const uint32_t (&zm)[V],
+                                           const uint32_t (&zp)[V], const uint32_t (&r)[V],
+                                           uint32_t (&out)[V], int &acc)
+{
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const uint32_t sh = shifted_word<V>(same, adj, pi, v);
+        if constexpr (COUNT) {
+            const UpCount c = count_up(same[v], sh, ym[v], yp[v], zm[v], zp[v]);
+            out[v] = up_rule(own[v], c, r[v]);
+            acc += up_antialigned_sum(own[v], c);
+        } else {
+            const uint32_t xa = xor3(same[v], sh, ym[v]), ma = maj3(same[v], sh, ym[v]);
+            const uint32_t xb = xor3(yp[v], zm[v], zp[v]), mb = maj3(yp[v], zm[v], zp[v]);
+            out[v] = maj3(ma, mb, maj3(xa, xb, own[v] ^ r[v]));
+        }
+    }
+    (void)acc;
+}
+
 }  // namespace bitops
 }  // namespace qz

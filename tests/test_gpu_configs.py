@@ -156,6 +156,28 @@ def test_same_tuning_full_run_L256(qz, orc, sweeps):
     assert np.array_equal(lat.download(), s)
 
 
+def test_two_sweep_pass_late_times_L512(qz, orc):
+    """4000 sweeps at L = 512 with two sweeps per pass (paired rows, and the
+    default tuning) against the one-sweep pass, which draws every stage's tie
+    bits on its own; then replayed windows against the oracle."""
+    L, seed, n, every = 512, 12, 4000, 50
+    one = qz.Lattice(L, seed, "bit")
+    one.set_pass(1)
+    tr1 = one.run(n, every)
+    for tuning in ((4, 56, 7), (0, 0, 0)):
+        print("L512 late times", tuning, flush=True)
+        two = qz.Lattice(L, seed, "bit")
+        two.set_pass(2, *tuning)
+        tr2 = two.run(n, every)
+        assert np.array_equal(tr1, tr2), tuning
+        for o in ((0, 0, 0), (300, 11, 509), (511, 256, 100)):
+            assert np.array_equal(one.window(o, 64), two.window(o, 64)), (tuning, o)
+        rng = np.random.default_rng(512)
+        o = [int(v) for v in rng.integers(0, L, size=3)]
+        assert replay(orc, two, L, seed, o, 64 + 4 * 6, 6), (tuning, o)
+        del two
+
+
 def test_physics_band_ell_L256(qz):
     """Loose band, not parity: mean ell at L=256 near the paper's value.
 

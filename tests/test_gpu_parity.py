@@ -157,6 +157,28 @@ def test_two_sweep_pass_matches_oracle(qz, orc, L):
         assert np.array_equal(lat.download(), s), (V, Ty, Tz)
 
 
+@pytest.mark.parametrize("tuning", [(4, 24, 32), (4, 120, 5), (4, 56, 8)])
+def test_two_sweep_pass_late_times(qz, orc, tuning):
+    """3000 sweeps at L = 256 with V = 4 tunings (paired and unpaired rows),
+    traced every 100: the late regime, where ties are sparse, against the
+    oracle."""
+    L, seed, n, every = 256, 77, 3000, 100
+    key = ("late", L, seed, n, every)
+    if key not in _LATE:
+        s = orc.init(L, seed)
+        _LATE[key] = (orc.run(s, seed, 0, n, every), s)
+    want, s = _LATE[key]
+    say("two-sweep late times", L, tuning)
+    lat = qz.Lattice(L, seed, "bit")
+    lat.set_pass(2, *tuning)
+    tr = lat.run(n, every)
+    assert np.array_equal(tr.astype(np.int64), want), tuning
+    assert np.array_equal(lat.download(), s), tuning
+
+
+_LATE = {}
+
+
 @pytest.mark.parametrize("every,n", [(2, 8), (3, 9), (5, 10)])
 def test_two_sweep_pass_trace_alignment(qz, orc, every, n):
     """Start at an odd time from an uploaded state: pairs straddle the traced
