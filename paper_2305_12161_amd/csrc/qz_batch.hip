@@ -87,9 +87,10 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
 
     // one colour update of the lane's quad; Xo = other colour's plane in LDS,
     // same = the lane's own words of that plane, zm/zp = planes below/above
+    // r = the quad's tie words (one Philox block), drawn beforehand
     auto update = [&](const uint32_t *Xo, const uint32_t (&own)[4], const uint32_t (&same)[4],
                       const uint32_t (&zmn)[4], const uint32_t (&zpn)[4], uint32_t zp_plane,
-                      uint32_t colour, uint32_t (&out)[4], bool count) {
+                      uint32_t colour, const uint32_t (&r)[4], uint32_t (&out)[4], bool count) {
         // the two neighbour triples: (same, shifted, y-1) and (y+1, z-1, z+1)
         uint32_t n0[4], n1[4], n2[4];
 #pragma unroll
@@ -100,55 +101,38 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
             n1[v] = Xo[gym[v]];
             n2[v] = Xo[gyp[v]];
         }
-        auto tie_bits = [&](uint32_t (&r)[4]) {
-            const uint32_t blk = (zp_plane * PW + g0) >> 2;      // Philox block = word index / 4
-            const Words4 rb = philox10(blk, t, colour, 0u, k0, k1);
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                r[v] = rb.w[v];
-        };
         if (count) {
             // the three-bit up count, also summed into the bond count
-            UpCount c[4];
-            uint32_t ties = 0;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                c[v] = count_up(same[v], n0[v], n1[v], n2[v], zmn[v], zpn[v]);
-                ties |= up_tie(c[v]);
-            }
-            uint32_t r[4] = {0u, 0u, 0u, 0u};
-            if (ties != 0u)
-                tie_bits(r);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                out[v] = up_rule(own[v], c[v], r[v]);
-                bonds += up_antialigned_sum(own[v], c[v]);
+                const UpCount c = count_up(same[v], n0[v], n1[v], n2[v], zmn[v], zpn[v]);
+                out[v] = up_rule(own[v], c, r[v]);
+                bonds += up_antialigned_sum(own[v], c);
             }
         } else {
             // majority of seven (the neighbours and s ^ r), as in the lattice kernels
-            uint32_t xa[4], ma[4], xb[4], mb[4], w[4];
-            uint32_t ties = 0;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                xa[v] = xor3(same[v], n0[v], n1[v]);
-                ma[v] = maj3(same[v], n0[v], n1[v]);
-                xb[v] = xor3(n2[v], zmn[v], zpn[v]);
-                mb[v] = maj3(n2[v], zmn[v], zpn[v]);
-                ties |= (xa[v] ^ xb[v]) & (ma[v] ^ mb[v]);
-                w[v] = own[v];
+                const uint32_t xa = xor3(same[v], n0[v], n1[v]), ma = maj3(same[v], n0[v], n1[v]);
+                const uint32_t xb = xor3(n2[v], zmn[v], zpn[v]), mb = maj3(n2[v], zmn[v], zpn[v]);
+                out[v] = maj3(ma, mb, maj3(xa, xb, own[v] ^ r[v]));
             }
-            if (ties != 0u) {
-                uint32_t r[4];
-                tie_bits(r);
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    w[v] ^= r[v];
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                out[v] = maj3(ma[v], mb[v], maj3(xa[v], xb[v], w[v]));
         }
     };
+    // The tie words depend only on the sites and the time, so each step's are
+    // drawn one step ahead (unconditionally), off the chain from the colour-0
+    // update to the colour-1 update.  Philox block = word index / 4.
+    auto draw = [&](uint32_t z, uint32_t colour, uint32_t (&r)[4]) {
+        const Words4 rb = philox10((z * PW + g0) >> 2, t, colour, 0u, k0, k1);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            r[v] = rb.w[v];
+    };
+    uint32_t s0[4] = {0u, 0u, 0u, 0u}, s1[4] = {0u, 0u, 0u, 0u};   // next step's tie words
+    if (act) {
+        draw((z0 + L - 1) % L, 0u, s0);
+        draw((z0 + L - 2) % L, 1u, s1);
+    }
 
     for (int qi = -1; qi <= (int)nz; ++qi) {
         const uint32_t zq = (z0 + L + qi) % L;
@@ -163,14 +147,24 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
             *reinterpret_cast<uint4 *>(X1 + g0) = make_uint4(c1c[0], c1c[1], c1c[2], c1c[3]);
             *reinterpret_cast<uint4 *>(X0 + g0) = make_uint4(n0m1[0], n0m1[1], n0m1[2], n0m1[3]);
         }
+        uint32_t r0[4], r1[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            r0[v] = s0[v];
+            r1[v] = s1[v];
+        }
+        if (act) {
+            draw((zq + 1) % L, 0u, s0);
+            draw(zq, 1u, s1);
+        }
         __syncthreads();
         if (act) {
             const bool mine = qi >= 0 && qi < (int)nz;
-            update(X1, c0o, c1c, c1m, c1p, zq, 0u, n0c, counting && mine);
+            update(X1, c0o, c1c, c1m, c1p, zq, 0u, r0, n0c, counting && mine);
             if (mine)
                 st4(D0, zq, n0c);
             if (qi >= 1) {
-                update(X0, c1m, n0m1, n0m2, n0c, zm, 1u, c1n, false);
+                update(X0, c1m, n0m1, n0m2, n0c, zm, 1u, r1, c1n, false);
                 st4(D1, zm, c1n);
             }
 #pragma unroll

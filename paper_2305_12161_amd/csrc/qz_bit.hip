@@ -29,6 +29,8 @@ namespace {
 using bitops::load_words;
 using bitops::store_words;
 using bitops::store_words_nt;
+using bitops::rule_words;
+using bitops::tie_words;
 using bitops::update_words;
 
 struct SweepArgs {
@@ -104,6 +106,18 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
     int bonds = 0;       // sum of a over owned colour-0 sites (COUNT only)
     uint32_t flips = 0;  // accepted flips over owned sites (COUNT only)
 
+    // The tie words depend only on the sites and the time, so each step's are
+    // drawn one step ahead (unconditionally), off the chain from the first
+    // colour's update to the second's.
+    auto gword = [&](uint32_t z) -> uint32_t { return (uint32_t)(((size_t)z * L + y) * W + w0); };
+    auto draw_step = [&](uint32_t z, uint32_t (&a)[V], uint32_t (&b)[V]) {
+        const uint32_t ga = gword(z), gb = gword((z + L - 1) % L);
+        tie_words<V>(A.k0, A.k1, ga, ga & 3u, A.t, f, a);
+        tie_words<V>(A.k0, A.k1, gb, gb & 3u, A.t, 1u - f, b);
+    };
+    uint32_t sF[V], sS[V];   // tie words of the next step's two updates
+    draw_step((z0 + L - 1) % L, sF, sS);
+
     for (int qi = -1; qi <= (int)Tza; ++qi) {
         const uint32_t zq = (z0 + L + qi) % L;            // plane of this step
         const uint32_t zm = (zq + L - 1) % L;             // plane of the colour-1 update
@@ -122,17 +136,22 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
         }
         __syncthreads();
 
+        uint32_t rF[V], rS[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            rF[v] = sF[v];
+            rS[v] = sS[v];
+        }
+        draw_step((zq + 1) % L, sF, sS);
         const uint32_t pi = (f + y + zq) & 1u;   // x parity of the first colour at (y, zq), second at (y, zm)
         if (c0_row) {
             uint32_t ym[V], yp[V];
             load_words<V>(X1 + em * W + w0, ym);
             load_words<V>(X1 + ep * W + w0, yp);
             const uint32_t adj = X1[e * W + (pi == 0u ? wprev : wnext)];
-            const uint32_t g0 = (uint32_t)(((size_t)zq * L + y) * W + w0);
             const bool mine = owned && qi >= 0 && qi < (int)Tza;
             int a_sum = 0;
-            update_words<V, COUNT>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, A.k0, A.k1, g0, g0 & 3u,
-                                   A.t, f, n0c, a_sum);
+            rule_words<V, COUNT>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, rF, n0c, a_sum);
             if (mine) {
                 if constexpr (COUNT) {
                     bonds += a_sum;
@@ -148,10 +167,8 @@ __global__ void __launch_bounds__(1024) k_bit_sweep(SweepArgs A)
             load_words<V>(X0 + em * W + w0, ym);
             load_words<V>(X0 + ep * W + w0, yp);
             const uint32_t adj = X0[e * W + (pi == 0u ? wprev : wnext)];
-            const uint32_t g1 = (uint32_t)(((size_t)zm * L + y) * W + w0);
             int unused = 0;
-            update_words<V, false>(c1m, n0m1, adj, pi, ym, yp, n0m2, n0c, A.k0, A.k1, g1, g1 & 3u,
-                                   A.t, 1u - f, c1n, unused);
+            rule_words<V, false>(c1m, n0m1, adj, pi, ym, yp, n0m2, n0c, rS, c1n, unused);
             if constexpr (COUNT) {
 #pragma unroll
                 for (int v = 0; v < V; ++v)

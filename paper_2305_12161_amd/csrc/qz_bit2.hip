@@ -323,9 +323,10 @@ bool bit_tuning2_valid(uint32_t L, const BitTuning &t)
 BitTuning bit_tuning2_default(uint32_t L)
 {
     // Measured on MI355X: where the lattice is far larger than the caches
-    // (L >= 1536) tiles of E = 64 held rows (56 owned) and Tz = 32 planes
-    // (0.354 ms per sweep at L = 2048 against 0.371 with E = 32); below that
-    // E = 32 and Tz = 8, which keep more workgroups in flight.
+    // (L >= 1536) tiles of E = 64 held rows (56 owned) and Tz = 64 planes
+    // (at L = 2048, late times: 0.271 ms per sweep against 0.282 with Tz =
+    // 32, 0.307 with Tz = 96, and 0.295 with E = 32); below that E = 32 and
+    // Tz = 8, which keep more workgroups in flight.
     const uint32_t W = L / 64;
     BitTuning t;
     t.V = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
@@ -336,7 +337,7 @@ BitTuning bit_tuning2_default(uint32_t L)
     while (E * 2 <= Emax && E * 2 * R <= Rmax && (size_t)2 * 4 * (E * 2) * W * 4 <= 64 * 1024)
         E *= 2;
     t.Ty = (int)std::min<uint32_t>(E - 8, L);
-    t.Tz = (int)std::min<uint32_t>(big ? 32 : 8, L);
+    t.Tz = (int)std::min<uint32_t>(big ? 64 : 8, L);
     return t;
 }
 
