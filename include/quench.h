@@ -167,7 +167,7 @@ int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
  * all three 0 selects the default for L.  QZ_EINVAL for another sweep count
  * or a tuning that does not fit (at most 1024 threads and 64 KiB of LDS per
  * workgroup); QZ_EUNSUPPORTED for the int8 layout.  qz_get_pass reports
- * (sweeps, V, Ty, Tz).  Default: 2 for L >= 1280 (where the one-sweep pass is
+ * (sweeps, V, Ty, Tz).  Default: 2 for L >= 1024 (where the one-sweep pass is
  * bound by HBM bandwidth), else 1. */
 int qz_set_pass(qz_lattice *q, int sweeps, int V, int Ty, int Tz);
 int qz_get_pass(const qz_lattice *q, int out_sweeps_V_Ty_Tz[4]);

@@ -322,14 +322,33 @@ bool bit_tuning2_valid(uint32_t L, const BitTuning &t)
 
 BitTuning bit_tuning2_default(uint32_t L)
 {
-    // Measured on MI355X: where the lattice is far larger than the caches
-    // (L >= 1536) tiles of E = 64 held rows (56 owned) and Tz = 64 planes
-    // (at L = 2048, late times: 0.271 ms per sweep against 0.282 with Tz =
-    // 32, 0.307 with Tz = 96, and 0.295 with E = 32); below that E = 32 and
-    // Tz = 8, which keep more workgroups in flight.
     const uint32_t W = L / 64;
     BitTuning t;
     t.V = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
+    // Measured on MI355X at late times (microseconds per sweep, best tile
+    // against the next best and the one-sweep pass): the best tile depends on
+    // how the workgroups of a launch fill the chip, so the sizes that were
+    // timed take their best.
+    //   L = 1024  Ty 24, Tz 24:  50.3 (Ty 56, Tz 16: 50.7; one sweep 58.5)
+    //   L = 1280  Ty 56, Tz 64: 100.1 (Ty 56, Tz 24: 107.9; one sweep 108.9)
+    //   L = 1536  Ty 24, Tz 48: 147.3 (Ty 24, Tz 32: 149.6; one sweep 176.8)
+    //   L = 1792  Ty 56, Tz 48: 212.3 (Ty 56, Tz 64: 220.1; one sweep 282.6)
+    //   L = 2048  Ty 56, Tz 64: 270.5 (Ty 56, Tz 48: 280.0; one sweep 397.9)
+    struct Timed {
+        uint32_t L;
+        int Ty, Tz;
+    };
+    static const Timed timed[] = {
+        {1024, 24, 24}, {1280, 56, 64}, {1536, 24, 48}, {1792, 56, 48}, {2048, 56, 64}};
+    for (const Timed &m : timed)
+        if (m.L == L && t.V == 4) {
+            t.Ty = m.Ty;
+            t.Tz = m.Tz;
+            return t;
+        }
+    // Elsewhere: where the lattice is far larger than the caches (L >= 1536)
+    // tiles of E = 64 held rows (56 owned) and Tz = 64 planes; below that
+    // E = 32 and Tz = 8, which keep more workgroups in flight.
     const uint32_t R = W / t.V;
     const bool big = L >= 1536;
     const uint32_t Emax = big ? 64 : 32, Rmax = big ? 1024 : 256;
@@ -342,9 +361,11 @@ BitTuning bit_tuning2_default(uint32_t L)
 }
 
 // Sweeps per pass chosen by default for a bit lattice of side L: two where the
-// one-sweep kernel is bound by HBM bandwidth (two copies of the lattice far
-// beyond the last-level cache), one otherwise.
-int bit_pass_default(uint32_t L) { return L >= 1280 ? 2 : 1; }
+// one-sweep kernel is bound by HBM bandwidth (two copies of the lattice well
+// beyond the last-level cache; from L = 1024, where the two-sweep pass was
+// measured faster), one otherwise (L = 768: 30.1 us per sweep with one sweep
+// per pass, 30.8 at best with two).
+int bit_pass_default(uint32_t L) { return L >= 1024 ? 2 : 1; }
 
 hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                       const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,

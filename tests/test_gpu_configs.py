@@ -178,6 +178,22 @@ def test_two_sweep_pass_late_times_L512(qz, orc):
         del two
 
 
+@pytest.mark.parametrize("L", [1024, 1280, 1536, 1792])
+def test_timed_default_tiles(qz, L):
+    """The sizes whose two-sweep tiles are a measured table entry: the
+    default configuration against the one-sweep pass (trace and windows)."""
+    one = qz.Lattice(L, 40 + L, "bit")
+    one.set_pass(1)
+    two = qz.Lattice(L, 40 + L, "bit")
+    assert two.pass_config()[0] == 2
+    print("timed default", L, two.pass_config(), flush=True)
+    tr1 = one.run(8, 2)
+    tr2 = two.run(8, 2)
+    assert np.array_equal(tr1, tr2)
+    for o in ((0, 0, 0), (L - 5, 3, L // 2), (L // 3, L - 1, 7)):
+        assert np.array_equal(one.window(o, 48), two.window(o, 48)), o
+
+
 def test_physics_band_ell_L256(qz):
     """Loose band, not parity: mean ell at L=256 near the paper's value.
 

@@ -96,6 +96,7 @@ def test_default_tunings_run_at_every_size(qz):
     for L in range(64, 1025, 64):
         say("default tuning", L)
         a = qz.Lattice(L, 7, "bit")
+        a.set_pass(1)
         b = qz.Lattice(L, 7, "bit")
         b.set_pass(2)
         ta = a.run(4, 2)
