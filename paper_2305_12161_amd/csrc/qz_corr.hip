@@ -334,6 +334,245 @@ __global__ void __launch_bounds__(kBlock) k_corr_x(uint32_t L, uint32_t W, const
         atomicAdd(ones, bacc[R]);
 }
 
+// ---------------------------------------------------------------------------
+// y and z axes on the matrix cores.  For axis a, row u is the plane of sites
+// at coordinate u along a, and column k one of the L^2 lines along a; with
+// b = 1 for up spins, the Gram matrix G[u][u'] = sum_k b(u,k) b(u',k) gives
+//   T(r) = sum_u G[u][(u + r) mod L]   (up-up pairs at separation r),
+// and the anti-aligned pair count is anti(r) = 2 (N_up - T(r)), since every
+// site has one partner at +r: the pairs with at least one up spin number
+// 2 N_up - T(r), of which T(r) are up-up.
+//
+// G is a plain int8 matrix product: each wave owns a 128 x 32 NB tile of G
+// (4 x NB blocks of v_mfma_i32_32x32x32_i8) over a chunk of the lines; G is
+// symmetric, so only tiles that reach the diagonal or beyond are computed and
+// their entries below it are skipped.  A row's lines come
+// as 32-bit words: word kappa = (o * 2 + p) * W + w holds the 32 lines
+// (o, x = 64 w + 2 j + p) of row u, o being the third coordinate, from colour
+// plane (p + u + o) & 1.  Both operands of an instruction must pair the same
+// 32 lines in the same order, and which 32 does not matter: lane half h of a
+// wave takes word kk = kappa0 + 4h + s of the row (s = 0..3) and expands bits
+// {j, 8 + j, 16 + j, 24 + j} into the four bytes of dword j (j = 0..3 for one
+// instruction, 4..7 for the next), so 8 words feed 8 instructions per block.
+// ---------------------------------------------------------------------------
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr uint32_t kGramTile = 128;   // rows of a wave's tile
+constexpr int kGramNB = 2;            // 32-column blocks of a wave's tile
+
+struct GramGeom {
+    uint32_t L, W, nT;     // nT = L / 128 row blocks
+    uint32_t CW, ncb;      // tile columns (32 NB) and column blocks L / CW
+    uint32_t ntile;        // tiles that reach the diagonal or beyond
+    uint32_t nsplit;       // line chunks per tile
+    uint32_t kchunk;       // words (of 32 lines) per chunk, a multiple of 8
+    uint32_t NK;           // words per row, 2 L W
+};
+
+__device__ __forceinline__ v4i expand_bits(uint32_t y, uint32_t j0)
+{
+    v4i f;
+    f[0] = (int)((y >> j0) & 0x01010101u);
+    f[1] = (int)((y >> (j0 + 1u)) & 0x01010101u);
+    f[2] = (int)((y >> (j0 + 2u)) & 0x01010101u);
+    f[3] = (int)((y >> (j0 + 3u)) & 0x01010101u);
+    return f;
+}
+
+// NB = 4: 128 x 128 tiles, one wave per SIMD (256 accumulator registers);
+// NB = 2: 128 x 64 tiles, two waves per SIMD.
+template <int AX, int NB>
+__global__ void __launch_bounds__(256, 4 / NB) k_corr_gram(GramGeom g, const uint32_t *P0,
+                                                  const uint32_t *P1, unsigned long long *tb)
+{
+    __shared__ uint32_t dsum[4][256];   // per wave: the tile's diagonals d - dbase
+    const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t i = lane & 31u, h = lane >> 5;
+    const uint32_t item = blockIdx.x * 4u + wv;
+    if (item >= g.ntile * g.nsplit)      // whole wave
+        return;
+    uint32_t *ds = dsum[wv];
+    for (uint32_t k = lane; k < 256u; k += 64u)
+        ds[k] = 0u;
+    // chunk-major: the waves in flight work on the same few chunks of lines,
+    // whose words (all rows) then stay in the last-level cache
+    const uint32_t tile = item % g.ntile, split = item / g.ntile;
+    // tile -> (bi, bj), row by row; row block bi starts at column block
+    // 128 bi / CW (tiles wholly below the diagonal are mirrors: skipped)
+    uint32_t bi = 0, rem = tile;
+    while (rem >= g.ncb - kGramTile * bi / g.CW) {
+        rem -= g.ncb - kGramTile * bi / g.CW;
+        ++bi;
+    }
+    const uint32_t bj = kGramTile * bi / g.CW + rem;
+    const uint32_t L = g.L, W = g.W, W2 = 2u * g.W;
+    const uint32_t k_begin = split * g.kchunk, k_end = min(g.NK, k_begin + g.kchunk);
+
+    v16i acc[4][NB];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                acc[m][n][r] = 0;
+    auto row_words = [&](uint32_t u, uint32_t o, uint32_t p, uint32_t w) -> uint4 {
+        const uint32_t *P = ((p + u + o) & 1u) ? P1 : P0;
+        const size_t off = (AX == 1) ? ((size_t)o * L + u) * W + w : ((size_t)u * L + o) * W + w;
+        return *reinterpret_cast<const uint4 *>(P + off);
+    };
+    // Software pipeline over the instruction steps (8 per 8 words): the words
+    // of the next 8 are loaded while these are multiplied, and the bytes of
+    // the next step are expanded between the 16 MFMAs of this one (one wave
+    // per SIMD: nothing else hides the load latency or the expansion).
+    uint4 na[4], nb[NB];
+    auto fetch = [&](uint32_t k0) {
+        const uint32_t kk = k0 + 4u * h;
+        const uint32_t o = kk / W2, p = (kk / W) & 1u, w = kk % W;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            na[m] = row_words(bi * kGramTile + 32u * m + i, o, p, w);
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+            nb[n] = row_words(bj * g.CW + 32u * n + i, o, p, w);
+    };
+    auto word = [](const uint4 &q, int s) -> uint32_t {
+        return s == 0 ? q.x : s == 1 ? q.y : s == 2 ? q.z : q.w;
+    };
+    fetch(k_begin);
+    uint4 ca[4], cb[NB];   // words of the current 8 steps
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        ca[m] = na[m];
+#pragma unroll
+    for (int n = 0; n < NB; ++n)
+        cb[n] = nb[n];
+    fetch(min(k_begin + 8u, k_end - 8u));
+    v4i fa[4], fb[NB];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        fa[m] = expand_bits(ca[m].x, 0u);
+#pragma unroll
+    for (int n = 0; n < NB; ++n)
+        fb[n] = expand_bits(cb[n].x, 0u);
+    for (uint32_t k0 = k_begin; k0 < k_end; k0 += 8u) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            // next step's bytes: word (st + 1) / 2, bit groups 0..3 or 4..7;
+            // after the 8th step the first of the prefetched words
+            v4i ga[4], gb[NB];
+            const int s1 = (st + 1) / 2;
+            const uint32_t j1 = ((st + 1) % 2) ? 4u : 0u;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                ga[m] = expand_bits(st < 7 ? word(ca[m], s1) : na[m].x, j1);
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+                gb[n] = expand_bits(st < 7 ? word(cb[n], s1) : nb[n].x, j1);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < NB; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n], acc[m][n],
+                                                                      0, 0, 0);
+            // one MFMA, then up to four VALU instructions, for each MFMA
+#pragma unroll
+            for (int q = 0; q < 4 * NB; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                fa[m] = ga[m];
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+                fb[n] = gb[n];
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            ca[m] = na[m];
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+            cb[n] = nb[n];
+        fetch(min(k0 + 16u, k_end - 8u));   // the last steps reload their own words
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // diagonals of the tile: entry (row, col) of block (m, n) in register r of
+    // this lane is row 32 m + 8 (r / 4) + 4 h + r % 4, column 32 n + i; its
+    // separation is d = CW bj + col - 128 bi - row; entries with d < 0 are
+    // the mirrors of entries of other tiles
+    const int dbase = (int)(bj * g.CW) - (int)(bi * kGramTile) - 127;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 32 * m + 8 * (r / 4) + 4 * (int)h + (r % 4);
+                const int col = 32 * n + (int)i;
+                const int v = acc[m][n][r];
+                if (v != 0 && dbase + 127 + col - row >= 0)
+                    atomicAdd(ds + (col - row + 127), (uint32_t)v);
+            }
+    // fold: an entry at separation d (u < u') is the pair (u, u') at +d and
+    // the pair (u', u) at +(L - d); T keeps r = 0 .. L/2
+    const int half = (int)(L / 2);
+    for (uint32_t k = lane; k < 255u; k += 64u) {
+        const int d = dbase + (int)k;
+        const uint32_t v = ds[k];
+        if (v == 0u || d < 0)
+            continue;
+        if (d == 0) {
+            atomicAdd(tb, (unsigned long long)v);
+            continue;
+        }
+        if (d <= half)
+            atomicAdd(tb + d, (unsigned long long)v);
+        if (d >= half)
+            atomicAdd(tb + ((int)L - d), (unsigned long long)v);
+    }
+}
+
+// anti(r) = 2 (N_up - T(r)) in place, for the two axes at tb and tb + R
+__global__ void k_corr_gram_finish(unsigned long long *tb, uint32_t n, const unsigned long long *ones)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n)
+        tb[k] = 2ull * (*ones - tb[k]);
+}
+
+GramGeom gram_geom(uint32_t L, uint32_t NB)
+{
+    GramGeom g;
+    g.L = L;
+    g.W = L / 64;
+    g.nT = L / kGramTile;
+    g.CW = 32 * NB;
+    g.ncb = L / g.CW;
+    g.ntile = 0;
+    for (uint32_t bi = 0; bi < g.nT; ++bi)
+        g.ntile += g.ncb - kGramTile * bi / g.CW;
+    g.NK = 2 * L * g.W;
+    // at least two rounds of resident waves over the launch (1024 SIMDs,
+    // 4 / NB waves each), chunks of at most 2048 words (all rows of a chunk:
+    // 16 MiB at L = 2048, so the chunks in flight fit in the last-level
+    // cache), at least 64 words, and per-wave diagonal sums below 2^32
+    const uint32_t waves = 2 * 1024 * (4 / NB);
+    uint32_t nsplit = std::max((waves + g.ntile - 1) / g.ntile, (g.NK + 2047) / 2048);
+    uint32_t kchunk = ((g.NK + nsplit - 1) / nsplit + 7) / 8 * 8;
+    if (kchunk < 64)
+        kchunk = 64;
+    const uint32_t kmax = (1u << 20) - 8;   // 32 lines per word, 128 entries per diagonal
+    if (kchunk > kmax)
+        kchunk = kmax;
+    g.kchunk = kchunk;
+    g.nsplit = (g.NK + kchunk - 1) / kchunk;
+    return g;
+}
+
 LineGeom line_geom(uint32_t L)
 {
     LineGeom g;
@@ -379,15 +618,31 @@ hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32
     g.nsplit = nsplit;
     const size_t lds_lines = std::max<size_t>(line_lds_bytes(W, g.Cy, g.Rr), (size_t)g.Rr * 8);
     const dim3 grid_lines(g.nrc * nsplit);
-    hipLaunchKernelGGL(k_corr_lines<1>, grid_lines, dim3(kBlock), lds_lines, st, g, P0, P1,
-                       anti + 1 * R);
-    hipLaunchKernelGGL(k_corr_lines<2>, grid_lines, dim3(kBlock), lds_lines, st, g, P0, P1,
-                       anti + 2 * R);
+    // y and z on the matrix cores where the row blocks and word quads fit
+    // (L a multiple of 256), else by XOR and popcount
+    const bool gram = L % 256 == 0;
+    if (!gram) {
+        hipLaunchKernelGGL(k_corr_lines<1>, grid_lines, dim3(kBlock), lds_lines, st, g, P0, P1,
+                           anti + 1 * R);
+        hipLaunchKernelGGL(k_corr_lines<2>, grid_lines, dim3(kBlock), lds_lines, st, g, P0, P1,
+                           anti + 2 * R);
+    }
     const uint32_t P = kBlock / W;
     const size_t lds_x = std::max<size_t>((size_t)P * 2 * W * 4, (size_t)(R + 1) * 8);
     const uint64_t nchunks = ((uint64_t)L * L + P - 1) / P;
     const uint32_t gx = (uint32_t)std::min<uint64_t>(nchunks, 2048);
     hipLaunchKernelGGL(k_corr_x, dim3(gx), dim3(kBlock), lds_x, st, L, W, P0, P1, anti, ones);
+    if (gram) {
+        // after k_corr_x, which also counts the up spins
+        const GramGeom gg = gram_geom(L, kGramNB);
+        const dim3 grid_gram((gg.ntile * gg.nsplit + 3) / 4);
+        hipLaunchKernelGGL((k_corr_gram<1, kGramNB>), grid_gram, dim3(256), 0, st, gg, P0, P1,
+                           anti + 1 * R);
+        hipLaunchKernelGGL((k_corr_gram<2, kGramNB>), grid_gram, dim3(256), 0, st, gg, P0, P1,
+                           anti + 2 * R);
+        hipLaunchKernelGGL(k_corr_gram_finish, dim3((2 * R + 255) / 256), dim3(256), 0, st,
+                           anti + R, 2 * R, ones);
+    }
     return hipGetLastError();
 }
 

@@ -233,6 +233,68 @@ def test_bit_equals_i8(qz, L):
 # --------------------------------------------------------------------------
 # measurements
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [512, 1024])
+def test_corr_closed_forms_large(qz, L):
+    """Axis sums of states with a closed form, at sizes where y and z run on
+    the matrix cores: uniform (S = N), Neel (S = N (-1)^r) and slabs normal
+    to y and to z (S = N - 4 r L^2 along the normal, N along the others)."""
+    N = L ** 3
+    R = L // 2 + 1
+    r = np.arange(R, dtype=np.int64)
+    flat = np.full(R, N, dtype=np.int64)
+    ar = np.arange(L)
+    half = np.where(ar < L // 2, -1, 1).astype(np.int8)
+
+    def state(name):   # int8 throughout: at L = 1024 a state is 1 GiB
+        s = np.empty((L, L, L), dtype=np.int8)
+        if name == "up":
+            s[...] = 1
+        elif name == "neel":
+            pyz = ((ar[:, None] + ar[None, :]) % 2).astype(np.int8)[:, :, None]
+            px = (ar % 2).astype(np.int8)[None, None, :]
+            np.bitwise_xor(pyz, px, out=s)
+            np.multiply(s, -2, out=s)
+            np.add(s, 1, out=s)
+        elif name == "slab_z":
+            s[...] = half[:, None, None]
+        else:
+            s[...] = half[None, :, None]
+        return s
+
+    cases = {
+        "up": (np.stack([flat, flat, flat]), N),
+        "neel": (np.tile(N * (-1) ** r, (3, 1)), 0),
+        "slab_z": (np.stack([flat, flat, N - 4 * r * L * L]), 0),
+        "slab_y": (np.stack([flat, N - 4 * r * L * L, flat]), 0),
+    }
+    lat = qz.Lattice(L, 1, "bit")
+    for name, (want, want_M) in cases.items():
+        say("corr closed form", L, name)
+        lat.upload(state(name), 0)
+        S, M = lat.corr()
+        assert M == want_M, name
+        assert np.array_equal(S, want), name
+
+
+def test_corr_matches_fft_L512(qz):
+    """A random state after 40 sweeps at L = 512 against the axis
+    autocorrelation computed with numpy's FFT (rounded; exact in double)."""
+    L, seed = 512, 91
+    lat = qz.Lattice(L, seed, "bit")
+    lat.run(40)
+    S, M = lat.corr()
+    s = lat.download().astype(np.float64)
+    assert M == int(s.sum())
+    R = L // 2 + 1
+    for a, ax in enumerate((2, 1, 0)):   # x, y, z are array axes 2, 1, 0
+        f = np.fft.rfft(s, axis=ax)
+        ac = np.fft.irfft(f * np.conj(f), n=L, axis=ax)
+        del f
+        want = np.rint(ac.sum(axis=tuple(k for k in range(3) if k != ax))[:R]).astype(np.int64)
+        del ac
+        assert np.array_equal(S[a], want), a
+
+
 @pytest.mark.parametrize("layout,L", [("i8", 6), ("i8", 16), ("i8", 34), ("bit", 64),
                                       ("bit", 128), ("bit", 192), ("bit", 256)])
 def test_bonds_and_corr_match_oracle(qz, orc, layout, L):
