@@ -101,22 +101,25 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
             n1[v] = Xo[gym[v]];
             n2[v] = Xo[gyp[v]];
         }
+        // majority of seven (the neighbours and s ^ r), as in the lattice
+        // kernels; counting adds a = (xa ^ s) + (xb ^ s) + 2 ((ma ^ s) + (mb ^ s))
+        uint32_t xa[4], ma[4], xb[4], mb[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            xa[v] = xor3(same[v], n0[v], n1[v]);
+            ma[v] = maj3(same[v], n0[v], n1[v]);
+            xb[v] = xor3(n2[v], zmn[v], zpn[v]);
+            mb[v] = maj3(n2[v], zmn[v], zpn[v]);
+            out[v] = maj3(ma[v], mb[v], maj3(xa[v], xb[v], own[v] ^ r[v]));
+        }
         if (count) {
-            // the three-bit up count, also summed into the bond count
+            uint32_t ones = 0, twos = 0;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const UpCount c = count_up(same[v], n0[v], n1[v], n2[v], zmn[v], zpn[v]);
-                out[v] = up_rule(own[v], c, r[v]);
-                bonds += up_antialigned_sum(own[v], c);
+                ones = popc_acc(xa[v] ^ own[v], popc_acc(xb[v] ^ own[v], ones));
+                twos = popc_acc(ma[v] ^ own[v], popc_acc(mb[v] ^ own[v], twos));
             }
-        } else {
-            // majority of seven (the neighbours and s ^ r), as in the lattice kernels
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const uint32_t xa = xor3(same[v], n0[v], n1[v]), ma = maj3(same[v], n0[v], n1[v]);
-                const uint32_t xb = xor3(n2[v], zmn[v], zpn[v]), mb = maj3(n2[v], zmn[v], zpn[v]);
-                out[v] = maj3(ma, mb, maj3(xa, xb, own[v] ^ r[v]));
-            }
+            bonds += (int)(ones + 2u * twos);
         }
     };
     // The tie words depend only on the sites and the time, so each step's are

@@ -163,9 +163,14 @@ __device__ __forceinline__ void update_words(const uint32_t (&own)[V], const uin
 }
 
 // The same rule with the tie words r already drawn: the new words with no
-// branch on whether any lane ties.  The two-sweep kernel draws the tie words
-// of all its stages up front, so that the Philox evaluations do not sit on the
+// branch on whether any lane ties.  The streaming kernels draw the tie words
+// of their stages ahead, so that the Philox evaluations do not sit on the
 // chain from one stage's result to the next.
+//
+// COUNT adds the sum of a over the sites, from the same two triples: with s
+// the own spin, a = (xa ^ s) + (xb ^ s) + 2 ((ma ^ s) + (mb ^ s)) per site
+// (a triple's parity and majority differ from s in exactly the ways that its
+// anti-aligned count 0..3 requires), so four popcounts per word.
 template <int V, bool COUNT>
 __device__ __forceinline__ void rule_words(const uint32_t (&own)[V], const uint32_t (&same)[V],
                                            uint32_t adj, uint32_t pi, const uint32_t (&ym)[V],
@@ -173,19 +178,20 @@ __device__ __forceinline__ void rule_words(const uint32_t (&own)[V], const uint3
                                            const uint32_t (&zp)[V], const uint32_t (&r)[V],
                                            uint32_t (&out)[V], int &acc)
 {
+    uint32_t ones = 0, twos = 0;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const uint32_t sh = shifted_word<V>(same, adj, pi, v);
+        const uint32_t xa = xor3(same[v], sh, ym[v]), ma = maj3(same[v], sh, ym[v]);
+        const uint32_t xb = xor3(yp[v], zm[v], zp[v]), mb = maj3(yp[v], zm[v], zp[v]);
+        out[v] = maj3(ma, mb, maj3(xa, xb, own[v] ^ r[v]));
         if constexpr (COUNT) {
-            const UpCount c = count_up(same[v], sh, ym[v], yp[v], zm[v], zp[v]);
-            out[v] = up_rule(own[v], c, r[v]);
-            acc += up_antialigned_sum(own[v], c);
-        } else {
-            const uint32_t xa = xor3(same[v], sh, ym[v]), ma = maj3(same[v], sh, ym[v]);
-            const uint32_t xb = xor3(yp[v], zm[v], zp[v]), mb = maj3(yp[v], zm[v], zp[v]);
-            out[v] = maj3(ma, mb, maj3(xa, xb, own[v] ^ r[v]));
+            ones = popc_acc(xa ^ own[v], popc_acc(xb ^ own[v], ones));
+            twos = popc_acc(ma ^ own[v], popc_acc(mb ^ own[v], twos));
         }
     }
+    if constexpr (COUNT)
+        acc += (int)(ones + 2u * twos);
     (void)acc;
 }
 
