@@ -127,7 +127,11 @@ int qz_run_device_traced(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every,
 int qz_bonds(qz_lattice *q, uint64_t out_B_axes[3]);
 
 /* Axis correlation sums of the current state: out_S[a*(L/2+1) + r] = S_a(r)
- * for a = 0 (x), 1 (y), 2 (z) and r = 0..L/2, and *out_M = M. */
+ * for a = 0 (x), 1 (y), 2 (z) and r = 0..L/2, and *out_M = M.  For the bit
+ * layout with L a multiple of 256 they come from the matrix cores (Gram
+ * matrix of the spins along each axis), and the x axis uses the state
+ * buffer's idle copy (the one the next sweep overwrites) as scratch; the
+ * results are the same integers as by direct summation. */
 int qz_corr(qz_lattice *q, int64_t *out_S, int64_t *out_M);
 
 /* Current time t (completed sweeps). */
@@ -274,7 +278,8 @@ int qz_batch_trace(qz_batch *b, size_t slot, uint64_t t_from, uint64_t count, ui
 
 /* A slot's lattice as int8 +-1 (L^3 bytes, index i), per-axis bond counts and
  * axis correlation sums, with the meanings of qz_download_spins, qz_bonds and
- * qz_corr (all synchronise). */
+ * qz_corr (all synchronise; qz_batch_corr also uses the slot's idle copy as
+ * scratch). */
 int qz_batch_download(qz_batch *b, size_t slot, int8_t *host);
 int qz_batch_bonds(qz_batch *b, size_t slot, uint64_t out_B_axes[3]);
 int qz_batch_corr(qz_batch *b, size_t slot, int64_t *out_S, int64_t *out_M);

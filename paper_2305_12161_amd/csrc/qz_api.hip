@@ -388,8 +388,10 @@ QZ_EXPORT int qz_corr(qz_lattice *q, int64_t *out_S, int64_t *out_M)
         QZ_HIP(q, qz::i8_corr(q->st, q->L, i8_spins(q), reinterpret_cast<long long *>(acc),
                               reinterpret_cast<long long *>(acc + 3 * R)));
     else
+        // the idle copy (the next sweep overwrites it) serves as scratch
         QZ_HIP(q, qz::bit_corr(q->st, q->L, bit_plane(q, q->cur, 0), bit_plane(q, q->cur, 1), acc,
-                               acc + 3 * R));
+                               acc + 3 * R, bit_plane(q, 1 - q->cur, 0),
+                               bit_plane(q, 1 - q->cur, 1)));
     unsigned long long *h = new (std::nothrow) unsigned long long[nvals];
     if (!h)
         return fail(QZ_ENOMEM, "host allocation failed");

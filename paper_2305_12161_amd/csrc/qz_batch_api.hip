@@ -566,8 +566,10 @@ QZ_EXPORT int qz_batch_corr(qz_batch *b, size_t slot, int64_t *out_S, int64_t *o
     const uint32_t L = b->specs[slot].L, R = L / 2 + 1;
     const int c = (int)b->host_reps[slot].cur;
     BZ_HIP(b, qz::fill_u64(b->st, b->corr, 3 * (size_t)R + 1, 0ull));
+    // the replica's idle copy (its next sweep overwrites it) serves as scratch
     BZ_HIP(b, qz::bit_corr(b->st, L, slot_plane(b, slot, c, 0), slot_plane(b, slot, c, 1), b->corr,
-                           b->corr + 3 * R));
+                           b->corr + 3 * R, slot_plane(b, slot, 1 - c, 0),
+                           slot_plane(b, slot, 1 - c, 1)));
     std::vector<unsigned long long> h(3 * (size_t)R + 1);
     BZ_HIP(b, hipMemcpyAsync(h.data(), b->corr, h.size() * 8, hipMemcpyDeviceToHost, b->st));
     BZ_HIP(b, hipStreamSynchronize(b->st));

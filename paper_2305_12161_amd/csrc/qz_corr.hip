@@ -536,12 +536,94 @@ __global__ void __launch_bounds__(256, 4 / NB) k_corr_gram(GramGeom g, const uin
     }
 }
 
-// anti(r) = 2 (N_up - T(r)) in place, for the two axes at tb and tb + R
-__global__ void k_corr_gram_finish(unsigned long long *tb, uint32_t n, const unsigned long long *ones)
+// anti(r) = 2 (N_up - T(r)) in place, one block per axis from axis a0 on,
+// with N_up = T(0) (the up-up pairs at separation 0); with x among the axes
+// (a0 = 0) the block of axis 0 also stores N_up at *ones
+__global__ void k_corr_gram_finish(unsigned long long *tb, uint32_t R, uint32_t a0,
+                                   unsigned long long *ones)
 {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n)
-        tb[k] = 2ull * (*ones - tb[k]);
+    __shared__ unsigned long long t0;
+    unsigned long long *t = tb + (size_t)(a0 + blockIdx.x) * R;
+    if (threadIdx.x == 0) {
+        t0 = t[0];
+        if (a0 + blockIdx.x == 0)
+            *ones = t0;
+    }
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < R; r += blockDim.x)
+        t[r] = 2ull * (t0 - t[r]);
+}
+
+// ---------------------------------------------------------------------------
+// Swap the x and z axes of a 1-bit lattice into Q: Q holds the lattice s' with
+// s'(x', y, z') = s(z', y, x'), in the same colour-separated layout (the
+// colour x + y + z is unchanged), so the z-axis sums of Q are the x-axis sums
+// of P and the x axis can run on the matrix cores too.  One workgroup per
+// (y, block zb of 64 planes): it stages the rows (z, y) of both colours in
+// LDS; a wave turns each 64 x 64 block (z, x) into a 64-bit row per lane
+// (x = 64 xb + 2 b + p at bit 2 b + p), transposes it across the wave in six
+// exchange steps, and lane l writes word zb of the two colour rows of Q's row
+// (z' = 64 xb + l, y).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t spread_bits(uint32_t v)
+{
+    uint64_t x = v;
+    x = (x | x << 16) & 0x0000FFFF0000FFFFull;
+    x = (x | x << 8) & 0x00FF00FF00FF00FFull;
+    x = (x | x << 4) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | x << 2) & 0x3333333333333333ull;
+    x = (x | x << 1) & 0x5555555555555555ull;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t compact_bits(uint64_t v)
+{
+    uint64_t x = v & 0x5555555555555555ull;
+    x = (x | x >> 1) & 0x3333333333333333ull;
+    x = (x | x >> 2) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | x >> 4) & 0x00FF00FF00FF00FFull;
+    x = (x | x >> 8) & 0x0000FFFF0000FFFFull;
+    x = (x | x >> 16) & 0x00000000FFFFFFFFull;
+    return (uint32_t)x;
+}
+
+__global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, const uint32_t *P0,
+                                                    const uint32_t *P1, uint32_t *Q0, uint32_t *Q1)
+{
+    extern __shared__ uint32_t sm[];   // [64 rows z][2 colours][W words]
+    const uint32_t nzb = L / 64;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t y = tile / nzb, zb = tile % nzb;
+    for (uint32_t k = threadIdx.x; k < 128u * W; k += blockDim.x) {
+        const uint32_t w = k % W, c = (k / W) & 1u, r = k / (2u * W);
+        sm[k] = (c ? P1 : P0)[((size_t)(64u * zb + r) * L + y) * W + w];
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t ce = (y + 64u * zb + lane) & 1u;   // colour of the even-x sites of row z
+    constexpr uint64_t kMask[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
+                                   0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
+                                   0x3333333333333333ull, 0x5555555555555555ull};
+    for (uint32_t xb = threadIdx.x >> 6; xb < W; xb += blockDim.x >> 6) {
+        const uint32_t we = sm[(lane * 2u + ce) * W + xb];
+        const uint32_t wo = sm[(lane * 2u + (ce ^ 1u)) * W + xb];
+        uint64_t v = spread_bits(we) | (spread_bits(wo) << 1);
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            const uint32_t j = 32u >> st;
+            const uint64_t m = kMask[st];   // bit positions k with (k & j) == 0
+            const uint32_t olo = __shfl_xor((uint32_t)v, (int)j, 64);
+            const uint32_t ohi = __shfl_xor((uint32_t)(v >> 32), (int)j, 64);
+            const uint64_t o = ((uint64_t)ohi << 32) | olo;
+            v = (lane & j) ? ((v & ~m) | ((o & ~m) >> j)) : ((v & m) | ((o & m) << j));
+        }
+        // lane l now holds row z' = 64 xb + l: bit k is x' = 64 zb + k
+        const uint32_t zp = 64u * xb + lane;
+        const uint32_t cp = (y + zp) & 1u;            // colour of the even-x' sites of row z'
+        const size_t off = ((size_t)zp * L + y) * W + zb;
+        (cp ? Q1 : Q0)[off] = compact_bits(v);
+        (cp ? Q0 : Q1)[off] = compact_bits(v >> 1);
+    }
 }
 
 GramGeom gram_geom(uint32_t L, uint32_t NB)
@@ -604,7 +686,8 @@ LineGeom line_geom(uint32_t L)
 }  // namespace
 
 hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
-                    unsigned long long *anti, unsigned long long *ones)
+                    unsigned long long *anti, unsigned long long *ones, uint32_t *Q0,
+                    uint32_t *Q1)
 {
     const uint32_t W = L / 64;
     const uint32_t R = L / 2 + 1;
@@ -627,21 +710,30 @@ hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32
         hipLaunchKernelGGL(k_corr_lines<2>, grid_lines, dim3(kBlock), lds_lines, st, g, P0, P1,
                            anti + 2 * R);
     }
-    const uint32_t P = kBlock / W;
-    const size_t lds_x = std::max<size_t>((size_t)P * 2 * W * 4, (size_t)(R + 1) * 8);
-    const uint64_t nchunks = ((uint64_t)L * L + P - 1) / P;
-    const uint32_t gx = (uint32_t)std::min<uint64_t>(nchunks, 2048);
-    hipLaunchKernelGGL(k_corr_x, dim3(gx), dim3(kBlock), lds_x, st, L, W, P0, P1, anti, ones);
+    const bool gram_x = gram && Q0 != nullptr && Q1 != nullptr;
+    if (!gram_x) {
+        const uint32_t P = kBlock / W;
+        const size_t lds_x = std::max<size_t>((size_t)P * 2 * W * 4, (size_t)(R + 1) * 8);
+        const uint64_t nchunks = ((uint64_t)L * L + P - 1) / P;
+        const uint32_t gx = (uint32_t)std::min<uint64_t>(nchunks, 2048);
+        hipLaunchKernelGGL(k_corr_x, dim3(gx), dim3(kBlock), lds_x, st, L, W, P0, P1, anti, ones);
+    }
     if (gram) {
-        // after k_corr_x, which also counts the up spins
         const GramGeom gg = gram_geom(L, kGramNB);
         const dim3 grid_gram((gg.ntile * gg.nsplit + 3) / 4);
+        if (gram_x) {
+            // x: the z axis of the lattice with x and z swapped (into Q)
+            hipLaunchKernelGGL(k_bit_swap_xz, dim3(L * (L / 64)), dim3(256), (size_t)128 * W * 4,
+                               st, L, W, P0, P1, Q0, Q1);
+            hipLaunchKernelGGL((k_corr_gram<2, kGramNB>), grid_gram, dim3(256), 0, st, gg, Q0, Q1,
+                               anti);
+        }
         hipLaunchKernelGGL((k_corr_gram<1, kGramNB>), grid_gram, dim3(256), 0, st, gg, P0, P1,
                            anti + 1 * R);
         hipLaunchKernelGGL((k_corr_gram<2, kGramNB>), grid_gram, dim3(256), 0, st, gg, P0, P1,
                            anti + 2 * R);
-        hipLaunchKernelGGL(k_corr_gram_finish, dim3((2 * R + 255) / 256), dim3(256), 0, st,
-                           anti + R, 2 * R, ones);
+        const uint32_t a0 = gram_x ? 0u : 1u;
+        hipLaunchKernelGGL(k_corr_gram_finish, dim3(3 - a0), dim3(256), 0, st, anti, R, a0, ones);
     }
     return hipGetLastError();
 }

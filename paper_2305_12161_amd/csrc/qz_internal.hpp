@@ -73,8 +73,13 @@ hipError_t bit_bonds_total(hipStream_t st, uint32_t L, const uint32_t *P0, const
 hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
                             uint32_t *P0, uint32_t *P1, bool mixed,
                             unsigned long long *flip_acc = nullptr);
+// Q0, Q1: scratch colour planes of the same size (the lattice's idle copy;
+// overwritten), or null.  With scratch and L a multiple of 256 all three axes
+// run on the matrix cores, else x (and, for other L, y and z) by XOR and
+// popcount.
 hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
-                    unsigned long long *anti /* 3*(L/2+1) */, unsigned long long *ones);
+                    unsigned long long *anti /* 3*(L/2+1) */, unsigned long long *ones,
+                    uint32_t *Q0 = nullptr, uint32_t *Q1 = nullptr);
 // Unpack planes z in [z0, z0+nz) to int8 (index (z-z0)*L*L + y*L + x).
 hipError_t bit_unpack(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
                       uint32_t z0, uint32_t nz, int8_t *out);

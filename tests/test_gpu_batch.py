@@ -78,6 +78,31 @@ def test_batch_matches_oracle(qz, orc):
         assert M == Mo and np.array_equal(S, So)
 
 
+def test_batch_corr_on_matrix_cores(qz, orc):
+    """An L = 256 replica (all three axes on the matrix cores, the x axis
+    through the replica's idle copy) against the oracle, measured between
+    runs without changing the trajectory of it or of its neighbour."""
+    specs = [(256, 211), (64, 212)]
+    b = qz.Batch(specs, trace_every=3, trace_cap=16)
+    ref = qz.Batch(specs, trace_every=3, trace_cap=16)
+    s = orc.init(256, 211)
+    t = 0
+    for n in (6, 9):
+        b.run(n)
+        ref.run(n)
+        b.sync()
+        orc.run(s, 211, t, n)
+        t += n
+        S, M = b.corr(0)
+        So, Mo = orc.corr(s)
+        assert M == Mo and np.array_equal(S, So), t
+    b.sync()
+    ref.sync()
+    for slot in range(2):
+        assert np.array_equal(b.trace(slot, 0, 5), ref.trace(slot, 0, 5))
+        assert np.array_equal(b.download(slot), ref.download(slot))
+
+
 def test_slot_reset_and_parking(qz):
     specs = [(64, 1), (64, 2), (128, 3)]
     b = qz.Batch(specs, trace_every=5, trace_cap=32)

@@ -276,6 +276,28 @@ def test_corr_closed_forms_large(qz, L):
         assert np.array_equal(S, want), name
 
 
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_corr_leaves_the_dynamics_unchanged(qz, sweeps):
+    """The correlation uses the lattice's idle copy as scratch (for the x
+    axis on the matrix cores): measuring between runs must not change the
+    trajectory."""
+    L, seed = 256, 23
+    a = qz.Lattice(L, seed, "bit")
+    b = qz.Lattice(L, seed, "bit")
+    a.set_pass(sweeps)
+    b.set_pass(sweeps)
+    ta = [a.run(10, 5)]
+    for _ in range(3):
+        S1, M1 = a.corr()
+        S2, M2 = a.corr()
+        assert np.array_equal(S1, S2) and M1 == M2
+        ta.append(a.run(11, 1))
+    tb = [b.run(10, 5)] + [b.run(11, 1) for _ in range(3)]
+    for x, y in zip(ta, tb):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.download(), b.download())
+
+
 def test_corr_matches_fft_L512(qz):
     """A random state after 40 sweeps at L = 512 against the axis
     autocorrelation computed with numpy's FFT (rounded; exact in double)."""
