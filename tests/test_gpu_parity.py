@@ -233,7 +233,7 @@ def test_bit_equals_i8(qz, L):
 # --------------------------------------------------------------------------
 # measurements
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("L", [512, 1024])
+@pytest.mark.parametrize("L", [512, 768, 1024])
 def test_corr_closed_forms_large(qz, L):
     """Axis sums of states with a closed form, at sizes where y and z run on
     the matrix cores: uniform (S = N), Neel (S = N (-1)^r) and slabs normal
