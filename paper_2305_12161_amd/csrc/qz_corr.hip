@@ -558,12 +558,10 @@ __global__ void k_corr_gram_finish(unsigned long long *tb, uint32_t R, uint32_t 
 // Swap the x and z axes of a 1-bit lattice into Q: Q holds the lattice s' with
 // s'(x', y, z') = s(z', y, x'), in the same colour-separated layout (the
 // colour x + y + z is unchanged), so the z-axis sums of Q are the x-axis sums
-// of P and the x axis can run on the matrix cores too.  One workgroup per
-// (y, block zb of 64 planes): it stages the rows (z, y) of both colours in
-// LDS; a wave turns each 64 x 64 block (z, x) into a 64-bit row per lane
-// (x = 64 xb + 2 b + p at bit 2 b + p), transposes it across the wave in six
-// exchange steps, and lane l writes word zb of the two colour rows of Q's row
-// (z' = 64 xb + l, y).
+// of P and the x axis can run on the matrix cores too.  A wave turns a 64 x 64
+// block (z, x) into a 64-bit row per lane (x = 64 xb + 2 b + p at bit
+// 2 b + p), transposes it across the wave in six exchange steps, and lane l
+// then holds word zb of the two colour rows of Q's row (z' = 64 xb + l, y).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t spread_bits(uint32_t v)
 {
@@ -590,23 +588,40 @@ __device__ __forceinline__ uint32_t compact_bits(uint64_t v)
 __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, const uint32_t *P0,
                                                     const uint32_t *P1, uint32_t *Q0, uint32_t *Q1)
 {
-    extern __shared__ uint32_t sm[];   // [64 rows z][2 colours][W words]
-    const uint32_t nzb = L / 64;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t y = tile / nzb, zb = tile % nzb;
-    for (uint32_t k = threadIdx.x; k < 128u * W; k += blockDim.x) {
-        const uint32_t w = k % W, c = (k / W) & 1u, r = k / (2u * W);
-        sm[k] = (c ? P1 : P0)[((size_t)(64u * zb + r) * L + y) * W + w];
-    }
-    __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t ce = (y + 64u * zb + lane) & 1u;   // colour of the even-x sites of row z
+    // One workgroup of 256 threads per (y, group xg of four 64-column blocks,
+    // one per wave): it builds the 256 rows (z' = x, y) of Q for x in
+    // [256 xg, 256 xg + 256) in LDS, block zb by block zb, and writes them
+    // out whole.
+    extern __shared__ uint32_t sm[];
+    uint32_t *out = sm;                   // [256 rows][2 parity slots][W]: slot 0 = even x'
+    uint32_t *in = sm + 512u * W;         // [64 rows z][2 parity slots][4 words]: slot 0 = even x
+    const uint32_t ngroups = W / 4;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // a y's groups share an XCD
+    const uint32_t y = tile / ngroups, xg = tile % ngroups;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     constexpr uint64_t kMask[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
                                    0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
                                    0x3333333333333333ull, 0x5555555555555555ull};
-    for (uint32_t xb = threadIdx.x >> 6; xb < W; xb += blockDim.x >> 6) {
-        const uint32_t we = sm[(lane * 2u + ce) * W + xb];
-        const uint32_t wo = sm[(lane * 2u + (ce ^ 1u)) * W + xb];
+    // words 4 xg .. 4 xg + 3 of rows z = 64 zb + r, both parities: entry
+    // k = threadIdx.x + 256 i of block zb, loaded one block ahead
+    auto fetch = [&](uint32_t zb, uint32_t i) -> uint32_t {
+        const uint32_t k = threadIdx.x + 256u * i;
+        const uint32_t j = k & 3u, slot = (k >> 2) & 1u, r = k >> 3;
+        const uint32_t z = 64u * zb + r;
+        const uint32_t c = slot ^ ((y + z) & 1u);   // colour holding the parity slot
+        return (c ? P1 : P0)[((size_t)z * L + y) * W + 4u * xg + j];
+    };
+    uint32_t pre0 = fetch(0, 0), pre1 = fetch(0, 1);
+    for (uint32_t zb = 0; zb < W; ++zb) {
+        in[threadIdx.x] = pre0;
+        in[threadIdx.x + 256u] = pre1;
+        __syncthreads();
+        if (zb + 1 < W) {
+            pre0 = fetch(zb + 1, 0);
+            pre1 = fetch(zb + 1, 1);
+        }
+        // wave wv: block xb = 4 xg + wv; lane = row z - 64 zb
+        const uint32_t we = in[lane * 8u + wv], wo = in[lane * 8u + 4u + wv];
         uint64_t v = spread_bits(we) | (spread_bits(wo) << 1);
 #pragma unroll
         for (int st = 0; st < 6; ++st) {
@@ -617,12 +632,18 @@ __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, con
             const uint64_t o = ((uint64_t)ohi << 32) | olo;
             v = (lane & j) ? ((v & ~m) | ((o & ~m) >> j)) : ((v & m) | ((o & m) << j));
         }
-        // lane l now holds row z' = 64 xb + l: bit k is x' = 64 zb + k
-        const uint32_t zp = 64u * xb + lane;
-        const uint32_t cp = (y + zp) & 1u;            // colour of the even-x' sites of row z'
-        const size_t off = ((size_t)zp * L + y) * W + zb;
-        (cp ? Q1 : Q0)[off] = compact_bits(v);
-        (cp ? Q0 : Q1)[off] = compact_bits(v >> 1);
+        // lane now holds row z' = 64 xb + lane: bit k is x' = 64 zb + k
+        const uint32_t row = 64u * wv + lane;
+        out[(row * 2u + 0u) * W + zb] = compact_bits(v);
+        out[(row * 2u + 1u) * W + zb] = compact_bits(v >> 1);
+        __syncthreads();
+    }
+    // rows z' = 256 xg + row: parity slot p' goes to colour (p' + y + z') & 1
+    for (uint32_t k = threadIdx.x; k < 512u * W; k += blockDim.x) {
+        const uint32_t w = k % W, slot = (k / W) & 1u, row = k / (2u * W);
+        const uint32_t zp = 256u * xg + row;
+        const uint32_t c = slot ^ ((y + zp) & 1u);
+        (c ? Q1 : Q0)[((size_t)zp * L + y) * W + w] = out[k];
     }
 }
 
@@ -723,8 +744,8 @@ hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32
         const dim3 grid_gram((gg.ntile * gg.nsplit + 3) / 4);
         if (gram_x) {
             // x: the z axis of the lattice with x and z swapped (into Q)
-            hipLaunchKernelGGL(k_bit_swap_xz, dim3(L * (L / 64)), dim3(256), (size_t)128 * W * 4,
-                               st, L, W, P0, P1, Q0, Q1);
+            hipLaunchKernelGGL(k_bit_swap_xz, dim3(L * (W / 4)), dim3(256),
+                               (size_t)(512 * W + 512) * 4, st, L, W, P0, P1, Q0, Q1);
             hipLaunchKernelGGL((k_corr_gram<2, kGramNB>), grid_gram, dim3(256), 0, st, gg, Q0, Q1,
                                anti);
         }
