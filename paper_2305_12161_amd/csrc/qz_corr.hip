@@ -1,9 +1,11 @@
 // qz_corr.hip -- axis correlation sums of the 1-bit layout.
 //
 // S_a(r) = sum_i s_i s_{i + r e_a} = N - 2 * anti_a(r), where anti_a(r) counts
-// the site pairs at separation r along axis a whose spins differ; the kernels
-// accumulate anti_a(r) for r = 0..L/2 with XOR + popcount on 32 sites at a
-// time (the integer pieces of C(r,t), Results, eq:correlation function).
+// the site pairs at separation r along axis a whose spins differ (the integer
+// pieces of C(r,t), Results, eq:correlation function), for r = 0..L/2.  Where
+// L is a multiple of 256 they come from Gram matrices on the matrix cores
+// (k_corr_gram, further down); elsewhere the kernels below accumulate
+// anti_a(r) with XOR + popcount on 32 sites at a time.
 //
 // Lines along y or z: for x-parity pi, word column w and fixed other
 // coordinate o (z for the y axis, y for the z axis), the words
@@ -335,7 +337,8 @@ __global__ void __launch_bounds__(kBlock) k_corr_x(uint32_t L, uint32_t W, const
 }
 
 // ---------------------------------------------------------------------------
-// y and z axes on the matrix cores.  For axis a, row u is the plane of sites
+// Axis sums on the matrix cores (y and z directly, x through the copy with x
+// and z swapped, below).  For axis a, row u is the plane of sites
 // at coordinate u along a, and column k one of the L^2 lines along a; with
 // b = 1 for up spins, the Gram matrix G[u][u'] = sum_k b(u,k) b(u',k) gives
 //   T(r) = sum_u G[u][(u + r) mod L]   (up-up pairs at separation r),
