@@ -2,8 +2,9 @@
 """Benchmark of the zero-temperature checkerboard quench on one MI355X.
 
 Workload: the L=2048 quench (1-bit layout, seed 3, infinite-temperature start,
-1e5 MCS) with the unsatisfied-bond count fused into every sweep (recorded every
-10 MCS) and the axis correlation sums taken at the 40 log-spaced times.  A
+1e5 MCS) with the unsatisfied-bond count (and the accepted flips) fused into
+the sweeps at the 40 log-spaced times (--trace-every N: every N MCS instead)
+and the axis correlation sums taken at the same times.  A
 "step" is one Monte Carlo sweep of that run, including the measurements that
 fall on it; W untimed sweeps are followed by K timed ones (by default the timed
 window runs to t = 1e5, i.e. the whole job after the first W sweeps).
@@ -16,6 +17,7 @@ library's stream.  `cpu_baseline` is the CPU oracle on a bounded sample of the
 same lattice (a window replay), on this host's cores.
 """
 import argparse
+import bisect
 import hashlib
 import json
 import os
@@ -55,6 +57,9 @@ def parse():
                     help="sweeps per pass over memory (1 or 2; 0 = the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-corr", action="store_true", help="skip the correlation measurements")
+    ap.add_argument("--trace-every", type=int, default=0,
+                    help="trace B (and accepted flips) every N MCS; 0 (default): at the 40 "
+                         "log-spaced times of the run, as the L=2048 configuration asks")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-replica workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-request workload")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -209,7 +214,15 @@ def main():
     K = args.steps if args.steps is not None else max(1, t_max - W)
     corr_times = [] if args.no_corr else [t for t in workloads.log_times(t_max) if W < t <= W + K]
     N = L ** 3
-    every = 10
+    every = args.trace_every
+    # sweeps whose entering B (and accepted flips) are traced: the log-spaced
+    # times, or every `every` MCS; the last sweep always (for the final lengths)
+    if every > 0:
+        trace_times = list(range(0, W + K, every))
+    else:
+        trace_times = [t for t in workloads.log_times(t_max) if t < W + K]
+    trace_times = sorted(set(trace_times + [W + K - 1]))
+    trace_index = {t: i for i, t in enumerate(trace_times)}
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -221,32 +234,30 @@ def main():
     tune = lat.tuning()
     pcfg = lat.pass_config()
     per_launch = pcfg[0]   # sweeps carried by one launch of the dominant kernel
-    ntrace = (W + K) // every + 2
-    trace = torch.zeros(ntrace, dtype=torch.int64, device="cuda")
-    flips = torch.zeros(ntrace, dtype=torch.int64, device="cuda")
+    trace = torch.zeros(len(trace_times), dtype=torch.int64, device="cuda")
+    flips = torch.zeros(len(trace_times), dtype=torch.int64, device="cuda")
     print(f"# L={L} seed={seed} tuning={tune} warmup={W} steps={K} corr_times={len(corr_times)}",
           file=sys.stderr, flush=True)
 
     def advance(t_from, t_to, timing):
-        """Sweeps t_from..t_to-1, B traced at multiples of `every`."""
+        """Sweeps t_from..t_to-1; a traced time starts a segment whose first
+        sweep carries the fused bond count (and the flip count)."""
         t = t_from
         while t < t_to:
-            if t % every == 0:
-                n = t_to - t if t_to - t < every else ((t_to - t) // every) * every
-                ev = every if n % every == 0 else n
-                sl = trace[t // every: t // every + n // ev]
-                fl = flips[t // every: t // every + n // ev]
-                if timing is not None:
-                    a = torch.cuda.Event(enable_timing=True)
-                    b = torch.cuda.Event(enable_timing=True)
-                    a.record(stream)
-                lat.run_device_traced(n, ev, sl, fl)
-                if timing is not None:
-                    b.record(stream)
-                    timing.append((a, b, n, t))
+            k = bisect.bisect_right(trace_times, t)
+            n = (min(trace_times[k], t_to) if k < len(trace_times) else t_to) - t
+            if timing is not None:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+            if t in trace_index:
+                i = trace_index[t]
+                lat.run_device_traced(n, n, trace[i:i + 1], flips[i:i + 1])
             else:
-                n = min(t_to - t, every - t % every)
                 lat.run_device(n, 0, None)
+            if timing is not None:
+                b.record(stream)
+                timing.append((a, b, n, t))
             t += n
 
     # warmup (untimed)
@@ -298,7 +309,11 @@ def main():
             traffic = tr.get("bytes_per_launch")
 
     from paper_2305_12161_amd import measure
-    B_last = int(trace[(W + K - 1) // every].item()) if W + K > 0 else 0
+    B_last = int(trace[trace_index[W + K - 1]].item())
+    window = [trace_index[x] for x in trace_times if W <= x < W + K]
+    bond_cadence = (f"every {every} MCS" if every > 0 else
+                    f"at the {len(window)} of 40 log-spaced times in the timed window and "
+                    f"the last sweep")
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -315,7 +330,7 @@ def main():
         "config": {
             "workload": f"L{L}_bit_quench: periodic L={L} simple-cubic Ising, 1-bit colour-separated "
                         f"spins, seed {seed}, T=inf start, T=0 checkerboard dynamics to t={W + K} MCS, "
-                        f"unsatisfied-bond count every {every} MCS, axis C(r<=L/2) at the "
+                        f"unsatisfied-bond count (fused) {bond_cadence}, axis C(r<=L/2) at the "
                         f"{len(corr_times)} of 40 log-spaced times in the timed window",
             "L": L, "layout": "bit", "seed": seed, "t_window": [W, W + K],
             "tuning_V_Ty_Tz": list(tune), "sweeps_per_pass": pcfg[0],
@@ -337,6 +352,12 @@ def main():
             "frac_t_ge_1e4": (round((N // 4) / late_s / 1e9 / HBM_PEAK_GBS, 4)
                               if late_s else None),
             "avg_ms_per_sweep_t_ge_1e4": round(late_s * 1e3, 5) if late_s else None,
+            # the bytes the kernel really moves (counter-measured `traffic`) over
+            # the same launch time: a two-sweep launch keeps the state between
+            # its sweeps on chip, so `achieved` (algorithmic) can exceed the peak
+            "traffic_GBs": round(traffic / launch_s / 1e9, 1) if traffic else None,
+            "traffic_frac": (round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+                             if traffic else None),
         },
         "sweep_only_attempts_per_ns": round(N / avg_sweep_s / 1e9, 2),
         "corr_ms_mean": round(sum(corr_ms) / len(corr_ms), 3) if corr_ms else None,
@@ -345,9 +366,9 @@ def main():
         # accepted moves (a physics output, not the work unit): flips per site in
         # the traced sweeps of the timed window, and in the last one
         "accepted_flips_per_site_window_mean": round(
-            float(flips[W // every:(W + K - 1) // every + 1].double().mean().item()) / N, 7),
+            float(flips[window].double().mean().item()) / N, 7),
         "accepted_flips_per_site_last": round(
-            int(flips[(W + K - 1) // every].item()) / N, 7),
+            int(flips[trace_index[W + K - 1]].item()) / N, 7),
         "ell_C_final": (round(measure.crossing_length(ells[-1][1], ells[-1][2], N), 4)
                         if ells else None),
     }
