@@ -62,6 +62,8 @@ def parse():
                          "log-spaced times of the run, as the L=2048 configuration asks")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-replica workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-request workload")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the mixed-cycle, double-checkerboard and FFT measurements")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=None,
                     help="arrivals per second (default: the configured literal)")
@@ -157,6 +159,57 @@ def served_workload(binding, torch, workloads, n_req, rate):
     for k in ("p50_latency_s", "p99_latency_s", "attempts_per_ns", "wall_s"):
         st[k] = round(st[k], 4)
     return st
+
+
+def next_rows_workload(binding, torch, L, seed):
+    """The rows beyond the plain path, on the L = 2048 start advanced 100 MCS:
+    the mixed cycle (colour order drawn per sweep; one sweep per pass), the
+    double checkerboard (coarse cubes of side 8 and 16, both cycles), and the
+    double-precision FFT correlation with shell averages (at L = 1024)."""
+    st = torch.cuda.current_stream()
+
+    def per_sweep_ms(lat, n):
+        lat.run(2)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        lat.run(n)
+        b.record(st)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    def rates(ms):
+        return {"ms_per_sweep": round(ms, 4),
+                "attempts_per_ns": round(L ** 3 / (ms * 1e6), 1),
+                # N/4 algorithmic bytes per sweep against the HBM peak
+                "roofline_frac": round((L ** 3 // 4) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    out = {"L": L, "start": "seed %d, t = 100" % seed}
+    lat = binding.Lattice(L, seed, "bit")
+    lat.run(100)
+    lat.set_pass(1)
+    out["plain_01_one_sweep_pass"] = rates(per_sweep_ms(lat, 40))
+    lat.set_cycle(True)
+    out["mixed_cycle"] = rates(per_sweep_ms(lat, 40))
+    for B in (8, 16):
+        lat.set_double_checkerboard(B)
+        for mixed in (False, True):
+            lat.set_cycle(mixed)
+            key = "double_checkerboard_B%d_%s" % (B, "mixed" if mixed else "01")
+            out[key] = rates(per_sweep_ms(lat, 10))
+    del lat
+    torch.cuda.empty_cache()
+    Lf = 1024
+    f = binding.Lattice(Lf, seed, "bit")
+    f.run(100)
+    f.fft_corr()                   # plan and scratch once
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.fft_corr()
+    out["fft_corr_L1024_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    del f
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(L, seed, budget_s=15.0):
@@ -387,6 +440,8 @@ def main():
     if not args.no_serve:
         rate = args.serve_rate if args.serve_rate else workloads.SERVE_RATE_PER_S
         leg("served", lambda: served_workload(binding, torch, workloads, args.serve_requests, rate))
+    if not args.no_next:
+        leg("next_rows", lambda: next_rows_workload(binding, torch, L, seed))
     if not args.no_cpu_baseline:
         leg("cpu_baseline", lambda: cpu_baseline(L, seed))
     print(json.dumps(out), flush=True)

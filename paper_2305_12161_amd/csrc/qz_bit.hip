@@ -306,6 +306,117 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// The same phase with four consecutive words per lane (W % 4 == 0): one
+// Philox block covers the lane's tie bits (its first word index is a multiple
+// of 4), the words move as 16-byte vectors, and the rows come from a 2D
+// mapping instead of 64-bit divisions.  In the mixed cycle the cube-order
+// bits of the four words come from at most two Philox blocks.
+__device__ __forceinline__ uint32_t cube_bits_mask(uint32_t bits, uint32_t q)
+{
+    // bits: bit k = cube (first cube of the word) + k; word bit b lies in cube
+    // column offset b >> q
+    if (q >= 5)
+        return (bits & 1u) ? 0xFFFFFFFFu : 0u;
+    uint32_t m = 0u;
+#pragma unroll
+    for (uint32_t b = 0; b < 32; ++b)
+        m |= ((bits >> (b >> q)) & 1u) << b;
+    return m;
+}
+
+__global__ void __launch_bounds__(256)
+    k_bit_phase4(uint32_t L, uint32_t W, uint32_t sB, uint32_t kc, uint32_t p, uint32_t k0,
+                 uint32_t k1, uint32_t t, uint32_t *Pp, const uint32_t *Po, uint32_t mixed,
+                 uint32_t step, unsigned long long *flip_acc)
+{
+    uint32_t flips = 0;
+    const uint32_t R = W / 4;                       // lanes per row
+    const uint32_t rpb = 256u / R;                  // rows per block
+    const uint32_t lr = threadIdx.x / R;
+    const uint32_t row = blockIdx.x * rpb + lr;     // z * L + y
+    const bool act = lr < rpb && row < L * L;
+    const uint32_t cc = mixed ? (kc ^ (philox10(0u, t, 3u, 0u, k0, k1).w[0] & 1u)) : kc;
+    const uint32_t q = sB - 1;
+    const uint32_t pat = (q == 0) ? 0xAAAAAAAAu : (q == 1) ? 0xCCCCCCCCu : (q == 2) ? 0xF0F0F0F0u
+                       : (q == 3) ? 0xFF00FF00u : (q == 4) ? 0xFFFF0000u : 0u;
+    if (act) {
+        const uint32_t w0 = (threadIdx.x % R) * 4u;
+        const uint32_t y = row % L, z = row / L;
+        uint32_t mask[4], any = 0u;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t w = w0 + (uint32_t)v;
+            const uint32_t A = (((32u * w) >> q) + (y >> sB) + (z >> sB)) & 1u;
+            mask[v] = ((A ^ cc) & 1u) ? pat : ~pat;
+            any |= mask[v];
+        }
+        if (mixed && any != 0u) {
+            // cubes whose fine colour in this step is p: first == p ^ step
+            const uint32_t nb = L >> sB;
+            const uint64_t cbase = (uint64_t)nb * ((uint64_t)(y >> sB) + (uint64_t)nb * (z >> sB));
+            uint32_t blk = 0xFFFFFFFFu;
+            Words4 o;
+            any = 0u;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint64_t cb0 = (uint64_t)((32u * (w0 + (uint32_t)v)) >> q) + cbase;
+                if ((uint32_t)(cb0 >> 7) != blk) {
+                    blk = (uint32_t)(cb0 >> 7);
+                    o = philox10(blk, t, 4u, 0u, k0, k1);
+                }
+                const uint32_t sub = (uint32_t)(cb0 >> 5) & 3u;
+                const uint32_t word = (sub & 2u) ? ((sub & 1u) ? o.w[3] : o.w[2])
+                                                 : ((sub & 1u) ? o.w[1] : o.w[0]);
+                const uint32_t first1 = cube_bits_mask(word >> (uint32_t)(cb0 & 31u), q);
+                mask[v] &= ((p ^ step) & 1u) ? first1 : ~first1;
+                any |= mask[v];
+            }
+        }
+        if (any != 0u) {
+            const uint32_t pi = (p + y + z) & 1u;
+            const size_t plane = (size_t)L * W;
+            const size_t rb = (size_t)row * W;
+            const size_t zb = (size_t)z * plane;
+            uint32_t own[4], same[4], ym[4], yp[4], zm[4], zp[4];
+            bitops::load_words<4>(Pp + rb + w0, own);
+            bitops::load_words<4>(Po + rb + w0, same);
+            bitops::load_words<4>(Po + zb + (size_t)((y + L - 1) % L) * W + w0, ym);
+            bitops::load_words<4>(Po + zb + (size_t)((y + 1) % L) * W + w0, yp);
+            bitops::load_words<4>(Po + (size_t)((z + L - 1) % L) * plane + (size_t)y * W + w0, zm);
+            bitops::load_words<4>(Po + (size_t)((z + 1) % L) * plane + (size_t)y * W + w0, zp);
+            const uint32_t adj = pi ? Po[rb + (w0 + 4u) % W] : Po[rb + (w0 + W - 1u) % W];
+            UpCount u[4];
+            uint32_t ties = 0u;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                u[v] = count_up(same[v], bitops::shifted_word<4>(same, adj, pi, v), ym[v], yp[v],
+                                zm[v], zp[v]);
+                ties |= up_tie(u[v]) & mask[v];
+            }
+            uint32_t r[4] = {0u, 0u, 0u, 0u};
+            if (ties != 0u) {
+                const Words4 rb4 = philox10((uint32_t)((rb + w0) >> 2), t, p, 0u, k0, k1);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    r[v] = rb4.w[v];
+            }
+            uint32_t nw[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint32_t n = up_rule(own[v], u[v], r[v]);
+                nw[v] = (own[v] & ~mask[v]) | (n & mask[v]);
+                flips = popc_acc(own[v] ^ nw[v], flips);
+            }
+            bitops::store_words<4>(Pp + rb + w0, nw);
+        }
+    }
+    if (flip_acc != nullptr) {
+        const unsigned long long ws = wave_sum_u64((unsigned long long)flips);
+        if ((threadIdx.x & 63) == 0 && ws)
+            atomicAdd(flip_acc, ws);
+    }
+}
+
 // --------------------------------------------------------------------------
 // initial state: thread h covers lattice sites i = 64h .. 64h+63 (one row
 // segment), i.e. one word of each colour.
@@ -599,12 +710,20 @@ hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t see
     // 01 cycle: (coarse, fine) = (0,0), (0,1), (1,0), (1,1).  Mixed cycle: for
     // each coarse colour in the drawn order, two steps, each one launch per plane.
     const uint32_t nsteps = mixed ? 2u : 1u;
+    const bool quads = W % 4 == 0;
+    const uint32_t rpb = quads ? 256u / (W / 4) : 1u;
+    const dim3 grid4((uint32_t)(((uint64_t)L * L + rpb - 1) / rpb));
     for (uint32_t kc = 0; kc < 2; ++kc)
         for (uint32_t step = 0; step < nsteps; ++step)
             for (uint32_t p = 0; p < 2; ++p) {
-                hipLaunchKernelGGL(k_bit_phase, dim3(grid_cap(nw, 8192)), dim3(256), 0, st, L, W,
-                                   sB, kc, p, (uint32_t)seed, (uint32_t)(seed >> 32), t,
-                                   p ? P1 : P0, p ? P0 : P1, mixed ? 1u : 0u, step, flip_acc);
+                if (quads)
+                    hipLaunchKernelGGL(k_bit_phase4, grid4, dim3(256), 0, st, L, W, sB, kc, p,
+                                       (uint32_t)seed, (uint32_t)(seed >> 32), t, p ? P1 : P0,
+                                       p ? P0 : P1, mixed ? 1u : 0u, step, flip_acc);
+                else
+                    hipLaunchKernelGGL(k_bit_phase, dim3(grid_cap(nw, 8192)), dim3(256), 0, st, L,
+                                       W, sB, kc, p, (uint32_t)seed, (uint32_t)(seed >> 32), t,
+                                       p ? P1 : P0, p ? P0 : P1, mixed ? 1u : 0u, step, flip_acc);
                 const hipError_t e = hipGetLastError();
                 if (e != hipSuccess)
                     return e;

@@ -498,7 +498,8 @@ def test_fft_corr_matches_oracle(qz, orc, layout, L, n):
 # double checkerboard (coarse cubes of side B)
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("mixed", [False, True], ids=["01", "mixed"])
-@pytest.mark.parametrize("L,B", [(64, 2), (64, 8), (64, 32), (128, 4), (128, 64), (256, 16)])
+@pytest.mark.parametrize("L,B", [(64, 2), (64, 8), (64, 32), (128, 4), (128, 64), (256, 16),
+                                 (256, 2), (256, 4), (256, 64), (256, 128), (512, 8)])
 def test_double_checkerboard_matches_oracle(qz, orc, L, B, mixed):
     seed = 90 + L + B + (1000 if mixed else 0)
     say("double checkerboard", L, B, "mixed" if mixed else "01")
@@ -530,7 +531,8 @@ def test_double_checkerboard_rejects(qz):
 @pytest.mark.parametrize("layout,L,mode", [("i8", 16, "01"), ("i8", 34, "mixed"),
                                            ("bit", 64, "01"), ("bit", 128, "mixed"),
                                            ("bit", 128, "pass2"), ("bit", 192, "pass2"),
-                                           ("bit", 64, "dcb"), ("bit", 128, "dcb-mixed")])
+                                           ("bit", 64, "dcb"), ("bit", 128, "dcb-mixed"),
+                                           ("bit", 256, "dcb"), ("bit", 256, "dcb-mixed")])
 def test_flip_trace_matches_oracle(qz, orc, layout, L, mode):
     seed = 300 + L
     say("flips", layout, L, mode)
