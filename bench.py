@@ -163,7 +163,8 @@ def served_workload(binding, torch, workloads, n_req, rate):
 
 def next_rows_workload(binding, torch, L, seed):
     """The rows beyond the plain path, on the L = 2048 start advanced 100 MCS:
-    the mixed cycle (colour order drawn per sweep; one sweep per pass), the
+    the mixed cycle (colour order drawn per sweep; one and two sweeps per
+    pass), the
     double checkerboard (coarse cubes of side 8 and 16, both cycles), and the
     double-precision FFT correlation with shell averages (at L = 1024)."""
     st = torch.cuda.current_stream()
@@ -190,7 +191,11 @@ def next_rows_workload(binding, torch, L, seed):
     lat.set_pass(1)
     out["plain_01_one_sweep_pass"] = rates(per_sweep_ms(lat, 40))
     lat.set_cycle(True)
-    out["mixed_cycle"] = rates(per_sweep_ms(lat, 40))
+    out["mixed_cycle_one_sweep_pass"] = rates(per_sweep_ms(lat, 40))
+    # two sweeps per pass where consecutive sweeps draw the same first colour
+    lat.set_pass(2)
+    out["mixed_cycle"] = rates(per_sweep_ms(lat, 80))
+    lat.set_pass(1)
     for B in (8, 16):
         lat.set_double_checkerboard(B)
         for mixed in (False, True):

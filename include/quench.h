@@ -163,10 +163,11 @@ int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
  * and writes the lattice once.  sweeps = 2: sweeps t and t+1 run
  * in one pass that keeps the state after sweep t on chip, halving the memory
  * traffic per sweep; the trajectory, the bond trace and every measurement are
- * identical to sweeps = 1 (Methods, "Checkerboard update": the 01 cycle is
- * applied exactly as before).  Runs of an odd number of sweeps end with one
- * single sweep; the mixed cycle and the double checkerboard always run one
- * sweep per pass.  V, Ty, Tz tune the two-sweep kernel as in qz_set_tuning
+ * identical to sweeps = 1 (Methods, "Checkerboard update").  Runs of an odd
+ * number of sweeps end with one single sweep; in the mixed cycle two sweeps
+ * share a pass only when both draw the same first colour (otherwise the
+ * first runs alone); the double checkerboard always runs one sweep per pass.
+ * V, Ty, Tz tune the two-sweep kernel as in qz_set_tuning
  * (V words per lane, Ty owned rows per tile, Ty + 8 rows held, Tz planes);
  * all three 0 selects the default for L.  QZ_EINVAL for another sweep count
  * or a tuning that does not fit (at most 1024 threads and 64 KiB of LDS per

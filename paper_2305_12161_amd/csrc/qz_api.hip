@@ -130,14 +130,15 @@ int sweep_once(qz_lattice *q, unsigned long long *bond_acc, unsigned long long *
     return QZ_OK;
 }
 
-// Sweeps t and t+1 in one pass (bit layout, plain checkerboard, 01 cycle).
+// Sweeps t and t+1 in one pass (bit layout, plain checkerboard), both updating
+// colour `first` first: always colour 0 in the 01 cycle.
 int sweep_pair(qz_lattice *q, unsigned long long *acc_a, unsigned long long *acc_c,
-               unsigned long long *flip_a, unsigned long long *flip_c)
+               unsigned long long *flip_a, unsigned long long *flip_c, uint32_t first)
 {
     const int a = q->cur, b = 1 - q->cur;
     QZ_HIP(q, qz::bit_sweep2(q->st, q->L, q->seed, (uint32_t)q->t, q->tune2, bit_plane(q, a, 0),
                              bit_plane(q, a, 1), bit_plane(q, b, 0), bit_plane(q, b, 1), acc_a,
-                             acc_c, flip_a, flip_c));
+                             acc_c, flip_a, flip_c, first));
     q->cur = b;
     q->t += 2;
     return QZ_OK;
@@ -146,18 +147,47 @@ int sweep_pair(qz_lattice *q, unsigned long long *acc_a, unsigned long long *acc
 // n sweeps; with every > 0, sweep k (k % every == 0) adds its entering bond
 // count to dev_trace[k / every] and its accepted flips to dev_flips[k / every]
 // (either pointer may be null).
+// Bit 0 of word 0 of the Philox4x32-10 block (0, t, 2, 0) under the key
+// (seed mod 2^32, seed >> 32): 1 when colour 1 goes first in sweep t of the
+// mixed cycle (Supplementary Methods I B), as the sweep kernels draw it.  The
+// host needs it to find consecutive sweeps with the same order.
+uint32_t mixed_first_colour(uint64_t seed, uint32_t t)
+{
+    uint32_t c0 = 0u, c1 = t, c2 = 2u, c3 = 0u;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0, pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c0 & 1u;
+}
+
 int run_impl(qz_lattice *q, uint64_t n, uint64_t every, unsigned long long *dev_trace,
              unsigned long long *dev_flips)
 {
-    const bool pairs = q->pass == 2 && q->layout == QZ_LAYOUT_BIT && !q->mixed && q->dcb == 0;
+    const bool pairs = q->pass == 2 && q->layout == QZ_LAYOUT_BIT && q->dcb == 0;
     auto slot = [&](unsigned long long *base, uint64_t k) -> unsigned long long * {
         return (every > 0 && base != nullptr && k % every == 0) ? base + k / every : nullptr;
     };
     for (uint64_t k = 0; k < n;) {
         int rc;
-        if (pairs && n - k >= 2) {
+        uint32_t first = 0u;
+        bool pair = pairs && n - k >= 2;
+        if (pair && q->mixed) {
+            // a pass carries two sweeps only when both update the same colour first
+            first = mixed_first_colour(q->seed, (uint32_t)q->t);
+            pair = mixed_first_colour(q->seed, (uint32_t)q->t + 1u) == first;
+        }
+        if (pair) {
             rc = sweep_pair(q, slot(dev_trace, k), slot(dev_trace, k + 1), slot(dev_flips, k),
-                            slot(dev_flips, k + 1));
+                            slot(dev_flips, k + 1), first);
             k += 2;
         } else {
             rc = sweep_once(q, slot(dev_trace, k), slot(dev_flips, k));

@@ -10,7 +10,10 @@
 //   B  sweep t,   colour 1 of plane q-1  from A's colour 0 of planes q-2, q-1, q
 //   C  sweep t+1, colour 0 of plane q-2  from B's colour 1 of planes q-3, q-2, q-1
 //   D  sweep t+1, colour 1 of plane q-3  from C's colour 0 of planes q-4, q-3, q-2
-// (Methods, "Checkerboard update": each colour reads only the other one).  The
+// (Methods, "Checkerboard update": each colour reads only the other one);
+// "colour 0" here is the colour updated first in both sweeps, which the
+// mixed cycle draws per sweep (Supplementary Methods I B): pairs of sweeps
+// that draw the same first colour run here with the planes exchanged.  The
 // y-neighbour rows of every stage's input come from LDS (four row sets per
 // step, double-buffered, one barrier per step); each stage loses one row at
 // each side, so the tile owns rows [4, E-4) and recomputes the rest, and it
@@ -37,6 +40,7 @@ struct Sweep2Args {
     uint32_t L, W, R;                   // R = W / V lanes per row
     uint32_t Ty, E, Tz, nty;            // E = Ty + 8 rows held per tile
     uint32_t k0, k1, t;
+    uint32_t f;                         // colour updated first in both sweeps
 };
 
 template <int V>
@@ -127,10 +131,10 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
                          uint32_t (&d)[V]) {
         const uint32_t ga = gword(z), gb = gword((z + L - 1) % L);
         const uint32_t gc = gword((z + L - 2) % L), gd = gword((z + L - 3) % L);
-        tie_words<V>(A.k0, A.k1, ga, ga & 3u, A.t, 0u, a);
-        tie_words<V>(A.k0, A.k1, gb, gb & 3u, A.t, 1u, b);
-        tie_words<V>(A.k0, A.k1, gc, gc & 3u, A.t + 1u, 0u, c);
-        tie_words<V>(A.k0, A.k1, gd, gd & 3u, A.t + 1u, 1u, d);
+        tie_words<V>(A.k0, A.k1, ga, ga & 3u, A.t, A.f, a);
+        tie_words<V>(A.k0, A.k1, gb, gb & 3u, A.t, 1u - A.f, b);
+        tie_words<V>(A.k0, A.k1, gc, gc & 3u, A.t + 1u, A.f, c);
+        tie_words<V>(A.k0, A.k1, gd, gd & 3u, A.t + 1u, 1u - A.f, d);
     };
     uint32_t sA[V], sB[V], sC[V], sD[V];   // tie words of the next step's stages
     draw_step((z0 + L - 3) % L, sA, sB, sC, sD);
@@ -165,7 +169,7 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
         __syncthreads();
 
         // all four stages update sites with the same x parity in this row
-        uint32_t pi = (y + zq) & 1u;
+        uint32_t pi = (A.f + y + zq) & 1u;
         if constexpr (PAIRED)
             pi = __builtin_amdgcn_readfirstlane(pi);   // the same in every lane of the wave
         const uint32_t wadj = pi == 0u ? wprev : wnext;
@@ -370,12 +374,18 @@ int bit_pass_default(uint32_t L) { return L >= 1024 ? 2 : 1; }
 hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                       const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
                       unsigned long long *acc_a, unsigned long long *acc_c,
-                      unsigned long long *flip_a, unsigned long long *flip_c)
+                      unsigned long long *flip_a, unsigned long long *flip_c, uint32_t first)
 {
-    if (!bit_tuning2_valid(L, tu))
+    if (!bit_tuning2_valid(L, tu) || first > 1u)
         return hipErrorInvalidValue;
     Sweep2Args a;
-    a.S0 = S0; a.S1 = S1; a.D0 = D0; a.D1 = D1;
+    // the kernel's stages A and C update "colour 0", B and D "colour 1": here
+    // the colour updated first, and the other
+    a.S0 = first ? S1 : S0;
+    a.S1 = first ? S0 : S1;
+    a.D0 = first ? D1 : D0;
+    a.D1 = first ? D0 : D1;
+    a.f = first;
     a.acc_a = acc_a;
     a.acc_c = acc_c;
     a.flip_a = flip_a;

@@ -64,7 +64,8 @@ hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, cons
 hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                       const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
                       unsigned long long *acc_a, unsigned long long *acc_c,
-                      unsigned long long *flip_a = nullptr, unsigned long long *flip_c = nullptr);
+                      unsigned long long *flip_a = nullptr, unsigned long long *flip_c = nullptr,
+                      uint32_t first = 0);
 hipError_t bit_bonds(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
                      unsigned long long *acc3);
 hipError_t bit_bonds_total(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,

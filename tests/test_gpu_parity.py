@@ -197,11 +197,44 @@ def test_two_sweep_pass_trace_alignment(qz, orc, every, n):
     assert lat.t == t0 + n
 
 
+@pytest.mark.parametrize("L,tuning", [(64, (1, 24, 5)), (128, (2, 56, 8)), (256, (4, 120, 5)),
+                                      (256, (4, 24, 32))])
+def test_two_sweep_pass_mixed_cycle(qz, orc, L, tuning):
+    """The mixed cycle with two sweeps per pass: consecutive sweeps that draw
+    the same first colour share a pass (planes exchanged when it is colour
+    1), the others run alone; every sweep traced, against the oracle."""
+    n = 21
+
+    def shared_passes(seed):   # first colours of the pairs that share a pass
+        fc = [orc.first_colour(seed, t) for t in range(n)]
+        t, out = 0, []
+        while t < n:
+            if t + 1 < n and fc[t] == fc[t + 1]:
+                out.append(fc[t])
+                t += 2
+            else:
+                t += 1
+        return set(out)
+
+    seed = 700 + L
+    while shared_passes(seed) != {0, 1}:   # a run with passes of both orders
+        seed += 1
+    s = orc.init(L, seed)
+    want = orc.run(s, seed, 0, n, 1, mixed=True)
+    lat = qz.Lattice(L, seed, "bit")
+    lat.set_cycle(True)
+    lat.set_pass(2, *tuning)
+    say("two-sweep mixed", L, tuning, seed)
+    tr = lat.run(n, 1)
+    assert np.array_equal(tr.astype(np.int64), want)
+    assert np.array_equal(lat.download(), s)
+
+
 def test_two_sweep_pass_falls_back_and_rejects(qz, orc):
     L, seed = 64, 8
     lat = qz.Lattice(L, seed, "bit")
     lat.set_pass(2)
-    lat.set_cycle(True)        # the mixed cycle runs one sweep per pass
+    lat.set_cycle(True)        # the mixed cycle pairs only sweeps of equal order
     tr = lat.run(5, 1)
     s = orc.init(L, seed)
     want = orc.run(s, seed, 0, 5, 1, mixed=True)
