@@ -108,38 +108,42 @@ __global__ void __launch_bounds__(kFftBlock)
         bcnt[b] = 0u;
     }
     __syncthreads();
-    const uint64_t N = (uint64_t)L * L * L;
-    // each thread walks a run of x at fixed (y, z), merging equal shells locally
+    // one wave per row (y, z); each lane walks 8 consecutive x, so a wave
+    // reads 512 consecutive values per step, and merges equal shells along its
+    // run before adding them to the block's sums
     const uint64_t rows = (uint64_t)L * L;
-    for (uint64_t row = (uint64_t)blockIdx.x * kFftBlock + threadIdx.x; row < rows;
-         row += (uint64_t)gridDim.x * kFftBlock) {
+    const uint32_t lane = threadIdx.x & 63u, nwv = kFftBlock / 64u;
+    for (uint64_t row = (uint64_t)blockIdx.x * nwv + (threadIdx.x >> 6); row < rows;
+         row += (uint64_t)gridDim.x * nwv) {
         const int dy = signed_comp((uint32_t)(row % L), L), dz = signed_comp((uint32_t)(row / L), L);
         const double base = (double)dy * dy + (double)dz * dz;
         const double *r = R + row * pad;
-        uint32_t cur = 0xFFFFFFFFu;
-        double acc = 0.0;
-        unsigned int cnt = 0u;
-        for (uint32_t x = 0; x < L; ++x) {
-            const int dx = signed_comp(x, L);
-            const uint32_t bin = (uint32_t)rint(sqrt(base + (double)dx * dx));
-            if (bin != cur) {
-                if (cnt && cur < nb) {
-                    atomicAdd(bsum + cur, acc);
-                    atomicAdd(bcnt + cur, cnt);
+        for (uint32_t x0 = 8u * lane; x0 < L; x0 += 512u) {
+            const uint32_t xe = min(x0 + 8u, L);
+            uint32_t cur = 0xFFFFFFFFu;
+            double acc = 0.0;
+            unsigned int cnt = 0u;
+            for (uint32_t x = x0; x < xe; ++x) {
+                const int dx = signed_comp(x, L);
+                const uint32_t bin = (uint32_t)rint(sqrt(base + (double)dx * dx));
+                if (bin != cur) {
+                    if (cnt && cur < nb) {
+                        atomicAdd(bsum + cur, acc);
+                        atomicAdd(bcnt + cur, cnt);
+                    }
+                    cur = bin;
+                    acc = 0.0;
+                    cnt = 0u;
                 }
-                cur = bin;
-                acc = 0.0;
-                cnt = 0u;
+                acc += r[x];
+                ++cnt;
             }
-            acc += r[x];
-            ++cnt;
-        }
-        if (cnt && cur < nb) {
-            atomicAdd(bsum + cur, acc);
-            atomicAdd(bcnt + cur, cnt);
+            if (cnt && cur < nb) {
+                atomicAdd(bsum + cur, acc);
+                atomicAdd(bcnt + cur, cnt);
+            }
         }
     }
-    (void)N;
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += kFftBlock)
         if (bcnt[b]) {
@@ -194,7 +198,8 @@ hipError_t fft_radial(hipStream_t st, uint32_t L, const double *X, uint32_t nb, 
                       unsigned long long *c_cnt)
 {
     const uint64_t rows = (uint64_t)L * L;
-    const uint32_t g = (uint32_t)std::min<uint64_t>((rows + kFftBlock - 1) / kFftBlock, 8192);
+    const uint64_t rows_per_block = kFftBlock / 64;   // one wave per row
+    const uint32_t g = (uint32_t)std::min<uint64_t>((rows + rows_per_block - 1) / rows_per_block, 16384);
     const size_t lds = (size_t)nb * (8 + 4);
     hipLaunchKernelGGL(k_fft_radial, dim3(g), dim3(kFftBlock), lds, st, L, fft_pad(L), X, nb,
                        c_sum, c_cnt);
