@@ -70,11 +70,11 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
     for (int v = 0; v < 4; ++v)
         c1m[v] = c1c[v] = c1p[v] = c0o[v] = n0m2[v] = n0m1[v] = n0c[v] = c1n[v] = pf1[v] = pf0[v] = 0u;
     auto ld4 = [&](const uint32_t *P, uint32_t z, uint32_t (&r)[4]) {
-        const uint4 q = *reinterpret_cast<const uint4 *>(P + (size_t)z * PW + g0);
+        const uint4 q = *reinterpret_cast<const uint4 *>(P + (z * PW + g0));
         r[0] = q.x; r[1] = q.y; r[2] = q.z; r[3] = q.w;
     };
     auto st4 = [&](uint32_t *P, uint32_t z, const uint32_t (&r)[4]) {
-        *reinterpret_cast<uint4 *>(P + (size_t)z * PW + g0) = make_uint4(r[0], r[1], r[2], r[3]);
+        *reinterpret_cast<uint4 *>(P + (z * PW + g0)) = make_uint4(r[0], r[1], r[2], r[3]);
     };
     const uint32_t z0 = T.z0;
     if (act) {
@@ -95,9 +95,12 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
         uint32_t n0[4], n1[4], n2[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+            // pi differs between the lanes of a wave (and between the words of
+            // a lane where rows are shorter than four words): select the
+            // funnel's operands rather than branch on it
             const uint32_t pi = (colour + yv[v] + zp_plane) & 1u;
             const uint32_t adj = Xo[pi ? gnx[v] : gpr[v]];
-            n0[v] = pi ? funnel(adj, same[v], 1) : funnel(same[v], adj, 31);
+            n0[v] = funnel(pi ? adj : same[v], pi ? same[v] : adj, pi ? 1u : 31u);
             n1[v] = Xo[gym[v]];
             n2[v] = Xo[gyp[v]];
         }
@@ -137,12 +140,14 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
         draw((z0 + L - 2) % L, 1u, s1);
     }
 
+    // the step's plane zq and its neighbours, advanced with one wrap test per
+    // step instead of divisions by L
+    uint32_t zq = (z0 + L - 1) % L;
+    uint32_t zm = (zq + L - 1) % L, z1 = (zq + 1) % L, z2 = (zq + 2) % L;
     for (int qi = -1; qi <= (int)nz; ++qi) {
-        const uint32_t zq = (z0 + L + qi) % L;
-        const uint32_t zm = (zq + L - 1) % L;
         if (act && qi < (int)nz) {
-            ld4(S1, (zq + 2) % L, pf1);
-            ld4(S0, (zq + 1) % L, pf0);
+            ld4(S1, z2, pf1);
+            ld4(S0, z1, pf0);
         }
         uint32_t *X1 = X1base + (size_t)(qi & 1) * 2 * PW;
         uint32_t *X0 = X1 + PW;
@@ -157,7 +162,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
             r1[v] = s1[v];
         }
         if (act) {
-            draw((zq + 1) % L, 0u, s0);
+            draw(z1, 0u, s0);
             draw(zq, 1u, s1);
         }
         __syncthreads();
@@ -180,6 +185,10 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
                 n0m1[v] = n0c[v];
             }
         }
+        zm = zq;
+        zq = z1;
+        z1 = z2;
+        z2 = (z2 + 1u == L) ? 0u : z2 + 1u;
     }
     // per-sub-tile bond sums -> the replica's trace slot
     __syncthreads();
