@@ -19,13 +19,21 @@ namespace qz {
 namespace {
 
 constexpr int kBatchBlock = 256;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
+// The body of one workgroup's sweep.  WK = words per colour row when the
+// rows are 1, 2 or 4 words long (L = 64, 128, 256): a lane's quad then holds
+// whole rows, so its x-neighbour words are its own and its y-neighbour words
+// are its own or one vector read of the next lane's quad.  WK = 0: any L, with
+// per-word neighbour indices.
+template <int WK>
+__device__ __forceinline__ void batch_body(const BatchArgs &A)
 {
     extern __shared__ uint32_t lds[];
     const uint32_t tid = threadIdx.x;
     const BatchGroup G = A.groups[blockIdx.x];          // all sub-tiles of this block share L, nz
-    const uint32_t L = G.L, W = L / 64, PW = L * W;    // words per plane
+    const uint32_t L = WK ? 64u * WK : G.L;
+    const uint32_t W = L / 64, PW = L * W;             // words per plane
     const uint32_t Q = PW / 4;                          // quads (lanes) per plane
     const uint32_t S = kBatchBlock / Q >= 1 ? kBatchBlock / Q : 1;
     const uint32_t sub = tid / Q, lane = tid % Q;
@@ -63,18 +71,24 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
         gpr[v] = (w == 0) ? g + W - 1 : g - 1;          // x-neighbour at colour index k-1
         gnx[v] = (w == W - 1) ? g + 1 - W : g + 1;      // x-neighbour at colour index k+1
     }
+    // WK > 0: the quad is rows y0 .. y0 + 4/WK - 1; the words of row y0 - 1
+    // start at lm, those of the row after the quad at lp
+    const uint32_t y0 = g0 / W, rows = 4 / W;
+    const uint32_t lm = ((y0 + L - 1) % L) * W, lp = ((y0 + rows) % L) * W;
 
     uint32_t *X1base = lds + (size_t)sub * 4 * PW;       // [2 buffers][X1 | X0][PW]
     uint32_t c1m[4], c1c[4], c1p[4], c0o[4], n0m2[4], n0m1[4], n0c[4], c1n[4], pf1[4], pf0[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
         c1m[v] = c1c[v] = c1p[v] = c0o[v] = n0m2[v] = n0m1[v] = n0c[v] = c1n[v] = pf1[v] = pf0[v] = 0u;
+    // global-memory accesses spelled out: the replica pointers come from a
+    // table, and flat accesses would also be waited for by every LDS wait
     auto ld4 = [&](const uint32_t *P, uint32_t z, uint32_t (&r)[4]) {
-        const uint4 q = *reinterpret_cast<const uint4 *>(P + (z * PW + g0));
+        const u32x4 q = *(const __attribute__((address_space(1))) u32x4 *)(P + (z * PW + g0));
         r[0] = q.x; r[1] = q.y; r[2] = q.z; r[3] = q.w;
     };
     auto st4 = [&](uint32_t *P, uint32_t z, const uint32_t (&r)[4]) {
-        *reinterpret_cast<uint4 *>(P + (z * PW + g0)) = make_uint4(r[0], r[1], r[2], r[3]);
+        *(__attribute__((address_space(1))) u32x4 *)(P + (z * PW + g0)) = u32x4{r[0], r[1], r[2], r[3]};
     };
     const uint32_t z0 = T.z0;
     if (act) {
@@ -93,16 +107,40 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
                       uint32_t colour, const uint32_t (&r)[4], uint32_t (&out)[4], bool count) {
         // the two neighbour triples: (same, shifted, y-1) and (y+1, z-1, z+1)
         uint32_t n0[4], n1[4], n2[4];
+        if constexpr (WK == 4) {
+            const uint4 m = *reinterpret_cast<const uint4 *>(Xo + lm);
+            const uint4 q = *reinterpret_cast<const uint4 *>(Xo + lp);
+            n1[0] = m.x; n1[1] = m.y; n1[2] = m.z; n1[3] = m.w;
+            n2[0] = q.x; n2[1] = q.y; n2[2] = q.z; n2[3] = q.w;
+        } else if constexpr (WK == 2) {
+            const uint2 m = *reinterpret_cast<const uint2 *>(Xo + lm);
+            const uint2 q = *reinterpret_cast<const uint2 *>(Xo + lp);
+            n1[0] = m.x; n1[1] = m.y; n1[2] = same[0]; n1[3] = same[1];
+            n2[0] = same[2]; n2[1] = same[3]; n2[2] = q.x; n2[3] = q.y;
+        } else if constexpr (WK == 1) {
+            n1[0] = Xo[lm]; n1[1] = same[0]; n1[2] = same[1]; n1[3] = same[2];
+            n2[0] = same[1]; n2[1] = same[2]; n2[2] = same[3]; n2[3] = Xo[lp];
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             // pi differs between the lanes of a wave (and between the words of
             // a lane where rows are shorter than four words): select the
             // funnel's operands rather than branch on it
             const uint32_t pi = (colour + yv[v] + zp_plane) & 1u;
-            const uint32_t adj = Xo[pi ? gnx[v] : gpr[v]];
+            uint32_t adj;
+            if constexpr (WK == 4)
+                adj = pi ? same[(v + 1) & 3] : same[(v + 3) & 3];
+            else if constexpr (WK == 2)
+                adj = same[v ^ 1];
+            else if constexpr (WK == 1)
+                adj = same[v];
+            else
+                adj = Xo[pi ? gnx[v] : gpr[v]];
             n0[v] = funnel(pi ? adj : same[v], pi ? same[v] : adj, pi ? 1u : 31u);
-            n1[v] = Xo[gym[v]];
-            n2[v] = Xo[gyp[v]];
+            if constexpr (WK == 0) {
+                n1[v] = Xo[gym[v]];
+                n2[v] = Xo[gyp[v]];
+            }
         }
         // majority of seven (the neighbours and s ^ r), as in the lattice
         // kernels; counting adds a = (xa ^ s) + (xb ^ s) + 2 ((ma ^ s) + (mb ^ s))
@@ -202,6 +240,16 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
     if (counting && lane == 0 && sacc[sub]) {
         const uint32_t slot = (uint32_t)((t64 / A.every) % A.cap);
         atomicAdd(R.trace + slot, (unsigned long long)sacc[sub]);
+    }
+}
+
+__global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
+{
+    switch (A.groups[blockIdx.x].L) {
+    case 64: batch_body<1>(A); break;
+    case 128: batch_body<2>(A); break;
+    case 256: batch_body<4>(A); break;
+    default: batch_body<0>(A); break;
     }
 }
 
