@@ -195,13 +195,19 @@ def next_rows_workload(binding, torch, L, seed):
     # two sweeps per pass where consecutive sweeps draw the same first colour
     lat.set_pass(2)
     out["mixed_cycle"] = rates(per_sweep_ms(lat, 80))
-    lat.set_pass(1)
     for B in (8, 16):
         lat.set_double_checkerboard(B)
         for mixed in (False, True):
             lat.set_cycle(mixed)
             key = "double_checkerboard_B%d_%s" % (B, "mixed" if mixed else "01")
+            # two sweeps per pass, the default at this size: a sweep of the 01
+            # cycle in one pass over memory (the mixed cycle runs its phases)
+            lat.set_pass(2)
             out[key] = rates(per_sweep_ms(lat, 10))
+            if not mixed:
+                # the same sweeps as four in-place phases
+                lat.set_pass(1)
+                out[key + "_phases"] = rates(per_sweep_ms(lat, 10))
     del lat
     torch.cuda.empty_cache()
     Lf = 1024

@@ -199,7 +199,11 @@ int qz_set_cycle(qz_lattice *q, int cycle);
  * Each site draws the same tie bit as in the plain checkerboard.  B must be a
  * power of two >= 2 with L % (2B) == 0 (QZ_EINVAL otherwise); B = 0 returns to
  * the plain checkerboard.  QZ_EUNSUPPORTED on the int8 layout.  The paper does
- * not state its block size. */
+ * not state its block size.  With two sweeps per pass (qz_set_pass; the
+ * default from L = 1024) a sweep of the 01 cycle runs its four phases in one
+ * pass over memory, between the two copies; otherwise, and in the mixed
+ * cycle, each phase is a pass that updates the lattice in place.  The results
+ * are the same. */
 int qz_set_double_checkerboard(qz_lattice *q, uint32_t B);
 
 /* The paper's own correlation measurement (Methods, "Calculating the

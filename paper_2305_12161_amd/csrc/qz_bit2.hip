@@ -19,6 +19,13 @@
 // each side, so the tile owns rows [4, E-4) and recomputes the rest, and it
 // recomputes three planes at each z end.  Reads copy A, writes copy B, so
 // tiles never race.  The results are identical to two one-sweep passes.
+//
+// DCB: one sweep of the double checkerboard's 01 cycle (Supplementary Methods
+// I A) in the same four stages.  Its four phases -- fine colour 0 then 1 of
+// the coarse-colour-0 cubes, then of the coarse-colour-1 cubes -- read and
+// write the planes exactly as A, B, C, D do, except that each stage changes
+// only the sites of its coarse colour (A, B: 0; C, D: 1) and every stage draws
+// the tie bits of sweep t.
 #include "qz_bitops.hpp"
 #include "qz_device.hpp"
 #include "qz_internal.hpp"
@@ -41,6 +48,7 @@ struct Sweep2Args {
     uint32_t Ty, E, Tz, nty;            // E = Ty + 8 rows held per tile
     uint32_t k0, k1, t;
     uint32_t f;                         // colour updated first in both sweeps
+    uint32_t sB;                        // DCB: cube side 2^sB
 };
 
 template <int V>
@@ -58,7 +66,9 @@ __device__ __forceinline__ void copy_words(uint32_t (&d)[V], const uint32_t (&s)
 // the odd wave the odd ones.  Every wave's rows then share the parity of y, so
 // the x parity pi of all four stages is the same across the wave and the
 // x-neighbour shift takes one uniform branch instead of both.
-template <int V, bool CA, bool CC, bool PAIRED>
+// DCB: the double-checkerboard sweep described above (CA then counts the
+// entering bonds and the flips of the whole sweep; CC is not used).
+template <int V, bool CA, bool CC, bool PAIRED, bool DCB>
 __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
 {
     extern __shared__ uint32_t lds[];
@@ -133,11 +143,33 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
         const uint32_t gc = gword((z + L - 2) % L), gd = gword((z + L - 3) % L);
         tie_words<V>(A.k0, A.k1, ga, ga & 3u, A.t, A.f, a);
         tie_words<V>(A.k0, A.k1, gb, gb & 3u, A.t, 1u - A.f, b);
-        tie_words<V>(A.k0, A.k1, gc, gc & 3u, A.t + 1u, A.f, c);
-        tie_words<V>(A.k0, A.k1, gd, gd & 3u, A.t + 1u, 1u - A.f, d);
+        const uint32_t t2 = DCB ? A.t : A.t + 1u;
+        tie_words<V>(A.k0, A.k1, gc, gc & 3u, t2, A.f, c);
+        tie_words<V>(A.k0, A.k1, gd, gd & 3u, t2, 1u - A.f, d);
     };
     uint32_t sA[V], sB[V], sC[V], sD[V];   // tie words of the next step's stages
     draw_step((z0 + L - 3) % L, sA, sB, sC, sD);
+
+    // DCB: the sites of coarse colour 0 among the lane's words of plane z.  A
+    // word's sites lie in cubes (32 w + b) >> q along x (q = sB - 1, since a
+    // colour row holds every second site), so below q = 5 the mask is a fixed
+    // pattern of runs of 2^q bits, and from q = 5 on all 32 sites share a cube.
+    const uint32_t dq = DCB ? A.sB - 1u : 0u;
+    const uint32_t dpat = dq == 0 ? 0xAAAAAAAAu : dq == 1 ? 0xCCCCCCCCu : dq == 2 ? 0xF0F0F0F0u
+                        : dq == 3 ? 0xFF00FF00u : dq == 4 ? 0xFFFF0000u : 0u;
+    auto coarse0 = [&](uint32_t z, uint32_t (&m)[V]) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint32_t par = (((32u * (w0 + (uint32_t)v)) >> dq) + (y >> A.sB) + (z >> A.sB)) & 1u;
+            m[v] = par ? dpat : ~dpat;
+        }
+    };
+    // keep the stage's old words outside its coarse colour (sel = ~0: all new)
+    auto keep = [&](const uint32_t (&own)[V], uint32_t (&out)[V], const uint32_t (&sel)[V]) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            out[v] = (out[v] & sel[v]) | (own[v] & ~sel[v]);
+    };
 
     for (int qi = -3; qi <= (int)Tza + 2; ++qi) {
         const uint32_t zq = (z0 + 2 * L + qi) % L;
@@ -181,6 +213,11 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             const uint32_t adj = X1[e * W + wadj];
             int a_sum = 0;
             rule_words<V, CA>(c0o, c1c, adj, pi, ym, yp, c1m, c1p, rA, n0n, a_sum);
+            if constexpr (DCB) {
+                uint32_t m[V];
+                coarse0(zq, m);
+                keep(c0o, n0n, m);
+            }
             if constexpr (CA)
                 if (rowD && qi >= 0 && qi < (int)Tza) {
                     bonds_a += a_sum;
@@ -197,6 +234,11 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             const uint32_t adj = X0[e * W + wadj];
             int unused = 0;
             rule_words<V, false>(c1m, n0a, adj, pi, ym, yp, n0b, n0n, rB, n1n, unused);
+            if constexpr (DCB) {
+                uint32_t m[V];
+                coarse0((zq + L - 1) % L, m);
+                keep(c1m, n1n, m);
+            }
             if constexpr (CA)
                 if (rowD && qi >= 1 && qi <= (int)Tza) {
 #pragma unroll
@@ -212,7 +254,20 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             const uint32_t adj = Y1[e * W + wadj];
             int a_sum = 0;
             rule_words<V, CC>(n0b, n1a, adj, pi, ym, yp, n1b, n1n, rC, m0n, a_sum);
+            if constexpr (DCB) {
+                uint32_t m[V];
+                coarse0(zc, m);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    m[v] = ~m[v];
+                keep(n0b, m0n, m);
+            }
             if (rowD && qi >= 2 && qi < (int)Tza + 2) {
+                if constexpr (DCB && CA) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        flips_a = popc_acc(n0b[v] ^ m0n[v], flips_a);
+                }
                 if constexpr (CC) {
                     bonds_c += a_sum;
 #pragma unroll
@@ -230,6 +285,19 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             const uint32_t adj = Y0[e * W + wadj];
             int unused = 0;
             rule_words<V, false>(n1b, m0a, adj, pi, ym, yp, m0b, m0n, rD, m1n, unused);
+            if constexpr (DCB) {
+                uint32_t m[V];
+                coarse0(zd, m);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    m[v] = ~m[v];
+                keep(n1b, m1n, m);
+                if constexpr (CA) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        flips_a = popc_acc(n1b[v] ^ m1n[v], flips_a);
+                }
+            }
             if constexpr (CC) {
 #pragma unroll
                 for (int v = 0; v < V; ++v)
@@ -286,19 +354,24 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
     }
 }
 
-template <int V, bool P>
+template <int V, bool P, bool DCB = false>
 void launch2(hipStream_t st, const Sweep2Args &a, dim3 grid, dim3 block, size_t lds)
 {
     const bool ca = a.acc_a != nullptr || a.flip_a != nullptr;
     const bool cc = a.acc_c != nullptr || a.flip_c != nullptr;
-    if (ca && cc) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, true, true, P>), grid, block, lds, st, a);
+    if constexpr (DCB) {
+        if (ca)
+            hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P, true>), grid, block, lds, st, a);
+        else
+            hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P, true>), grid, block, lds, st, a);
+    } else if (ca && cc) {
+        hipLaunchKernelGGL((k_bit_sweep2<V, true, true, P, false>), grid, block, lds, st, a);
     } else if (ca) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P, false>), grid, block, lds, st, a);
     } else if (cc) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, false, true, P>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, false, true, P, false>), grid, block, lds, st, a);
     } else {
-        hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P, false>), grid, block, lds, st, a);
     }
 }
 
@@ -371,25 +444,13 @@ BitTuning bit_tuning2_default(uint32_t L)
 // per pass, 30.8 at best with two).
 int bit_pass_default(uint32_t L) { return L >= 1024 ? 2 : 1; }
 
-hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
-                      const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
-                      unsigned long long *acc_a, unsigned long long *acc_c,
-                      unsigned long long *flip_a, unsigned long long *flip_c, uint32_t first)
+namespace {
+
+// the launch geometry and arguments shared by both entry points
+template <bool DCB>
+hipError_t sweep2_launch(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t,
+                         const BitTuning &tu, Sweep2Args &a)
 {
-    if (!bit_tuning2_valid(L, tu) || first > 1u)
-        return hipErrorInvalidValue;
-    Sweep2Args a;
-    // the kernel's stages A and C update "colour 0", B and D "colour 1": here
-    // the colour updated first, and the other
-    a.S0 = first ? S1 : S0;
-    a.S1 = first ? S0 : S1;
-    a.D0 = first ? D1 : D0;
-    a.D1 = first ? D0 : D1;
-    a.f = first;
-    a.acc_a = acc_a;
-    a.acc_c = acc_c;
-    a.flip_a = flip_a;
-    a.flip_c = flip_c;
     a.L = L;
     a.W = L / 64;
     a.R = a.W / tu.V;
@@ -409,14 +470,63 @@ hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, con
     switch (tu.V) {
     case 4:
         if (paired)
-            launch2<4, true>(st, a, grid, block, lds);
+            launch2<4, true, DCB>(st, a, grid, block, lds);
         else
-            launch2<4, false>(st, a, grid, block, lds);
+            launch2<4, false, DCB>(st, a, grid, block, lds);
         break;
-    case 2: launch2<2, false>(st, a, grid, block, lds); break;
-    default: launch2<1, false>(st, a, grid, block, lds); break;
+    case 2: launch2<2, false, DCB>(st, a, grid, block, lds); break;
+    default: launch2<1, false, DCB>(st, a, grid, block, lds); break;
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
+                      const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
+                      unsigned long long *acc_a, unsigned long long *acc_c,
+                      unsigned long long *flip_a, unsigned long long *flip_c, uint32_t first)
+{
+    if (!bit_tuning2_valid(L, tu) || first > 1u)
+        return hipErrorInvalidValue;
+    Sweep2Args a;
+    // the kernel's stages A and C update "colour 0", B and D "colour 1": here
+    // the colour updated first, and the other
+    a.S0 = first ? S1 : S0;
+    a.S1 = first ? S0 : S1;
+    a.D0 = first ? D1 : D0;
+    a.D1 = first ? D0 : D1;
+    a.f = first;
+    a.sB = 0;
+    a.acc_a = acc_a;
+    a.acc_c = acc_c;
+    a.flip_a = flip_a;
+    a.flip_c = flip_c;
+    return sweep2_launch<false>(st, L, seed, t, tu, a);
+}
+
+hipError_t bit_double_sweep2(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
+                             const BitTuning &tu, const uint32_t *S0, const uint32_t *S1,
+                             uint32_t *D0, uint32_t *D1, unsigned long long *bond_acc,
+                             unsigned long long *flip_acc)
+{
+    uint32_t sB = 0;
+    while ((1u << sB) < B)
+        ++sB;
+    if (!bit_tuning2_valid(L, tu) || B < 2 || (1u << sB) != B || L % (2 * B))
+        return hipErrorInvalidValue;
+    Sweep2Args a;
+    a.S0 = S0;
+    a.S1 = S1;
+    a.D0 = D0;
+    a.D1 = D1;
+    a.f = 0;
+    a.sB = sB;
+    a.acc_a = bond_acc;
+    a.acc_c = nullptr;
+    a.flip_a = flip_acc;
+    a.flip_c = nullptr;
+    return sweep2_launch<true>(st, L, seed, t, tu, a);
 }
 
 }  // namespace qz
