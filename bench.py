@@ -200,14 +200,13 @@ def next_rows_workload(binding, torch, L, seed):
         for mixed in (False, True):
             lat.set_cycle(mixed)
             key = "double_checkerboard_B%d_%s" % (B, "mixed" if mixed else "01")
-            # two sweeps per pass, the default at this size: a sweep of the 01
-            # cycle in one pass over memory (the mixed cycle runs its phases)
+            # two sweeps per pass, the default at this size: a sweep in one
+            # pass over memory (plus one in-place phase in the mixed cycle)
             lat.set_pass(2)
             out[key] = rates(per_sweep_ms(lat, 10))
-            if not mixed:
-                # the same sweeps as four in-place phases
-                lat.set_pass(1)
-                out[key + "_phases"] = rates(per_sweep_ms(lat, 10))
+            # the same sweeps as in-place phases only
+            lat.set_pass(1)
+            out[key + "_phases"] = rates(per_sweep_ms(lat, 10))
     del lat
     torch.cuda.empty_cache()
     Lf = 1024

@@ -200,10 +200,10 @@ int qz_set_cycle(qz_lattice *q, int cycle);
  * power of two >= 2 with L % (2B) == 0 (QZ_EINVAL otherwise); B = 0 returns to
  * the plain checkerboard.  QZ_EUNSUPPORTED on the int8 layout.  The paper does
  * not state its block size.  With two sweeps per pass (qz_set_pass; the
- * default from L = 1024) a sweep of the 01 cycle runs its four phases in one
- * pass over memory, between the two copies; otherwise, and in the mixed
- * cycle, each phase is a pass that updates the lattice in place.  The results
- * are the same. */
+ * default from L = 1024) a sweep runs in one pass over memory between the two
+ * copies (the mixed cycle adds one in-place pass for its last step; tiles of
+ * more than 512 lanes run it as phases); otherwise each phase is a pass that
+ * updates the lattice in place.  The results are the same. */
 int qz_set_double_checkerboard(qz_lattice *q, uint32_t B);
 
 /* The paper's own correlation measurement (Methods, "Calculating the

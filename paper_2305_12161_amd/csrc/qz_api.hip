@@ -112,12 +112,16 @@ int sweep_once(qz_lattice *q, unsigned long long *bond_acc, unsigned long long *
                                     flip_acc));
         QZ_HIP(q, qz::i8_half_sweep(q->st, q->L, q->seed, t, 1, q->mixed, i8_spins(q), nullptr,
                                     flip_acc));
-    } else if (q->dcb > 0 && !q->mixed && q->pass == 2) {
-        // the 01 cycle's four phases in one pass over memory
+    } else if (q->dcb > 0 && q->pass == 2 && qz::bit_double_sweep2_fits(q->L, q->tune2, q->mixed)) {
+        // the 01 cycle's four phases in one pass over memory; the mixed
+        // cycle's first four steps likewise, and its last one in place
         const int a = q->cur, b = 1 - q->cur;
         QZ_HIP(q, qz::bit_double_sweep2(q->st, q->L, q->dcb, q->seed, t, q->tune2,
                                         bit_plane(q, a, 0), bit_plane(q, a, 1), bit_plane(q, b, 0),
-                                        bit_plane(q, b, 1), bond_acc, flip_acc));
+                                        bit_plane(q, b, 1), q->mixed, bond_acc, flip_acc));
+        if (q->mixed)
+            QZ_HIP(q, qz::bit_double_phase(q->st, q->L, q->dcb, q->seed, t, bit_plane(q, b, 0),
+                                           bit_plane(q, b, 1), 1u, 0u, 1u, true, flip_acc));
         q->cur = b;
     } else if (q->dcb > 0) {
         const int c = q->cur;

@@ -25,8 +25,17 @@
 // the coarse-colour-0 cubes, then of the coarse-colour-1 cubes -- read and
 // write the planes exactly as A, B, C, D do, except that each stage changes
 // only the sites of its coarse colour (A, B: 0; C, D: 1) and every stage draws
-// the tie bits of sweep t.
+// the tie bits of sweep t.  In the mixed cycle (Supplementary Methods I B) the
+// coarse colour taken first (c) and each cube's fine order are drawn per
+// sweep; a cube's two steps (fine colour f, then 1 - f) then fall on the
+// stages as A: c-cubes with f = 0; B: all c-cubes; C: c-cubes with f = 1 and
+// (1-c)-cubes with f = 0; D: all (1-c)-cubes; the last step, fine colour 0 of
+// the (1-c)-cubes with f = 1, is one more in-place phase after the pass.  Each
+// update still reads its neighbours in the state the sequential order gives
+// them: cubes of one coarse colour never touch, and every stage that updates
+// a (1-c)-cube runs after the c-cubes' sites it reads are final.
 #include "qz_bitops.hpp"
+#include "qz_cube.hpp"
 #include "qz_device.hpp"
 #include "qz_internal.hpp"
 
@@ -66,10 +75,14 @@ __device__ __forceinline__ void copy_words(uint32_t (&d)[V], const uint32_t (&s)
 // the odd wave the odd ones.  Every wave's rows then share the parity of y, so
 // the x parity pi of all four stages is the same across the wave and the
 // x-neighbour shift takes one uniform branch instead of both.
-// DCB: the double-checkerboard sweep described above (CA then counts the
-// entering bonds and the flips of the whole sweep; CC is not used).
-template <int V, bool CA, bool CC, bool PAIRED, bool DCB>
-__global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
+// DCB: the double-checkerboard sweep described above, 1 = 01 cycle, 2 = mixed
+// cycle (CA then counts the entering bonds and the flips of the pass; CC is
+// not used).
+// The mixed double checkerboard keeps more state per lane (the cube-order
+// masks of two stages): its workgroups are limited to 512 lanes, which leaves
+// it registers enough not to spill.
+template <int V, bool CA, bool CC, bool PAIRED, int DCB>
+__global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args A)
 {
     extern __shared__ uint32_t lds[];
     const uint32_t L = A.L, W = A.W, E = A.E;
@@ -164,6 +177,23 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             m[v] = par ? dpat : ~dpat;
         }
     };
+    // mixed: the coarse colour taken first, and per word the sites whose cube
+    // takes fine colour 1 first (stages A and C), kept per layer of cubes
+    constexpr bool MIX = DCB == 2;
+    const uint32_t cc0 = MIX ? (philox10(0u, A.t, 3u, 0u, A.k0, A.k1).w[0] & 1u) : 0u;
+    uint32_t fA[V], fC[V];
+    uint32_t kA = 0xFFFFFFFFu, kC = 0xFFFFFFFFu;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        fA[v] = fC[v] = 0u;
+    auto order = [&](uint32_t z, uint32_t &kz, uint32_t (&fo)[V]) {
+        if ((z >> A.sB) != kz) {            // z is the same in every lane
+            kz = z >> A.sB;
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                fo[v] = cube_order_mask(w0 + (uint32_t)v, y, z, L, A.sB, A.k0, A.k1, A.t);
+        }
+    };
     // keep the stage's old words outside its coarse colour (sel = ~0: all new)
     auto keep = [&](const uint32_t (&own)[V], uint32_t (&out)[V], const uint32_t (&sel)[V]) {
 #pragma unroll
@@ -216,6 +246,14 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             if constexpr (DCB) {
                 uint32_t m[V];
                 coarse0(zq, m);
+                if constexpr (MIX)
+                    order(zq, kA, fA);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    m[v] = cc0 ? ~m[v] : m[v];
+                    if constexpr (MIX)
+                        m[v] &= ~fA[v];
+                }
                 keep(c0o, n0n, m);
             }
             if constexpr (CA)
@@ -237,6 +275,9 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             if constexpr (DCB) {
                 uint32_t m[V];
                 coarse0((zq + L - 1) % L, m);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    m[v] = cc0 ? ~m[v] : m[v];
                 keep(c1m, n1n, m);
             }
             if constexpr (CA)
@@ -257,9 +298,14 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
             if constexpr (DCB) {
                 uint32_t m[V];
                 coarse0(zc, m);
+                if constexpr (MIX)
+                    order(zc, kC, fC);
 #pragma unroll
-                for (int v = 0; v < V; ++v)
-                    m[v] = ~m[v];
+                for (int v = 0; v < V; ++v) {
+                    const uint32_t first = cc0 ? ~m[v] : m[v];     // sites of the first coarse colour
+                    // mixed: first-colour cubes with f = 1, the others with f = 0
+                    m[v] = MIX ? ~(first ^ fC[v]) : ~first;
+                }
                 keep(n0b, m0n, m);
             }
             if (rowD && qi >= 2 && qi < (int)Tza + 2) {
@@ -290,7 +336,7 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
                 coarse0(zd, m);
 #pragma unroll
                 for (int v = 0; v < V; ++v)
-                    m[v] = ~m[v];
+                    m[v] = cc0 ? m[v] : ~m[v];                     // the second coarse colour
                 keep(n1b, m1n, m);
                 if constexpr (CA) {
 #pragma unroll
@@ -354,24 +400,24 @@ __global__ void __launch_bounds__(1024) k_bit_sweep2(Sweep2Args A)
     }
 }
 
-template <int V, bool P, bool DCB = false>
+template <int V, bool P, int DCB = 0>
 void launch2(hipStream_t st, const Sweep2Args &a, dim3 grid, dim3 block, size_t lds)
 {
     const bool ca = a.acc_a != nullptr || a.flip_a != nullptr;
     const bool cc = a.acc_c != nullptr || a.flip_c != nullptr;
-    if constexpr (DCB) {
+    if constexpr (DCB != 0) {
         if (ca)
-            hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P, true>), grid, block, lds, st, a);
+            hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P, DCB>), grid, block, lds, st, a);
         else
-            hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P, true>), grid, block, lds, st, a);
+            hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P, DCB>), grid, block, lds, st, a);
     } else if (ca && cc) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, true, true, P, false>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, true, true, P, 0>), grid, block, lds, st, a);
     } else if (ca) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P, false>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P, 0>), grid, block, lds, st, a);
     } else if (cc) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, false, true, P, false>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, false, true, P, 0>), grid, block, lds, st, a);
     } else {
-        hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P, false>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P, 0>), grid, block, lds, st, a);
     }
 }
 
@@ -447,7 +493,7 @@ int bit_pass_default(uint32_t L) { return L >= 1024 ? 2 : 1; }
 namespace {
 
 // the launch geometry and arguments shared by both entry points
-template <bool DCB>
+template <int DCB>
 hipError_t sweep2_launch(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t,
                          const BitTuning &tu, Sweep2Args &a)
 {
@@ -502,18 +548,26 @@ hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, con
     a.acc_c = acc_c;
     a.flip_a = flip_a;
     a.flip_c = flip_c;
-    return sweep2_launch<false>(st, L, seed, t, tu, a);
+    return sweep2_launch<0>(st, L, seed, t, tu, a);
+}
+
+bool bit_double_sweep2_fits(uint32_t L, const BitTuning &tu, bool mixed)
+{
+    if (!bit_tuning2_valid(L, tu))
+        return false;
+    const uint32_t R = (L / 64) / (uint32_t)tu.V, E = (uint32_t)tu.Ty + 8;
+    return !mixed || ((E * R + 63) / 64) * 64 <= 512;
 }
 
 hipError_t bit_double_sweep2(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
                              const BitTuning &tu, const uint32_t *S0, const uint32_t *S1,
-                             uint32_t *D0, uint32_t *D1, unsigned long long *bond_acc,
-                             unsigned long long *flip_acc)
+                             uint32_t *D0, uint32_t *D1, bool mixed,
+                             unsigned long long *bond_acc, unsigned long long *flip_acc)
 {
     uint32_t sB = 0;
     while ((1u << sB) < B)
         ++sB;
-    if (!bit_tuning2_valid(L, tu) || B < 2 || (1u << sB) != B || L % (2 * B))
+    if (!bit_double_sweep2_fits(L, tu, mixed) || B < 2 || (1u << sB) != B || L % (2 * B))
         return hipErrorInvalidValue;
     Sweep2Args a;
     a.S0 = S0;
@@ -526,7 +580,7 @@ hipError_t bit_double_sweep2(hipStream_t st, uint32_t L, uint32_t B, uint64_t se
     a.acc_c = nullptr;
     a.flip_a = flip_acc;
     a.flip_c = nullptr;
-    return sweep2_launch<true>(st, L, seed, t, tu, a);
+    return mixed ? sweep2_launch<2>(st, L, seed, t, tu, a) : sweep2_launch<1>(st, L, seed, t, tu, a);
 }
 
 }  // namespace qz

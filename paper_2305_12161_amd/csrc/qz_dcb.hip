@@ -4,6 +4,7 @@
 // the 01 cycle can also run as one pass of the four-stage kernel (its DCB
 // flag); the phases here serve the mixed cycle and one sweep per pass.
 #include "qz_bitops.hpp"
+#include "qz_cube.hpp"
 #include "qz_device.hpp"
 #include "qz_internal.hpp"
 
@@ -34,42 +35,6 @@ uint32_t grid_cap(uint64_t work, uint32_t cap)
 // (first ^ step); a launch for plane p masks in the cubes whose fine colour
 // of this step is p.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t cube_bits_mask(uint32_t bits, uint32_t q)
-{
-    // bits: bit k = cube (first cube of the word) + k; word bit b lies in cube
-    // column offset b >> q, so each of the low 32 >> q bits becomes a run of
-    // 2^q bits: q doubling steps, each moving bit k to bit 2k (at most 16
-    // significant bits going in) and copying it to bit 2k + 1
-    if (q >= 5)
-        return (bits & 1u) ? 0xFFFFFFFFu : 0u;
-    uint32_t x = q == 0 ? bits : bits & ((1u << (32u >> q)) - 1u);
-    for (uint32_t s = 0; s < q; ++s) {
-        x = (x | (x << 8)) & 0x00FF00FFu;
-        x = (x | (x << 4)) & 0x0F0F0F0Fu;
-        x = (x | (x << 2)) & 0x33333333u;
-        x = (x | (x << 1)) & 0x55555555u;
-        x |= x << 1;
-    }
-    return x;
-}
-
-__device__ __forceinline__ uint32_t cube_order_mask(uint32_t w, uint32_t y, uint32_t z,
-                                                    uint32_t L, uint32_t sB, uint32_t k0,
-                                                    uint32_t k1, uint32_t t)
-{
-    // bit b of the word lies in cube column (32w + b) >> (sB - 1) along x
-    const uint32_t q = sB - 1;
-    const uint32_t nb = L >> sB;
-    const uint64_t cb0 = (uint64_t)((32u * w) >> q) +
-                         (uint64_t)nb * ((uint64_t)(y >> sB) + (uint64_t)nb * (z >> sB));
-    const Words4 o = philox10((uint32_t)(cb0 >> 7), t, 4u, 0u, k0, k1);
-    const uint32_t sub = (uint32_t)(cb0 >> 5) & 3u;
-    const uint32_t word = (sub & 2u) ? ((sub & 1u) ? o.w[3] : o.w[2])
-                                     : ((sub & 1u) ? o.w[1] : o.w[0]);
-    const uint32_t bits = word >> (uint32_t)(cb0 & 31u);   // bit k: cube cb0 + k
-    return cube_bits_mask(bits, q);
-}
-
 __global__ void __launch_bounds__(256)
     k_bit_phase(uint32_t L, uint32_t W, uint32_t sB, uint32_t kc, uint32_t p, uint32_t k0,
                 uint32_t k1, uint32_t t, uint32_t *Pp, const uint32_t *Po, uint32_t mixed,
@@ -379,6 +344,31 @@ hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t see
                     return e;
             }
     return hipSuccess;
+}
+
+hipError_t bit_double_phase(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
+                            uint32_t *P0, uint32_t *P1, uint32_t kc, uint32_t p, uint32_t step,
+                            bool mixed, unsigned long long *flip_acc)
+{
+    uint32_t sB = 0;
+    while ((1u << sB) < B)
+        ++sB;
+    if (B < 2 || (1u << sB) != B || L % (2 * B) || kc > 1 || p > 1 || step > 1)
+        return hipErrorInvalidValue;
+    const uint32_t W = L / 64;
+    if (W % 4 == 0) {
+        const uint32_t rpb = 256u / (W / 4);
+        const dim3 grid4((uint32_t)(((uint64_t)L * L + rpb - 1) / rpb));
+        hipLaunchKernelGGL(k_bit_phase4, grid4, dim3(256), 0, st, L, W, sB, kc, p,
+                           (uint32_t)seed, (uint32_t)(seed >> 32), t, p ? P1 : P0, p ? P0 : P1,
+                           mixed ? 1u : 0u, step, flip_acc);
+    } else {
+        const uint64_t nw = (uint64_t)L * L * W;
+        hipLaunchKernelGGL(k_bit_phase, dim3(grid_cap(nw, 8192)), dim3(256), 0, st, L, W, sB, kc,
+                           p, (uint32_t)seed, (uint32_t)(seed >> 32), t, p ? P1 : P0, p ? P0 : P1,
+                           mixed ? 1u : 0u, step, flip_acc);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace qz

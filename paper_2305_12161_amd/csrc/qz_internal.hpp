@@ -74,13 +74,25 @@ hipError_t bit_bonds_total(hipStream_t st, uint32_t L, const uint32_t *P0, const
 hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
                             uint32_t *P0, uint32_t *P1, bool mixed,
                             unsigned long long *flip_acc = nullptr);
-// One double-checkerboard sweep of the 01 cycle in one pass of the two-sweep
-// kernel (copy S -> copy D, tiling tu); bond_acc / flip_acc (nullable) receive
-// the bond count of the entering state and the flips of the sweep.
+// One phase of bit_double_sweep, in place: fine colour p of the cubes of
+// coarse colour kc (its position in the sweep's order when mixed), step
+// `step` of the mixed cycle's per-cube fine order.
+hipError_t bit_double_phase(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
+                            uint32_t *P0, uint32_t *P1, uint32_t kc, uint32_t p, uint32_t step,
+                            bool mixed, unsigned long long *flip_acc);
+// Whether bit_double_sweep2 takes tiling tu at side L (the mixed cycle needs
+// workgroups of at most 512 lanes).
+bool bit_double_sweep2_fits(uint32_t L, const BitTuning &tu, bool mixed);
+// One double-checkerboard sweep in one pass of the two-sweep kernel (copy S ->
+// copy D, tiling tu); bond_acc / flip_acc (nullable) receive the bond count
+// of the entering state and the flips of the pass.  mixed: the mixed cycle's
+// stages A-D; its last step (fine colour 0 of the second coarse colour's
+// cubes that take fine colour 1 first) is then left to bit_double_phase(kc =
+// 1, p = 0, step = 1) on copy D.
 hipError_t bit_double_sweep2(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
                              const BitTuning &tu, const uint32_t *S0, const uint32_t *S1,
-                             uint32_t *D0, uint32_t *D1, unsigned long long *bond_acc,
-                             unsigned long long *flip_acc);
+                             uint32_t *D0, uint32_t *D1, bool mixed,
+                             unsigned long long *bond_acc, unsigned long long *flip_acc);
 // Q0, Q1: scratch colour planes of the same size (the lattice's idle copy;
 // overwritten), or null.  With scratch and L a multiple of 256 all three axes
 // run on the matrix cores, else x (and, for other L, y and z) by XOR and

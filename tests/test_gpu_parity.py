@@ -548,18 +548,22 @@ def test_double_checkerboard_matches_oracle(qz, orc, L, B, mixed):
     assert np.array_equal(lat.download(), s)
 
 
-# the 01 cycle's four phases in one pass of the two-sweep kernel (two sweeps
-# per pass selected); tile = (V, Ty, Tz) or None for the default tile
+# a sweep in one pass of the four-stage kernel (two sweeps per pass selected;
+# the mixed cycle adds one in-place phase); tile = (V, Ty, Tz) or None for the
+# default tile
+@pytest.mark.parametrize("mixed", [False, True], ids=["01", "mixed"])
 @pytest.mark.parametrize("L,B,tile", [(64, 2, None), (64, 8, None), (64, 32, None),
                                       (128, 4, None), (128, 64, None), (192, 16, None),
                                       (192, 32, None), (256, 2, None), (256, 4, (4, 24, 8)),
                                       (256, 16, None), (256, 64, None), (256, 128, (4, 120, 40)),
                                       (512, 8, (4, 56, 16)), (512, 256, (4, 56, 64))])
-def test_double_checkerboard_one_pass_matches_oracle(qz, orc, L, B, tile):
-    seed = 190 + L + B
-    say("double checkerboard one pass", L, B, tile)
+def test_double_checkerboard_one_pass_matches_oracle(qz, orc, L, B, tile, mixed):
+    seed = 190 + L + B + (500 if mixed else 0)
+    say("double checkerboard one pass", L, B, tile, "mixed" if mixed else "01")
     lat = qz.Lattice(L, seed, "bit")
     lat.set_double_checkerboard(B)
+    if mixed:
+        lat.set_cycle(True)
     if tile is None:
         lat.set_pass(2)
     else:
@@ -567,24 +571,27 @@ def test_double_checkerboard_one_pass_matches_oracle(qz, orc, L, B, tile):
     n = 5 if L < 256 else 3
     tr = lat.run(n, 1)
     s = orc.init(L, seed)
-    want = orc.run_double(s, B, seed, 0, n, 1)
+    want = orc.run_double(s, B, seed, 0, n, 1, mixed=mixed)
     assert np.array_equal(tr.astype(np.int64), want)
     assert np.array_equal(lat.download(), s)
 
 
+@pytest.mark.parametrize("mixed", [False, True], ids=["01", "mixed"])
 @pytest.mark.parametrize("B", [8, 16])
-def test_double_checkerboard_one_pass_large(qz, B):
+def test_double_checkerboard_one_pass_large(qz, B, mixed):
     """L = 1024, the paired tile of the large lattices: the one-pass sweep and
     the in-place phases (checked against the oracle above) give the same bond
     and flip traces and the same lattice."""
     L, seed = 1024, 77 + B
-    say("double checkerboard one pass vs phases", L, B)
+    say("double checkerboard one pass vs phases", L, B, "mixed" if mixed else "01")
     one = qz.Lattice(L, seed, "bit")
     one.set_double_checkerboard(B)
+    one.set_cycle(mixed)
     one.set_pass(2, 4, 56, 64)
     Bo, Fo = one.run_traced(4, 1)
     ph = qz.Lattice(L, seed, "bit")
     ph.set_double_checkerboard(B)
+    ph.set_cycle(mixed)
     ph.set_pass(1)
     Bp, Fp = ph.run_traced(4, 1)
     assert np.array_equal(Bo, Bp)
@@ -610,18 +617,20 @@ def test_double_checkerboard_rejects(qz):
                                            ("bit", 128, "pass2"), ("bit", 192, "pass2"),
                                            ("bit", 64, "dcb"), ("bit", 128, "dcb-mixed"),
                                            ("bit", 256, "dcb"), ("bit", 256, "dcb-mixed"),
-                                           ("bit", 128, "dcb-pass2"), ("bit", 256, "dcb-pass2")])
+                                           ("bit", 128, "dcb-pass2"), ("bit", 256, "dcb-pass2"),
+                                           ("bit", 128, "dcb-mixed-pass2"),
+                                           ("bit", 256, "dcb-mixed-pass2")])
 def test_flip_trace_matches_oracle(qz, orc, layout, L, mode):
     seed = 300 + L
     say("flips", layout, L, mode)
     lat = qz.Lattice(L, seed, layout)
-    mixed = mode in ("mixed", "dcb-mixed")
+    mixed = mode in ("mixed", "dcb-mixed", "dcb-mixed-pass2")
     double_B = 4 if mode.startswith("dcb") else 0
     if mixed:
         lat.set_cycle(True)
     if double_B:
         lat.set_double_checkerboard(double_B)
-    if mode in ("pass2", "dcb-pass2"):
+    if mode in ("pass2", "dcb-pass2", "dcb-mixed-pass2"):
         lat.set_pass(2)
     for every, n in ((1, 5), (3, 9)):
         B, F = lat.run_traced(n, every)
