@@ -127,16 +127,18 @@ __device__ __forceinline__ void batch_body(const BatchArgs &A)
             // a lane where rows are shorter than four words): select the
             // funnel's operands rather than branch on it
             const uint32_t pi = (colour + yv[v] + zp_plane) & 1u;
-            uint32_t adj;
-            if constexpr (WK == 4)
-                adj = pi ? same[(v + 1) & 3] : same[(v + 3) & 3];
-            else if constexpr (WK == 2)
-                adj = same[v ^ 1];
-            else if constexpr (WK == 1)
-                adj = same[v];
-            else
-                adj = Xo[pi ? gnx[v] : gpr[v]];
-            n0[v] = funnel(pi ? adj : same[v], pi ? same[v] : adj, pi ? 1u : 31u);
+            if constexpr (WK == 4) {
+                // both shifts from the lane's own words, then one select
+                const uint32_t up = funnel(same[(v + 1) & 3], same[v], 1);
+                const uint32_t dn = funnel(same[v], same[(v + 3) & 3], 31);
+                n0[v] = pi ? up : dn;
+            } else if constexpr (WK == 2 || WK == 1) {
+                const uint32_t adj = WK == 2 ? same[v ^ 1] : same[v];
+                n0[v] = funnel(pi ? adj : same[v], pi ? same[v] : adj, pi ? 1u : 31u);
+            } else {
+                const uint32_t adj = Xo[pi ? gnx[v] : gpr[v]];
+                n0[v] = funnel(pi ? adj : same[v], pi ? same[v] : adj, pi ? 1u : 31u);
+            }
             if constexpr (WK == 0) {
                 n1[v] = Xo[gym[v]];
                 n2[v] = Xo[gyp[v]];
