@@ -165,8 +165,8 @@ int qz_get_tuning(const qz_lattice *q, int out_V_Ty_Tz[3]);
  * traffic per sweep; the trajectory, the bond trace and every measurement are
  * identical to sweeps = 1 (Methods, "Checkerboard update").  Runs of an odd
  * number of sweeps end with one single sweep; in the mixed cycle two sweeps
- * share a pass only when both draw the same first colour (otherwise the
- * first runs alone); the double checkerboard always runs one sweep per pass.
+ * share a pass whichever first colours they draw; the double checkerboard
+ * runs one sweep per pass (see qz_set_double_checkerboard).
  * V, Ty, Tz tune the two-sweep kernel as in qz_set_tuning
  * (V words per lane, Ty owned rows per tile, Ty + 8 rows held, Tz planes);
  * all three 0 selects the default for L.  QZ_EINVAL for another sweep count

@@ -141,15 +141,16 @@ int sweep_once(qz_lattice *q, unsigned long long *bond_acc, unsigned long long *
     return QZ_OK;
 }
 
-// Sweeps t and t+1 in one pass (bit layout, plain checkerboard), both updating
-// colour `first` first: always colour 0 in the 01 cycle.
+// Sweeps t and t+1 in one pass (bit layout, plain checkerboard); sweep t
+// updates colour `first` first (always colour 0 in the 01 cycle), sweep t+1
+// the same colour first, or the other one when swap is set.
 int sweep_pair(qz_lattice *q, unsigned long long *acc_a, unsigned long long *acc_c,
-               unsigned long long *flip_a, unsigned long long *flip_c, uint32_t first)
+               unsigned long long *flip_a, unsigned long long *flip_c, uint32_t first, bool swap)
 {
     const int a = q->cur, b = 1 - q->cur;
     QZ_HIP(q, qz::bit_sweep2(q->st, q->L, q->seed, (uint32_t)q->t, q->tune2, bit_plane(q, a, 0),
                              bit_plane(q, a, 1), bit_plane(q, b, 0), bit_plane(q, b, 1), acc_a,
-                             acc_c, flip_a, flip_c, first));
+                             acc_c, flip_a, flip_c, first, swap));
     q->cur = b;
     q->t += 2;
     return QZ_OK;
@@ -190,15 +191,16 @@ int run_impl(qz_lattice *q, uint64_t n, uint64_t every, unsigned long long *dev_
     for (uint64_t k = 0; k < n;) {
         int rc;
         uint32_t first = 0u;
-        bool pair = pairs && n - k >= 2;
+        bool swap = false;
+        const bool pair = pairs && n - k >= 2;
         if (pair && q->mixed) {
-            // a pass carries two sweeps only when both update the same colour first
+            // the pass takes both orders of the second sweep
             first = mixed_first_colour(q->seed, (uint32_t)q->t);
-            pair = mixed_first_colour(q->seed, (uint32_t)q->t + 1u) == first;
+            swap = mixed_first_colour(q->seed, (uint32_t)q->t + 1u) != first;
         }
         if (pair) {
             rc = sweep_pair(q, slot(dev_trace, k), slot(dev_trace, k + 1), slot(dev_flips, k),
-                            slot(dev_flips, k + 1), first);
+                            slot(dev_flips, k + 1), first, swap);
             k += 2;
         } else {
             rc = sweep_once(q, slot(dev_trace, k), slot(dev_flips, k));

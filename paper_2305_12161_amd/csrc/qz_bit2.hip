@@ -11,9 +11,10 @@
 //   C  sweep t+1, colour 0 of plane q-2  from B's colour 1 of planes q-3, q-2, q-1
 //   D  sweep t+1, colour 1 of plane q-3  from C's colour 0 of planes q-4, q-3, q-2
 // (Methods, "Checkerboard update": each colour reads only the other one);
-// "colour 0" here is the colour updated first in both sweeps, which the
-// mixed cycle draws per sweep (Supplementary Methods I B): pairs of sweeps
-// that draw the same first colour run here with the planes exchanged.  The
+// "colour 0" here is the colour updated first in sweep t, which the mixed
+// cycle draws per sweep (Supplementary Methods I B): colour 1 first runs with
+// the planes exchanged, and a sweep t+1 that draws the other first colour
+// runs C and D the other way round (MODE 3 below).  The
 // y-neighbour rows of every stage's input come from LDS (four row sets per
 // step, double-buffered, one barrier per step); each stage loses one row at
 // each side, so the tile owns rows [4, E-4) and recomputes the rest, and it
@@ -75,15 +76,23 @@ __device__ __forceinline__ void copy_words(uint32_t (&d)[V], const uint32_t (&s)
 // the odd wave the odd ones.  Every wave's rows then share the parity of y, so
 // the x parity pi of all four stages is the same across the wave and the
 // x-neighbour shift takes one uniform branch instead of both.
-// DCB: the double-checkerboard sweep described above, 1 = 01 cycle, 2 = mixed
-// cycle (CA then counts the entering bonds and the flips of the pass; CC is
-// not used).
+// MODE 0: two sweeps that update the same colour first.  MODE 1, 2: the
+// double-checkerboard sweep described above, 01 or mixed cycle (CA then
+// counts the entering bonds and the flips of the pass; CC is not used).
+// MODE 3: two sweeps of the mixed cycle that draw different first colours,
+// so the colours go 0, 1 | 1, 0 ("colour 0" being sweep t's first): C updates
+// colour 1 of plane q-2 again, from A's colour 0 of planes q-3, q-2, q-1
+// (their rows take B's row set, which C no longer reads), and D colour 0 of
+// plane q-3 from C's colour 1; C and D draw the tie bits of sweep t+1 with
+// their own colours, and their x parity is the opposite of A's and B's.
 // The mixed double checkerboard keeps more state per lane (the cube-order
 // masks of two stages): its workgroups are limited to 512 lanes, which leaves
 // it registers enough not to spill.
-template <int V, bool CA, bool CC, bool PAIRED, int DCB>
-__global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args A)
+template <int V, bool CA, bool CC, bool PAIRED, int MODE>
+__global__ void __launch_bounds__(MODE == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args A)
 {
+    constexpr bool DCB = MODE == 1 || MODE == 2;
+    constexpr bool SWAP = MODE == 3;
     extern __shared__ uint32_t lds[];
     const uint32_t L = A.L, W = A.W, E = A.E;
     const uint32_t tid = threadIdx.x;
@@ -121,13 +130,14 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
     uint32_t c1m[V], c1c[V], c1p[V], pf1[V], pg1[V];
     uint32_t c0o[V], pf0[V], pg0[V];
     uint32_t n0a[V], n0b[V], n0n[V];           // colour 0 after sweep t: q-1, q-2; new q
+    uint32_t n0c[V];                           // SWAP: colour 0 after sweep t, plane q-3
     uint32_t n1a[V], n1b[V], n1n[V];           // colour 1 after sweep t: q-2, q-3; new q-1
     uint32_t m0a[V], m0b[V], m0n[V];           // colour 0 after sweep t+1: q-3, q-4; new q-2
     uint32_t m1n[V];                           // colour 1 after sweep t+1: new q-3
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         c1m[v] = c1c[v] = c1p[v] = pf1[v] = c0o[v] = pf0[v] = pg1[v] = pg0[v] = 0u;
-        n0a[v] = n0b[v] = n0n[v] = n1a[v] = n1b[v] = n1n[v] = 0u;
+        n0a[v] = n0b[v] = n0n[v] = n0c[v] = n1a[v] = n1b[v] = n1n[v] = 0u;
         m0a[v] = m0b[v] = m0n[v] = m1n[v] = 0u;
     }
     if (held) {
@@ -157,8 +167,8 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
         tie_words<V>(A.k0, A.k1, ga, ga & 3u, A.t, A.f, a);
         tie_words<V>(A.k0, A.k1, gb, gb & 3u, A.t, 1u - A.f, b);
         const uint32_t t2 = DCB ? A.t : A.t + 1u;
-        tie_words<V>(A.k0, A.k1, gc, gc & 3u, t2, A.f, c);
-        tie_words<V>(A.k0, A.k1, gd, gd & 3u, t2, 1u - A.f, d);
+        tie_words<V>(A.k0, A.k1, gc, gc & 3u, t2, SWAP ? 1u - A.f : A.f, c);
+        tie_words<V>(A.k0, A.k1, gd, gd & 3u, t2, SWAP ? A.f : 1u - A.f, d);
     };
     uint32_t sA[V], sB[V], sC[V], sD[V];   // tie words of the next step's stages
     draw_step((z0 + L - 3) % L, sA, sB, sC, sD);
@@ -179,7 +189,7 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
     };
     // mixed: the coarse colour taken first, and per word the sites whose cube
     // takes fine colour 1 first (stages A and C), kept per layer of cubes
-    constexpr bool MIX = DCB == 2;
+    constexpr bool MIX = MODE == 2;
     const uint32_t cc0 = MIX ? (philox10(0u, A.t, 3u, 0u, A.k0, A.k1).w[0] & 1u) : 0u;
     uint32_t fA[V], fC[V];
     uint32_t kA = 0xFFFFFFFFu, kC = 0xFFFFFFFFu;
@@ -225,7 +235,7 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
         if (held) {
             store_words<V>(X1 + e * W + w0, c1c);
             store_words<V>(X0 + e * W + w0, n0a);
-            store_words<V>(Y1 + e * W + w0, n1a);
+            store_words<V>(Y1 + e * W + w0, SWAP ? n0b : n1a);
             store_words<V>(Y0 + e * W + w0, m0a);
         }
         __syncthreads();
@@ -235,6 +245,8 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
         if constexpr (PAIRED)
             pi = __builtin_amdgcn_readfirstlane(pi);   // the same in every lane of the wave
         const uint32_t wadj = pi == 0u ? wprev : wnext;
+        const uint32_t piC = SWAP ? pi ^ 1u : pi;          // stages C and D
+        const uint32_t wadjC = piC == 0u ? wprev : wnext;
         // A: sweep t, colour 0, plane q
         if (rowA) {
             uint32_t ym[V], yp[V];
@@ -292,9 +304,12 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
             uint32_t ym[V], yp[V];
             load_words<V>(Y1 + em * W + w0, ym);
             load_words<V>(Y1 + ep * W + w0, yp);
-            const uint32_t adj = Y1[e * W + wadj];
+            const uint32_t adj = Y1[e * W + wadjC];
             int a_sum = 0;
-            rule_words<V, CC>(n0b, n1a, adj, pi, ym, yp, n1b, n1n, rC, m0n, a_sum);
+            if constexpr (SWAP)
+                rule_words<V, CC>(n1a, n0b, adj, piC, ym, yp, n0c, n0a, rC, m0n, a_sum);
+            else
+                rule_words<V, CC>(n0b, n1a, adj, pi, ym, yp, n1b, n1n, rC, m0n, a_sum);
             if constexpr (DCB) {
                 uint32_t m[V];
                 coarse0(zc, m);
@@ -318,7 +333,7 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
                     bonds_c += a_sum;
 #pragma unroll
                     for (int v = 0; v < V; ++v)
-                        flips_c = popc_acc(n0b[v] ^ m0n[v], flips_c);
+                        flips_c = popc_acc((SWAP ? n1a[v] : n0b[v]) ^ m0n[v], flips_c);
                 }
                 store_words_nt<V>(A.D0 + off(zc), m0n);
             }
@@ -328,9 +343,12 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
             uint32_t ym[V], yp[V];
             load_words<V>(Y0 + em * W + w0, ym);
             load_words<V>(Y0 + ep * W + w0, yp);
-            const uint32_t adj = Y0[e * W + wadj];
+            const uint32_t adj = Y0[e * W + wadjC];
             int unused = 0;
-            rule_words<V, false>(n1b, m0a, adj, pi, ym, yp, m0b, m0n, rD, m1n, unused);
+            if constexpr (SWAP)
+                rule_words<V, false>(n0c, m0a, adj, piC, ym, yp, m0b, m0n, rD, m1n, unused);
+            else
+                rule_words<V, false>(n1b, m0a, adj, pi, ym, yp, m0b, m0n, rD, m1n, unused);
             if constexpr (DCB) {
                 uint32_t m[V];
                 coarse0(zd, m);
@@ -347,7 +365,7 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
             if constexpr (CC) {
 #pragma unroll
                 for (int v = 0; v < V; ++v)
-                    flips_c = popc_acc(n1b[v] ^ m1n[v], flips_c);
+                    flips_c = popc_acc((SWAP ? n0c[v] : n1b[v]) ^ m1n[v], flips_c);
             }
             store_words_nt<V>(A.D1 + off(zd), m1n);
         }
@@ -358,6 +376,8 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
         copy_words<V>(c0o, pf0);
         copy_words<V>(pf1, pg1);
         copy_words<V>(pf0, pg0);
+        if constexpr (SWAP)
+            copy_words<V>(n0c, n0b);
         copy_words<V>(n0b, n0a);
         copy_words<V>(n0a, n0n);
         copy_words<V>(n1b, n1a);
@@ -400,24 +420,24 @@ __global__ void __launch_bounds__(DCB == 2 ? 512 : 1024) k_bit_sweep2(Sweep2Args
     }
 }
 
-template <int V, bool P, int DCB = 0>
+template <int V, bool P, int MODE = 0>
 void launch2(hipStream_t st, const Sweep2Args &a, dim3 grid, dim3 block, size_t lds)
 {
     const bool ca = a.acc_a != nullptr || a.flip_a != nullptr;
     const bool cc = a.acc_c != nullptr || a.flip_c != nullptr;
-    if constexpr (DCB != 0) {
+    if constexpr (MODE == 1 || MODE == 2) {
         if (ca)
-            hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P, DCB>), grid, block, lds, st, a);
+            hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P, MODE>), grid, block, lds, st, a);
         else
-            hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P, DCB>), grid, block, lds, st, a);
+            hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P, MODE>), grid, block, lds, st, a);
     } else if (ca && cc) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, true, true, P, 0>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, true, true, P, MODE>), grid, block, lds, st, a);
     } else if (ca) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P, 0>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, true, false, P, MODE>), grid, block, lds, st, a);
     } else if (cc) {
-        hipLaunchKernelGGL((k_bit_sweep2<V, false, true, P, 0>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, false, true, P, MODE>), grid, block, lds, st, a);
     } else {
-        hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P, 0>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_bit_sweep2<V, false, false, P, MODE>), grid, block, lds, st, a);
     }
 }
 
@@ -493,7 +513,7 @@ int bit_pass_default(uint32_t L) { return L >= 1024 ? 2 : 1; }
 namespace {
 
 // the launch geometry and arguments shared by both entry points
-template <int DCB>
+template <int MODE>
 hipError_t sweep2_launch(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t,
                          const BitTuning &tu, Sweep2Args &a)
 {
@@ -516,12 +536,12 @@ hipError_t sweep2_launch(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t,
     switch (tu.V) {
     case 4:
         if (paired)
-            launch2<4, true, DCB>(st, a, grid, block, lds);
+            launch2<4, true, MODE>(st, a, grid, block, lds);
         else
-            launch2<4, false, DCB>(st, a, grid, block, lds);
+            launch2<4, false, MODE>(st, a, grid, block, lds);
         break;
-    case 2: launch2<2, false, DCB>(st, a, grid, block, lds); break;
-    default: launch2<1, false, DCB>(st, a, grid, block, lds); break;
+    case 2: launch2<2, false, MODE>(st, a, grid, block, lds); break;
+    default: launch2<1, false, MODE>(st, a, grid, block, lds); break;
     }
     return hipGetLastError();
 }
@@ -531,24 +551,26 @@ hipError_t sweep2_launch(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t,
 hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                       const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
                       unsigned long long *acc_a, unsigned long long *acc_c,
-                      unsigned long long *flip_a, unsigned long long *flip_c, uint32_t first)
+                      unsigned long long *flip_a, unsigned long long *flip_c, uint32_t first,
+                      bool swap)
 {
     if (!bit_tuning2_valid(L, tu) || first > 1u)
         return hipErrorInvalidValue;
     Sweep2Args a;
     // the kernel's stages A and C update "colour 0", B and D "colour 1": here
-    // the colour updated first, and the other
+    // the colour updated first, and the other (swap: C and D the other way
+    // round; C writes through D0 and D the other plane)
     a.S0 = first ? S1 : S0;
     a.S1 = first ? S0 : S1;
-    a.D0 = first ? D1 : D0;
-    a.D1 = first ? D0 : D1;
+    a.D0 = (first ^ (swap ? 1u : 0u)) ? D1 : D0;
+    a.D1 = (first ^ (swap ? 1u : 0u)) ? D0 : D1;
     a.f = first;
     a.sB = 0;
     a.acc_a = acc_a;
     a.acc_c = acc_c;
     a.flip_a = flip_a;
     a.flip_c = flip_c;
-    return sweep2_launch<0>(st, L, seed, t, tu, a);
+    return swap ? sweep2_launch<3>(st, L, seed, t, tu, a) : sweep2_launch<0>(st, L, seed, t, tu, a);
 }
 
 bool bit_double_sweep2_fits(uint32_t L, const BitTuning &tu, bool mixed)

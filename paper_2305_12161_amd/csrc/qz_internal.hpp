@@ -59,13 +59,15 @@ hipError_t bit_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, cons
                      const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
                      unsigned long long *bond_acc, bool mixed,
                      unsigned long long *flip_acc = nullptr);
-// Sweeps t and t+1 of the 01 cycle in one pass (copy S -> copy D); acc_a /
-// acc_c (nullable) receive the bond counts of the states entering them.
+// Sweeps t and t+1 in one pass (copy S -> copy D); acc_a / acc_c (nullable)
+// receive the bond counts of the states entering them.  first: the colour
+// sweep t updates first; swap: sweep t+1 updates the other colour first (the
+// mixed cycle's pairs of different orders), else the same one.
 hipError_t bit_sweep2(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, const BitTuning &tu,
                       const uint32_t *S0, const uint32_t *S1, uint32_t *D0, uint32_t *D1,
                       unsigned long long *acc_a, unsigned long long *acc_c,
                       unsigned long long *flip_a = nullptr, unsigned long long *flip_c = nullptr,
-                      uint32_t first = 0);
+                      uint32_t first = 0, bool swap = false);
 hipError_t bit_bonds(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,
                      unsigned long long *acc3);
 hipError_t bit_bonds_total(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32_t *P1,

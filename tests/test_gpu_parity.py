@@ -200,24 +200,18 @@ def test_two_sweep_pass_trace_alignment(qz, orc, every, n):
 @pytest.mark.parametrize("L,tuning", [(64, (1, 24, 5)), (128, (2, 56, 8)), (256, (4, 120, 5)),
                                       (256, (4, 24, 32))])
 def test_two_sweep_pass_mixed_cycle(qz, orc, L, tuning):
-    """The mixed cycle with two sweeps per pass: consecutive sweeps that draw
-    the same first colour share a pass (planes exchanged when it is colour
-    1), the others run alone; every sweep traced, against the oracle."""
+    """The mixed cycle with two sweeps per pass: every two consecutive sweeps
+    share a pass, whichever first colours they draw (planes exchanged when
+    sweep t draws colour 1; the second sweep's stages the other way round
+    when it draws the other colour); every sweep traced, against the oracle."""
     n = 21
 
-    def shared_passes(seed):   # first colours of the pairs that share a pass
+    def pair_orders(seed):     # (first colour of t, of t+1) of each shared pass
         fc = [orc.first_colour(seed, t) for t in range(n)]
-        t, out = 0, []
-        while t < n:
-            if t + 1 < n and fc[t] == fc[t + 1]:
-                out.append(fc[t])
-                t += 2
-            else:
-                t += 1
-        return set(out)
+        return {(fc[t], fc[t + 1]) for t in range(0, n - 1, 2)}
 
     seed = 700 + L
-    while shared_passes(seed) != {0, 1}:   # a run with passes of both orders
+    while len(pair_orders(seed)) < 4:      # passes of all four order pairs
         seed += 1
     s = orc.init(L, seed)
     want = orc.run(s, seed, 0, n, 1, mixed=True)
@@ -228,6 +222,25 @@ def test_two_sweep_pass_mixed_cycle(qz, orc, L, tuning):
     tr = lat.run(n, 1)
     assert np.array_equal(tr.astype(np.int64), want)
     assert np.array_equal(lat.download(), s)
+
+
+def test_two_sweep_pass_mixed_cycle_large(qz):
+    """L = 1024, the paired tile of the large lattices: the mixed cycle with two
+    sweeps per pass (all four order pairs occur in 12 sweeps of this seed)
+    gives the same bond and flip traces and lattice as one sweep per pass."""
+    L, seed = 1024, 91
+    say("two-sweep mixed vs one-sweep", L, seed)
+    two = qz.Lattice(L, seed, "bit")
+    two.set_cycle(True)
+    two.set_pass(2, 4, 56, 64)
+    B2, F2 = two.run_traced(12, 1)
+    one = qz.Lattice(L, seed, "bit")
+    one.set_cycle(True)
+    one.set_pass(1)
+    B1, F1 = one.run_traced(12, 1)
+    assert np.array_equal(B2, B1)
+    assert np.array_equal(F2, F1)
+    assert np.array_equal(two.download(), one.download())
 
 
 def test_two_sweep_pass_falls_back_and_rejects(qz, orc):
@@ -620,19 +633,20 @@ def test_double_checkerboard_rejects(qz):
                                            ("bit", 64, "dcb"), ("bit", 128, "dcb-mixed"),
                                            ("bit", 256, "dcb"), ("bit", 256, "dcb-mixed"),
                                            ("bit", 128, "dcb-pass2"), ("bit", 256, "dcb-pass2"),
+                                           ("bit", 128, "mixed-pass2"), ("bit", 256, "mixed-pass2"),
                                            ("bit", 128, "dcb-mixed-pass2"),
                                            ("bit", 256, "dcb-mixed-pass2")])
 def test_flip_trace_matches_oracle(qz, orc, layout, L, mode):
     seed = 300 + L
     say("flips", layout, L, mode)
     lat = qz.Lattice(L, seed, layout)
-    mixed = mode in ("mixed", "dcb-mixed", "dcb-mixed-pass2")
+    mixed = mode in ("mixed", "mixed-pass2", "dcb-mixed", "dcb-mixed-pass2")
     double_B = 4 if mode.startswith("dcb") else 0
     if mixed:
         lat.set_cycle(True)
     if double_B:
         lat.set_double_checkerboard(double_B)
-    if mode in ("pass2", "dcb-pass2", "dcb-mixed-pass2"):
+    if mode in ("pass2", "mixed-pass2", "dcb-pass2", "dcb-mixed-pass2"):
         lat.set_pass(2)
     for every, n in ((1, 5), (3, 9)):
         B, F = lat.run_traced(n, every)
