@@ -82,8 +82,8 @@ hipError_t bit_double_sweep(hipStream_t st, uint32_t L, uint32_t B, uint64_t see
 hipError_t bit_double_phase(hipStream_t st, uint32_t L, uint32_t B, uint64_t seed, uint32_t t,
                             uint32_t *P0, uint32_t *P1, uint32_t kc, uint32_t p, uint32_t step,
                             bool mixed, unsigned long long *flip_acc);
-// Whether bit_double_sweep2 takes tiling tu at side L (the mixed cycle needs
-// workgroups of at most 512 lanes).
+// Whether bit_double_sweep2 takes tiling tu at side L (the mixed cycle runs
+// with fewer rows per tile, about 256 lanes, and needs at most 512).
 bool bit_double_sweep2_fits(uint32_t L, const BitTuning &tu, bool mixed);
 // One double-checkerboard sweep in one pass of the two-sweep kernel (copy S ->
 // copy D, tiling tu); bond_acc / flip_acc (nullable) receive the bond count

@@ -570,7 +570,7 @@ def test_double_checkerboard_matches_oracle(qz, orc, L, B, mixed):
                                       (192, 32, None), (256, 2, None), (256, 4, (4, 24, 8)),
                                       (256, 16, None), (256, 64, None), (256, 128, (4, 120, 40)),
                                       (512, 8, (4, 56, 16)), (512, 256, (4, 56, 64)),
-                                      # 1024 lanes: the mixed cycle falls back to its phases
+                                      # 1024 lanes (the mixed cycle cuts the rows to 56)
                                       (512, 16, (2, 248, 16))])
 def test_double_checkerboard_one_pass_matches_oracle(qz, orc, L, B, tile, mixed):
     seed = 190 + L + B + (500 if mixed else 0)
