@@ -1,4 +1,5 @@
-// qz_bit2.hip -- two sweeps of the 01 cycle in ONE streaming pass (1-bit layout).
+// qz_bit2.hip -- two sweeps in ONE streaming pass (1-bit layout), and one
+// double-checkerboard sweep in the same four-stage pass.
 //
 // The one-sweep kernel reads every word once and writes it once per sweep, so
 // it is bound by HBM.  Here a workgroup carries the lattice through sweeps t
@@ -21,8 +22,8 @@
 // recomputes three planes at each z end.  Reads copy A, writes copy B, so
 // tiles never race.  The results are identical to two one-sweep passes.
 //
-// DCB: one sweep of the double checkerboard's 01 cycle (Supplementary Methods
-// I A) in the same four stages.  Its four phases -- fine colour 0 then 1 of
+// MODE 1 and 2 (double checkerboard): one sweep of its 01 cycle
+// (Supplementary Methods I A) in the same four stages.  Its four phases -- fine colour 0 then 1 of
 // the coarse-colour-0 cubes, then of the coarse-colour-1 cubes -- read and
 // write the planes exactly as A, B, C, D do, except that each stage changes
 // only the sites of its coarse colour (A, B: 0; C, D: 1) and every stage draws
