@@ -266,7 +266,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the quench of one "
-              "lattice is not sharded across GPUs in this build.", file=sys.stderr)
+              "lattice is not sharded across GPUs; run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2305_12161_amd import binding, workloads
