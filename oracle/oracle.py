@@ -57,6 +57,10 @@ def _load():
                                       ctypes.c_int, ctypes.c_int, _i8p, ctypes.c_uint64,
                                       ctypes.c_uint64]
     lib.or_window_advance.restype = None
+    lib.or_window_advance_cycle.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_int, ctypes.c_int, _i8p,
+                                            ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int]
+    lib.or_window_advance_cycle.restype = None
     lib.or_first_colour.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
     lib.or_first_colour.restype = ctypes.c_int
     lib.or_sweep_mixed.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, _i8p]
@@ -256,14 +260,19 @@ def sweep_mixed(s: np.ndarray, seed: int, t: int) -> int:
     return int(_load().or_sweep_mixed(L, seed, t, _i8(s)))
 
 
-def window_advance(L: int, seed: int, origin, w: np.ndarray, t0: int, T: int) -> None:
+def window_advance(L: int, seed: int, origin, w: np.ndarray, t0: int, T: int,
+                   mixed: bool = False) -> None:
     """Advance a W^3 window (global corner `origin` = (ox, oy, oz)) by T sweeps in place.
 
     Sites within local distance 2T of a face are not trustworthy afterwards.
+    mixed=True follows the mixed cycle (colour order drawn per sweep).
     """
     W = w.shape[0]
     ox, oy, oz = (int(v) for v in origin)
-    _load().or_window_advance(L, seed, ox, oy, oz, W, _i8(w), t0, T)
+    if mixed:
+        _load().or_window_advance_cycle(L, seed, ox, oy, oz, W, _i8(w), t0, T, 1)
+    else:
+        _load().or_window_advance(L, seed, ox, oy, oz, W, _i8(w), t0, T)
 
 
 # --------------------------------------------------------------------------

@@ -423,12 +423,16 @@ void or_run(int L, uint64_t seed, int8_t *s, uint64_t t0, uint64_t n, uint64_t e
 /* half-sweep moves information by one site, after T sweeps every site at    */
 /* local distance >= 2T from each face holds the exact global result.        */
 /* ------------------------------------------------------------------------ */
-void or_window_advance(int L, uint64_t seed, int ox, int oy, int oz, int W, int8_t *w,
-                       uint64_t t0, uint64_t T)
+/* mixed != 0: the mixed cycle (Supplementary Methods I B), whose sweep t     */
+/* updates colour or_first_colour(seed, t) first; else the 01 cycle.         */
+void or_window_advance_cycle(int L, uint64_t seed, int ox, int oy, int oz, int W, int8_t *w,
+                             uint64_t t0, uint64_t T, int mixed)
 {
     for (uint64_t k = 0; k < T; ++k) {
         uint32_t t = (uint32_t)(t0 + k);
-        for (int p = 0; p < 2; ++p) {
+        int first = mixed ? or_first_colour(seed, t) : 0;
+        for (int half = 0; half < 2; ++half) {
+            int p = half ? 1 - first : first;
 #pragma omp parallel for schedule(static)
             for (int lz = 1; lz < W - 1; ++lz)
                 for (int ly = 1; ly < W - 1; ++ly)
@@ -459,6 +463,12 @@ void or_window_advance(int L, uint64_t seed, int ox, int oy, int oz, int W, int8
                     }
         }
     }
+}
+
+void or_window_advance(int L, uint64_t seed, int ox, int oy, int oz, int W, int8_t *w,
+                       uint64_t t0, uint64_t T)
+{
+    or_window_advance_cycle(L, seed, ox, oy, oz, W, w, t0, T, 0);
 }
 
 /* Thread control for the OpenMP loops; returns the count now in effect. */

@@ -367,6 +367,38 @@ def test_window_replay_matches_full_run(orc):
             assert np.array_equal(got, want)
 
 
+def test_window_replay_mixed_matches_full_run(orc):
+    """The mixed-cycle replay against full mixed-cycle runs; the 01-cycle
+    replay of the same cube differs wherever a sweep draws colour 1 first."""
+    L = 16
+    seed = 77
+    rng = np.random.default_rng(5)
+    s = orc.init(L, seed)
+    orc.run(s, seed, 0, 6, mixed=True)
+    t0 = 6
+    # the cycle must draw both orders within the replayed sweeps
+    assert {orc.first_colour(seed, t0 + k) for k in range(3)} == {0, 1}
+    differs = False
+    for T in (1, 2, 3):
+        for _ in range(3):
+            W = 4 + 4 * T + int(rng.integers(0, 3))
+            o = [int(v) for v in rng.integers(0, L, size=3)]
+            z, y, x = np.ix_([(o[2] + k) % L for k in range(W)], [(o[1] + k) % L for k in range(W)],
+                             [(o[0] + k) % L for k in range(W)])
+            w = np.ascontiguousarray(s[z, y, x])
+            w01 = w.copy()
+            full = s.copy()
+            orc.run(full, seed, t0, T, mixed=True)
+            orc.window_advance(L, seed, o, w, t0, T, mixed=True)
+            orc.window_advance(L, seed, o, w01, t0, T)
+            m = 2 * T
+            got = w[m:W - m, m:W - m, m:W - m]
+            want = full[z, y, x][m:W - m, m:W - m, m:W - m]
+            assert np.array_equal(got, want)
+            differs |= not np.array_equal(w01[m:W - m, m:W - m, m:W - m], want)
+    assert differs
+
+
 def test_init_window_is_a_slice_of_init(orc):
     L = 12
     s = orc.init(L, 8)
