@@ -123,6 +123,23 @@ int qz_run_traced(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64
 int qz_run_device_traced(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_every, uint64_t *dev_B,
                          uint64_t *dev_flips);
 
+/* As qz_run_traced / qz_run_device_traced, but the traced sweeps are listed:
+ * at[0 .. n_at-1] are sweep offsets within the run (0 <= at[i] < n_sweeps,
+ * strictly increasing; QZ_EINVAL otherwise), and entry i of B / flips belongs
+ * to sweep t0 + at[i] (the bond count of the state entering it, the spins it
+ * flips).  This fits measurement schedules that are not uniform, such as the
+ * log-spaced times of the Results.  Listed sweeps do not break the pairing of
+ * sweeps into passes over memory (qz_set_pass): either sweep of a pass can be
+ * counted inside the pass.  B or flips may be null (not both when n_at > 0).
+ * qz_run_at writes host arrays and synchronises; qz_run_device_at writes
+ * caller device memory (n_at uint64 values each, zeroed by the library) and
+ * never synchronises; the list itself is host memory, read before the call
+ * returns. */
+int qz_run_at(qz_lattice *q, uint64_t n_sweeps, const uint64_t *at, size_t n_at,
+              uint64_t *host_B, uint64_t *host_flips);
+int qz_run_device_at(qz_lattice *q, uint64_t n_sweeps, const uint64_t *at, size_t n_at,
+                     uint64_t *dev_B, uint64_t *dev_flips);
+
 /* Per-axis unsatisfied-bond counts [B_x, B_y, B_z] of the current state. */
 int qz_bonds(qz_lattice *q, uint64_t out_B_axes[3]);
 

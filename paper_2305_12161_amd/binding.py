@@ -38,6 +38,8 @@ def _load():
         "qz_run_device": ([vp, u64, u64, vp], i32),
         "qz_run_traced": ([vp, u64, u64, c.POINTER(u64), c.POINTER(u64)], i32),
         "qz_run_device_traced": ([vp, u64, u64, vp, vp], i32),
+        "qz_run_at": ([vp, u64, c.POINTER(u64), sz, c.POINTER(u64), c.POINTER(u64)], i32),
+        "qz_run_device_at": ([vp, u64, c.POINTER(u64), sz, vp, vp], i32),
         "qz_bonds": ([vp, c.POINTER(u64)], i32),
         "qz_corr": ([vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64)], i32),
         "qz_time": ([vp, c.POINTER(u64)], i32),
@@ -154,6 +156,26 @@ class Lattice:
         pb = ctypes.c_void_p(dev_B.data_ptr()) if dev_B is not None else None
         pf = ctypes.c_void_p(dev_flips.data_ptr()) if dev_flips is not None else None
         _check(lib.qz_run_device_traced(self._h, n, trace_every, pb, pf))
+
+    def run_at(self, n: int, at):
+        """Run n sweeps; returns (B, flips) for the sweeps at the listed offsets
+        (strictly increasing, each < n): the bond count entering the sweep and
+        the number of spins it flipped."""
+        P = ctypes.POINTER(ctypes.c_uint64)
+        lst = np.ascontiguousarray(at, dtype=np.uint64)
+        B = np.zeros(lst.size, dtype=np.uint64)
+        F = np.zeros(lst.size, dtype=np.uint64)
+        _check(lib.qz_run_at(self._h, n, lst.ctypes.data_as(P), lst.size, B.ctypes.data_as(P),
+                             F.ctypes.data_as(P)))
+        return B.astype(np.int64), F.astype(np.int64)
+
+    def run_device_at(self, n: int, at, dev_B, dev_flips) -> None:
+        """Asynchronous run; device traces of B and of the flips at the listed sweeps."""
+        P = ctypes.POINTER(ctypes.c_uint64)
+        lst = np.ascontiguousarray(at, dtype=np.uint64)
+        pb = ctypes.c_void_p(dev_B.data_ptr()) if dev_B is not None else None
+        pf = ctypes.c_void_p(dev_flips.data_ptr()) if dev_flips is not None else None
+        _check(lib.qz_run_device_at(self._h, n, lst.ctypes.data_as(P), lst.size, pb, pf))
 
     def bonds(self) -> np.ndarray:
         out = np.zeros(3, dtype=np.uint64)

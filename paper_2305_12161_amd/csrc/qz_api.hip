@@ -156,9 +156,6 @@ int sweep_pair(qz_lattice *q, unsigned long long *acc_a, unsigned long long *acc
     return QZ_OK;
 }
 
-// n sweeps; with every > 0, sweep k (k % every == 0) adds its entering bond
-// count to dev_trace[k / every] and its accepted flips to dev_flips[k / every]
-// (either pointer may be null).
 // Bit 0 of word 0 of the Philox4x32-10 block (0, t, 2, 0) under the key
 // (seed mod 2^32, seed >> 32): 1 when colour 1 goes first in sweep t of the
 // mixed cycle (Supplementary Methods I B), as the sweep kernels draw it.  The
@@ -181,14 +178,34 @@ uint32_t mixed_first_colour(uint64_t seed, uint32_t t)
     return c0 & 1u;
 }
 
-int run_impl(qz_lattice *q, uint64_t n, uint64_t every, unsigned long long *dev_trace,
+// Which sweeps of a run are traced: every `every`-th one (k % every == 0,
+// entry k / every), or those listed in `at` (sorted, strictly increasing;
+// entry i for the sweep at[i]).  Neither: no sweep.
+struct TracePlan {
+    uint64_t every = 0;
+    const uint64_t *at = nullptr;
+    size_t n_at = 0;
+    // entry of sweep k, or -1; sweeps are asked for in increasing order
+    mutable size_t next = 0;
+    int64_t entry(uint64_t k) const
+    {
+        if (every > 0)
+            return k % every == 0 ? (int64_t)(k / every) : -1;
+        while (next < n_at && at[next] < k)
+            ++next;
+        return (next < n_at && at[next] == k) ? (int64_t)next : -1;
+    }
+};
+
+int run_plan(qz_lattice *q, uint64_t n, const TracePlan &plan, unsigned long long *dev_trace,
              unsigned long long *dev_flips)
 {
     const bool pairs = q->pass == 2 && q->layout == QZ_LAYOUT_BIT && q->dcb == 0;
-    auto slot = [&](unsigned long long *base, uint64_t k) -> unsigned long long * {
-        return (every > 0 && base != nullptr && k % every == 0) ? base + k / every : nullptr;
+    auto slot = [&](unsigned long long *base, int64_t e) -> unsigned long long * {
+        return (base != nullptr && e >= 0) ? base + e : nullptr;
     };
     for (uint64_t k = 0; k < n;) {
+        const int64_t e0 = plan.entry(k);
         int rc;
         uint32_t first = 0u;
         bool swap = false;
@@ -199,15 +216,41 @@ int run_impl(qz_lattice *q, uint64_t n, uint64_t every, unsigned long long *dev_
             swap = mixed_first_colour(q->seed, (uint32_t)q->t + 1u) != first;
         }
         if (pair) {
-            rc = sweep_pair(q, slot(dev_trace, k), slot(dev_trace, k + 1), slot(dev_flips, k),
-                            slot(dev_flips, k + 1), first, swap);
+            const int64_t e1 = plan.entry(k + 1);
+            rc = sweep_pair(q, slot(dev_trace, e0), slot(dev_trace, e1), slot(dev_flips, e0),
+                            slot(dev_flips, e1), first, swap);
             k += 2;
         } else {
-            rc = sweep_once(q, slot(dev_trace, k), slot(dev_flips, k));
+            rc = sweep_once(q, slot(dev_trace, e0), slot(dev_flips, e0));
             k += 1;
         }
         if (rc != QZ_OK)
             return rc;
+    }
+    return QZ_OK;
+}
+
+// n sweeps; with every > 0, sweep k (k % every == 0) adds its entering bond
+// count to dev_trace[k / every] and its accepted flips to dev_flips[k / every]
+// (either pointer may be null).
+int run_impl(qz_lattice *q, uint64_t n, uint64_t every, unsigned long long *dev_trace,
+             unsigned long long *dev_flips)
+{
+    TracePlan plan;
+    plan.every = every;
+    return run_plan(q, n, plan, every > 0 ? dev_trace : nullptr, every > 0 ? dev_flips : nullptr);
+}
+
+// The list of traced sweeps must be strictly increasing and inside the run.
+int check_list(const uint64_t *at, size_t n_at, uint64_t n_sweeps)
+{
+    if (n_at > 0 && !at)
+        return fail(QZ_EINVAL, "null list of traced sweeps");
+    for (size_t i = 0; i < n_at; ++i) {
+        if (at[i] >= n_sweeps)
+            return fail(QZ_EINVAL, "a traced sweep lies beyond the run");
+        if (i > 0 && at[i] <= at[i - 1])
+            return fail(QZ_EINVAL, "traced sweeps must be strictly increasing");
     }
     return QZ_OK;
 }
@@ -393,6 +436,77 @@ QZ_EXPORT int qz_run_device(qz_lattice *q, uint64_t n_sweeps, uint64_t trace_eve
     if (q && trace_every > 0 && !dev_trace)
         return fail(QZ_EINVAL, "null trace buffer");
     return qz_run_device_traced(q, n_sweeps, trace_every, dev_trace, nullptr);
+}
+
+QZ_EXPORT int qz_run_device_at(qz_lattice *q, uint64_t n_sweeps, const uint64_t *at,
+                               size_t n_at, uint64_t *dev_B, uint64_t *dev_flips)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if ((rc = check_list(at, n_at, n_sweeps)) != QZ_OK)
+        return rc;
+    unsigned long long *slots = reinterpret_cast<unsigned long long *>(dev_B);
+    unsigned long long *fslots = reinterpret_cast<unsigned long long *>(dev_flips);
+    if (n_at > 0 && !slots && !fslots)
+        return fail(QZ_EINVAL, "null trace buffers");
+    if (n_at > 0 && slots)
+        QZ_HIP(q, qz::fill_u64(q->st, slots, n_at, 0ull));
+    if (n_at > 0 && fslots)
+        QZ_HIP(q, qz::fill_u64(q->st, fslots, n_at, 0ull));
+    TracePlan plan;
+    plan.at = at;
+    plan.n_at = n_at;
+    return run_plan(q, n_sweeps, plan, n_at > 0 ? slots : nullptr, n_at > 0 ? fslots : nullptr);
+}
+
+QZ_EXPORT int qz_run_at(qz_lattice *q, uint64_t n_sweeps, const uint64_t *at, size_t n_at,
+                        uint64_t *host_B, uint64_t *host_flips)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if ((rc = check_list(at, n_at, n_sweeps)) != QZ_OK)
+        return rc;
+    if (n_at == 0)
+        return run_impl(q, n_sweeps, 0, nullptr, nullptr);
+    if (!host_B && !host_flips)
+        return fail(QZ_EINVAL, "null trace buffers");
+    unsigned long long *slots =
+        reinterpret_cast<unsigned long long *>(q->base + q->map.trace_off);
+    unsigned long long *fslots =
+        reinterpret_cast<unsigned long long *>(q->base + q->map.flips_off);
+    // runs of at most kTraceCap listed sweeps, each through the handle's rings
+    uint64_t k0 = 0;
+    size_t done = 0;
+    while (done < n_at) {
+        const size_t chunk = std::min<size_t>(n_at - done, qz::kTraceCap);
+        // this piece ends just before the first listed sweep of the next one
+        const uint64_t k1 = (done + chunk < n_at) ? at[done + chunk] : n_sweeps;
+        std::vector<uint64_t> rel(chunk);
+        for (size_t i = 0; i < chunk; ++i)
+            rel[i] = at[done + i] - k0;
+        if (host_B)
+            QZ_HIP(q, qz::fill_u64(q->st, slots, chunk, 0ull));
+        if (host_flips)
+            QZ_HIP(q, qz::fill_u64(q->st, fslots, chunk, 0ull));
+        TracePlan plan;
+        plan.at = rel.data();
+        plan.n_at = chunk;
+        rc = run_plan(q, k1 - k0, plan, host_B ? slots : nullptr, host_flips ? fslots : nullptr);
+        if (rc != QZ_OK)
+            return rc;
+        if (host_B)
+            QZ_HIP(q, hipMemcpyAsync(host_B + done, slots, chunk * 8, hipMemcpyDeviceToHost,
+                                     q->st));
+        if (host_flips)
+            QZ_HIP(q, hipMemcpyAsync(host_flips + done, fslots, chunk * 8,
+                                     hipMemcpyDeviceToHost, q->st));
+        QZ_HIP(q, hipStreamSynchronize(q->st));
+        done += chunk;
+        k0 = k1;
+    }
+    return QZ_OK;
 }
 
 QZ_EXPORT int qz_bonds(qz_lattice *q, uint64_t out_B_axes[3])
