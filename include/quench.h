@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define QZ_ABI_VERSION 1
+#define QZ_ABI_VERSION 2
 
 typedef enum {
     QZ_OK = 0,
@@ -250,41 +250,63 @@ int qz_fft_corr(qz_lattice *q, void *dev_scratch, size_t bytes, double *out_C, d
  * captured HIP graph.  Every replica follows exactly the trajectory a single
  * lattice created from the same (L, seed) would follow: batching never changes
  * results.  The paper runs 40 independent realisations per lattice size
- * (Results); a batch runs such ensembles side by side.
- *
- * Slots keep their L for the life of the batch; a slot can be restarted with
- * a new seed (serving) or parked (inactive slots are skipped).
+ * (Results); a batch runs such ensembles side by side, and a server keeps one
+ * batch resident and refills its slots (qz_batch_slot_replace).
  * ------------------------------------------------------------------------ */
 typedef struct qz_batch qz_batch;  /* opaque, library-owned host object */
 
 typedef struct {
     uint32_t L;      /* side; L % 64 == 0 and 64 <= L <= 256 */
     uint64_t seed;   /* seed of the T = infinity start and of the tie bits */
+    uint64_t t_max;  /* the replica stops (is skipped) from this time on; 0 = never */
 } qz_replica_spec;
 
 /* Device bytes for n replica slots with a bond-count ring of trace_cap
- * entries per slot; 0 if a size is unsupported. */
+ * entries per slot; 0 if a size is unsupported.  Slot i is sized for
+ * specs[i].L and can later hold any side up to that one. */
 size_t qz_batch_state_bytes(const qz_replica_spec *specs, size_t n, uint32_t trace_cap);
 
 /* Create the batch in caller memory and draw every slot's start (t := 0, all
  * slots active).  If trace_every > 0, the sweep starting at each time t with
  * t % trace_every == 0 records B(t) of that slot into its ring of trace_cap
- * entries (entry (t / trace_every) % trace_cap).  The library also creates a
- * private stream, used only to capture graphs.  Errors: QZ_EINVAL, QZ_ENOMEM,
+ * entries (entry (t / trace_every) % trace_cap).
+ * tuning_json (nullable) fixes the launch shape, e.g.
+ *     {"graph_sweeps": 100, "tz": {"64": 8, "128": 8, "256": 8}}
+ * -- planes per sub-tile for slots of side L (each must divide L; sides not
+ * named take the default, 8) and sweeps per captured graph (0: no graph;
+ * default 100; at most trace_cap * trace_every).  With tuning_json == NULL
+ * the library autotunes: for each side in the batch it times a few sweeps of
+ * the whole batch per candidate plane count (2, 4, 8, 16, 32) and keeps the
+ * fastest, then draws the starts again (the choice never changes results).
+ * The library also creates a private stream, used only to capture graphs.
+ * Errors: QZ_EINVAL (also for malformed tuning_json), QZ_ENOMEM,
  * QZ_EUNSUPPORTED, QZ_EDEVICE. */
 int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t trace_every,
                     uint32_t trace_cap, void *dev_mem, size_t dev_bytes, void *hip_stream,
-                    qz_batch **out);
+                    const char *tuning_json, qz_batch **out);
 int qz_batch_destroy(qz_batch *b);
 
-/* Advance every active slot by n_sweeps MCS (asynchronous). */
-int qz_batch_run(qz_batch *b, uint64_t n_sweeps);
+/* Advance every active slot by n_sweeps MCS (a slot with t_max stops there).
+ * host_traces == NULL or trace_every == 0: asynchronous.  Otherwise
+ * trace_every must equal the batch's, the call synchronises, and for slot s
+ * entry i of host_traces[s * P .. s * P + P - 1], P = ceil(n_sweeps /
+ * trace_every), is B(tau_s + i * trace_every), where tau_s is the first
+ * multiple of trace_every at or after the slot's time t0_s when the call
+ * starts -- or UINT64_MAX where the slot did not reach that time in this run
+ * (parked, at its t_max, or past the run's end). */
+int qz_batch_run(qz_batch *b, uint64_t n_sweeps, uint64_t trace_every, uint64_t *host_traces);
 
 /* Wait for the batch's work and refresh the host view of slot times. */
 int qz_batch_sync(qz_batch *b);
 
+/* Serving: put a new replica into a slot -- side spec->L (at most the side the
+ * slot was created with, QZ_EINVAL otherwise), seed, t_max -- drawing its
+ * start at t = 0 and making it active (synchronises; rebuilds the launch's
+ * tile tables if the side changes). */
+int qz_batch_slot_replace(qz_batch *b, size_t slot, const qz_replica_spec *spec);
+
 /* Restart a slot from a new T = infinity start drawn from `seed`, at t = 0,
- * and make it active (synchronises). */
+ * keeping its side and t_max, and make it active (synchronises). */
 int qz_batch_slot_reset(qz_batch *b, size_t slot, uint64_t seed);
 
 /* Park (active = 0) or resume (active = 1) a slot (synchronises). */
@@ -307,10 +329,15 @@ int qz_batch_bonds(qz_batch *b, size_t slot, uint64_t out_B_axes[3]);
 int qz_batch_corr(qz_batch *b, size_t slot, int64_t *out_S, int64_t *out_M);
 
 /* Planes per sub-tile for slots of side L (Tz divides L; 0 keeps the current
- * value; default 8) and sweeps per captured graph (0 = no graph; at most
+ * value) and sweeps per captured graph (0 = no graph; at most
  * trace_cap * trace_every, larger values are reduced to that, so that one
  * graph never reuses a ring entry).  Results never depend on it. */
 int qz_batch_set_tuning(qz_batch *b, uint32_t L, uint32_t Tz, uint32_t graph_sweeps);
+
+/* The launch shape in use as text (NUL-terminated, at most len bytes):
+ * {"source": "json" | "autotune" | "set", "graph_sweeps": G,
+ *  "tz": {"L": Tz, ...}} for every side in the batch. */
+int qz_batch_tuning_json(const qz_batch *b, char *buf, size_t len);
 
 /* Text for a status code, and the calling thread's last error message. */
 const char *qz_status_string(int status);

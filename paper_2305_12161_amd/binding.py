@@ -85,6 +85,18 @@ def _stream_handle(stream):
     return stream, ctypes.c_void_p(stream.cuda_stream)
 
 
+def _dev_buf(t, need: int):
+    """Device pointer of a torch tensor that receives `need` 64-bit values, or
+    None.  Refuses tensors the library would write past or misread."""
+    if t is None:
+        return None
+    if not t.is_cuda or t.element_size() != 8 or not t.is_contiguous():
+        raise ValueError("trace buffers must be contiguous 64-bit device tensors")
+    if t.numel() < need:
+        raise ValueError(f"trace buffer holds {t.numel()} values, the run writes {need}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 class Lattice:
     """One quench lattice held on the device (torch-owned memory)."""
 
@@ -137,7 +149,7 @@ class Lattice:
 
     def run_device(self, n: int, trace_every: int, dev_trace) -> None:
         """Asynchronous run; dev_trace is a torch int64/uint64 device tensor."""
-        ptr = ctypes.c_void_p(dev_trace.data_ptr()) if dev_trace is not None else None
+        ptr = _dev_buf(dev_trace, n // trace_every if trace_every else 0)
         _check(lib.qz_run_device(self._h, n, trace_every, ptr))
 
     def run_traced(self, n: int, trace_every: int):
@@ -153,8 +165,8 @@ class Lattice:
 
     def run_device_traced(self, n: int, trace_every: int, dev_B, dev_flips) -> None:
         """Asynchronous run with device traces of B and of the accepted flips."""
-        pb = ctypes.c_void_p(dev_B.data_ptr()) if dev_B is not None else None
-        pf = ctypes.c_void_p(dev_flips.data_ptr()) if dev_flips is not None else None
+        need = n // trace_every if trace_every else 0
+        pb, pf = _dev_buf(dev_B, need), _dev_buf(dev_flips, need)
         _check(lib.qz_run_device_traced(self._h, n, trace_every, pb, pf))
 
     def run_at(self, n: int, at):
@@ -173,8 +185,7 @@ class Lattice:
         """Asynchronous run; device traces of B and of the flips at the listed sweeps."""
         P = ctypes.POINTER(ctypes.c_uint64)
         lst = np.ascontiguousarray(at, dtype=np.uint64)
-        pb = ctypes.c_void_p(dev_B.data_ptr()) if dev_B is not None else None
-        pf = ctypes.c_void_p(dev_flips.data_ptr()) if dev_flips is not None else None
+        pb, pf = _dev_buf(dev_B, lst.size), _dev_buf(dev_flips, lst.size)
         _check(lib.qz_run_device_at(self._h, n, lst.ctypes.data_as(P), lst.size, pb, pf))
 
     def bonds(self) -> np.ndarray:
@@ -263,7 +274,7 @@ class Lattice:
 # batched replicas
 # --------------------------------------------------------------------------
 class _ReplicaSpec(ctypes.Structure):
-    _fields_ = [("L", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+    _fields_ = [("L", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("t_max", ctypes.c_uint64)]
 
 
 def _batch_signatures():
@@ -272,10 +283,11 @@ def _batch_signatures():
     spec_p = c.POINTER(_ReplicaSpec)
     sig = {
         "qz_batch_state_bytes": ([spec_p, sz, u32], sz),
-        "qz_batch_create": ([spec_p, sz, u32, u32, vp, sz, vp, c.POINTER(vp)], i32),
+        "qz_batch_create": ([spec_p, sz, u32, u32, vp, sz, vp, c.c_char_p, c.POINTER(vp)], i32),
         "qz_batch_destroy": ([vp], i32),
-        "qz_batch_run": ([vp, u64], i32),
+        "qz_batch_run": ([vp, u64, u64, c.POINTER(u64)], i32),
         "qz_batch_sync": ([vp], i32),
+        "qz_batch_slot_replace": ([vp, sz, spec_p], i32),
         "qz_batch_slot_reset": ([vp, sz, u64], i32),
         "qz_batch_slot_active": ([vp, sz, i32], i32),
         "qz_batch_slot_time": ([vp, sz, c.POINTER(u64)], i32),
@@ -284,6 +296,7 @@ def _batch_signatures():
         "qz_batch_bonds": ([vp, sz, c.POINTER(u64)], i32),
         "qz_batch_corr": ([vp, sz, c.POINTER(c.c_int64), c.POINTER(c.c_int64)], i32),
         "qz_batch_set_tuning": ([vp, u32, u32, u32], i32),
+        "qz_batch_tuning_json": ([vp, c.c_char_p, sz], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -294,24 +307,40 @@ def _batch_signatures():
 _batch_signatures()
 
 
+def _spec(s):
+    """(L, seed) or (L, seed, t_max) -> the C struct (t_max 0: no limit)."""
+    L, seed = int(s[0]), int(s[1])
+    t_max = int(s[2]) if len(s) > 2 else 0
+    return _ReplicaSpec(L, seed & (2**64 - 1), t_max)
+
+
 def batch_state_bytes(specs, trace_cap: int) -> int:
-    arr = (_ReplicaSpec * len(specs))(*[_ReplicaSpec(int(L), int(s) & (2**64 - 1))
-                                        for L, s in specs])
+    arr = (_ReplicaSpec * len(specs))(*[_spec(s) for s in specs])
     return int(lib.qz_batch_state_bytes(arr, len(specs), trace_cap))
 
 
 class Batch:
-    """Replica slots (L, seed) advanced together on the device."""
+    """Replica slots (L, seed[, t_max]) advanced together on the device.
+
+    tuning: the launch shape handed to the library -- "tuned" (default) takes
+    the autotuner's stored winners (tune.py) when every side of the batch has
+    one, else lets the library autotune at creation; None always lets the
+    library autotune; a dict or JSON text is passed as given."""
 
     def __init__(self, specs, trace_every: int = 0, trace_cap: int = 1024, device=None,
-                 stream=None):
+                 stream=None, tuning="tuned"):
+        import json
         import torch
-        self.specs = [(int(L), int(s)) for L, s in specs]
-        arr = (_ReplicaSpec * len(self.specs))(*[_ReplicaSpec(L, s & (2**64 - 1))
-                                                 for L, s in self.specs])
+        self.specs = [(int(s[0]), int(s[1])) for s in specs]
+        arr = (_ReplicaSpec * len(self.specs))(*[_spec(s) for s in specs])
         nbytes = int(lib.qz_batch_state_bytes(arr, len(self.specs), trace_cap))
         if nbytes == 0:
             raise QuenchError(QZ_EUNSUPPORTED, "unsupported replica size in the batch")
+        if isinstance(tuning, str) and tuning == "tuned":
+            from . import tune
+            tuning = tune.batch_tuning_json(sorted({L for L, _ in self.specs}))
+        if isinstance(tuning, dict):
+            tuning = json.dumps(tuning)
         device = torch.device("cuda") if device is None else torch.device(device)
         self.mem = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream, sh = _stream_handle(stream)
@@ -319,6 +348,7 @@ class Batch:
         h = ctypes.c_void_p()
         _check(lib.qz_batch_create(arr, len(self.specs), self.trace_every, self.trace_cap,
                                    ctypes.c_void_p(self.mem.data_ptr()), nbytes, sh,
+                                   tuning.encode() if tuning is not None else None,
                                    ctypes.byref(h)))
         self._h = h
 
@@ -336,8 +366,32 @@ class Batch:
         except Exception:
             pass
 
-    def run(self, n: int) -> None:
-        _check(lib.qz_batch_run(self._h, n))
+    def run(self, n: int, trace_every: int = 0):
+        """Advance every active slot n sweeps.  trace_every > 0 (the batch's
+        cadence) returns an int64 array [slot, i] of B at the traced times
+        reached in this run (-1 where a slot did not reach that time) and
+        synchronises; otherwise the call is asynchronous and returns None."""
+        if trace_every:
+            P = -(-n // trace_every)
+            out = np.zeros(len(self.specs) * P, dtype=np.uint64)
+            _check(lib.qz_batch_run(self._h, n, trace_every,
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+            return out.view(np.int64).reshape(len(self.specs), P)
+        _check(lib.qz_batch_run(self._h, n, 0, None))
+        return None
+
+    def replace(self, slot: int, L: int, seed: int, t_max: int = 0) -> None:
+        """Put a new replica (side L up to the slot's original side) into a slot."""
+        spec = _spec((L, seed, t_max))
+        _check(lib.qz_batch_slot_replace(self._h, slot, ctypes.byref(spec)))
+        self.specs[slot] = (int(L), int(seed))
+
+    def tuning(self) -> dict:
+        """The launch shape in use: {"source", "graph_sweeps", "tz": {L: Tz}}."""
+        import json
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib.qz_batch_tuning_json(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def sync(self) -> None:
         _check(lib.qz_batch_sync(self._h))

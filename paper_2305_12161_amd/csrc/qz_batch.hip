@@ -46,7 +46,8 @@ __device__ __forceinline__ void batch_body(const BatchArgs &A)
     if (sub < S && G.first + sub < G.last) {
         T = A.tiles[G.first + sub];
         R = A.reps[T.slot];
-        act = R.active != 0u;
+        // a replica that has reached its t_max is skipped like a parked one
+        act = R.active != 0u && (R.t_max == 0u || R.t + A.step < R.t_max);
     }
     const uint64_t t64 = act ? R.t + A.step : 0;
     const uint32_t t = (uint32_t)t64;
@@ -255,14 +256,26 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_sweep(BatchArgs A)
     }
 }
 
-// After a group of k sweeps: every active replica's time advances by k and
-// its current copy flips k times; traced slots of the next group are cleared.
+// Sweeps of a group of k that replica r runs: all k, or those left before
+// its t_max.
+__device__ __forceinline__ uint32_t batch_steps(const BatchReplica &r, uint32_t k)
+{
+    if (!r.active)
+        return 0u;
+    if (r.t_max == 0u)
+        return k;
+    return r.t >= r.t_max ? 0u : (uint32_t)min((uint64_t)k, r.t_max - r.t);
+}
+
+// After a group of k sweeps: every active replica's time advances by the
+// sweeps it ran and its current copy flips as often.
 __global__ void k_batch_advance(BatchReplica *reps, uint32_t n, uint32_t k)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && reps[i].active) {
-        reps[i].t += k;
-        reps[i].cur ^= (k & 1u);
+    if (i < n) {
+        const uint32_t m = batch_steps(reps[i], k);
+        reps[i].t += m;
+        reps[i].cur ^= (m & 1u);
     }
 }
 
@@ -272,10 +285,11 @@ __global__ void k_batch_clear_trace(BatchReplica *reps, uint32_t n, uint32_t spa
                                     uint32_t cap)
 {
     const uint32_t i = blockIdx.x;
-    if (i >= n || !reps[i].active || reps[i].trace == nullptr)
+    if (i >= n || reps[i].trace == nullptr)
         return;
     const uint64_t t0 = reps[i].t;
-    for (uint32_t d = threadIdx.x; d < span; d += blockDim.x) {
+    const uint32_t m = batch_steps(reps[i], span);
+    for (uint32_t d = threadIdx.x; d < m; d += blockDim.x) {
         const uint64_t t = t0 + d;
         if (t % every == 0u)
             reps[i].trace[(t / every) % cap] = 0ull;

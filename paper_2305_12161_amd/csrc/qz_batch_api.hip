@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <map>
+#include <set>
 #include <new>
 #include <string>
 #include <vector>
@@ -25,6 +26,7 @@ struct qz_batch {
     size_t bytes;
     uint32_t every, cap;
     std::vector<qz_replica_spec> specs;
+    std::vector<uint32_t> cap_L;             // side each slot's memory was sized for
     std::vector<qz::BatchReplica> host_reps;  // mirror of the device table
     qz::BatchReplica *d_reps;
     qz::BatchTile *d_tiles;
@@ -40,6 +42,7 @@ struct qz_batch {
     uint32_t graph_sweeps;
     hipGraphExec_t graph;
     bool graph_ok;
+    std::string tune_source;                 // "json", "autotune" or "set"
     bool failed;
     bool dirty;                              // host table newer than the device copy
 };
@@ -72,6 +75,9 @@ int dev_fail(qz_batch *b, hipError_t e, const char *where)
 // to fill the chip (measured on MI355X: Tz = 8 for every size of the 584-
 // replica batch runs 2.1x faster than 16 / 16 / 32).
 uint32_t default_tz(uint32_t L) { return L % 8 == 0 ? 8u : 1u; }
+
+// Sweeps per captured graph unless the tuning says otherwise.
+constexpr uint32_t kDefaultGraphSweeps = 100;
 
 struct Layout {
     std::vector<size_t> rep_off;
@@ -274,6 +280,193 @@ uint32_t *slot_plane(qz_batch *b, size_t slot, int copy, int colour)
     return r.base + (size_t)(2 * copy + colour) * (nsites(L) / 64);
 }
 
+// ---- tuning text: {"graph_sweeps": G, "tz": {"64": 8, "128": 8, ...}} ----
+// Both keys are optional; unknown keys are an error, so that a misspelt key
+// is not silently ignored.
+struct JsonIn {
+    const char *p;
+    void ws()
+    {
+        while (*p == ' ' || *p == '\n' || *p == '\t' || *p == '\r')
+            ++p;
+    }
+    bool lit(char c)
+    {
+        ws();
+        if (*p != c)
+            return false;
+        ++p;
+        return true;
+    }
+    bool str(std::string *out)
+    {
+        ws();
+        if (*p != '"')
+            return false;
+        const char *q = ++p;
+        while (*p && *p != '"')
+            ++p;
+        if (*p != '"')
+            return false;
+        out->assign(q, p);
+        ++p;
+        return true;
+    }
+    bool num(uint64_t *out)
+    {
+        ws();
+        if (*p < '0' || *p > '9')
+            return false;
+        uint64_t v = 0;
+        while (*p >= '0' && *p <= '9') {
+            v = v * 10 + (uint64_t)(*p - '0');
+            if (v > 0xFFFFFFFFull)
+                return false;
+            ++p;
+        }
+        *out = v;
+        return true;
+    }
+};
+
+bool parse_tuning(const char *text, std::map<uint32_t, uint32_t> *tz, uint32_t *graph_sweeps,
+                  bool *has_graph)
+{
+    JsonIn in{text};
+    *has_graph = false;
+    if (!in.lit('{'))
+        return false;
+    if (in.lit('}'))
+        return (in.ws(), *in.p == '\0');
+    do {
+        std::string key;
+        if (!in.str(&key) || !in.lit(':'))
+            return false;
+        if (key == "graph_sweeps") {
+            uint64_t v;
+            if (!in.num(&v))
+                return false;
+            *graph_sweeps = (uint32_t)v;
+            *has_graph = true;
+        } else if (key == "tz") {
+            if (!in.lit('{'))
+                return false;
+            if (!in.lit('}')) {
+                do {
+                    std::string ks;
+                    uint64_t v;
+                    if (!in.str(&ks) || ks.empty() || ks.size() > 9 || !in.lit(':') || !in.num(&v))
+                        return false;
+                    for (char c : ks)
+                        if (c < '0' || c > '9')
+                            return false;
+                    (*tz)[(uint32_t)std::stoul(ks)] = (uint32_t)v;
+                } while (in.lit(','));
+                if (!in.lit('}'))
+                    return false;
+            }
+        } else {
+            return false;
+        }
+    } while (in.lit(','));
+    if (!in.lit('}'))
+        return false;
+    in.ws();
+    return *in.p == '\0';
+}
+
+std::string tuning_text(const qz_batch *b)
+{
+    std::set<uint32_t> Ls;
+    for (const auto &sp : b->specs)
+        Ls.insert(sp.L);
+    std::string o = "{\"source\": \"" + b->tune_source +
+                    "\", \"graph_sweeps\": " + std::to_string(b->graph_sweeps) + ", \"tz\": {";
+    bool first = true;
+    for (uint32_t L : Ls) {
+        auto it = b->tz.find(L);
+        const uint32_t v = it != b->tz.end() ? it->second : default_tz(L);
+        o += (first ? "\"" : ", \"") + std::to_string(L) + "\": " + std::to_string(v);
+        first = false;
+    }
+    return o + "}}";
+}
+
+// Autotune: for each side L in the batch, in turn, time whole-batch sweeps
+// with each plane count per sub-tile that divides L and keep the fastest
+// (the others held at their current choice).  The sweeps run on the drawn
+// starts, which are drawn again afterwards: results never depend on this.
+int autotune(qz_batch *b)
+{
+    std::set<uint32_t> Ls;
+    for (const auto &sp : b->specs)
+        Ls.insert(sp.L);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BZ_HIP(b, hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return dev_fail(b, e, "hipEventCreate");
+    }
+    int rc = QZ_OK;
+    const uint32_t warm = 2, timed = 8;
+    auto time_batch = [&](float *ms) -> int {
+        hipError_t x = enqueue_group(b, b->st, warm);
+        if (x == hipSuccess)
+            x = hipEventRecord(e0, b->st);
+        for (uint32_t k = 0; x == hipSuccess && k < timed; ++k)
+            x = enqueue_group(b, b->st, 1);
+        if (x == hipSuccess)
+            x = hipEventRecord(e1, b->st);
+        if (x == hipSuccess)
+            x = hipEventSynchronize(e1);
+        if (x == hipSuccess)
+            x = hipEventElapsedTime(ms, e0, e1);
+        return x == hipSuccess ? QZ_OK : dev_fail(b, x, "autotune timing");
+    };
+    for (uint32_t L : Ls) {
+        uint32_t best = default_tz(L);
+        float best_ms = 0.0f;
+        bool have = false;
+        for (uint32_t tz : {2u, 4u, 8u, 16u, 32u}) {
+            if (L % tz)
+                continue;
+            b->tz[L] = tz;
+            if ((rc = build_tables(b)) != QZ_OK)
+                break;
+            float ms = 0.0f;
+            if ((rc = time_batch(&ms)) != QZ_OK)
+                break;
+            if (!have || ms < best_ms) {
+                best = tz;
+                best_ms = ms;
+                have = true;
+            }
+        }
+        if (rc != QZ_OK)
+            break;
+        b->tz[L] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == QZ_OK)
+        rc = build_tables(b);
+    return rc;
+}
+
+// Draw every slot's start and set its time to 0.
+int draw_starts(qz_batch *b)
+{
+    for (size_t i = 0; i < b->specs.size(); ++i) {
+        qz::BatchReplica &r = b->host_reps[i];
+        r.t = 0;
+        r.cur = 0;
+        BZ_HIP(b, qz::bit_init(b->st, b->specs[i].L, b->specs[i].seed, slot_plane(b, i, 0, 0),
+                               slot_plane(b, i, 0, 1)));
+    }
+    return push_reps(b);
+}
+
 }  // namespace
 
 QZ_EXPORT size_t qz_batch_state_bytes(const qz_replica_spec *specs, size_t n, uint32_t trace_cap)
@@ -286,7 +479,7 @@ QZ_EXPORT size_t qz_batch_state_bytes(const qz_replica_spec *specs, size_t n, ui
 
 QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t trace_every,
                               uint32_t trace_cap, void *dev_mem, size_t dev_bytes,
-                              void *hip_stream, qz_batch **out)
+                              void *hip_stream, const char *tuning_json, qz_batch **out)
 {
     if (!out)
         return fail(QZ_EINVAL, "null output pointer");
@@ -300,6 +493,17 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
             return fail(QZ_EUNSUPPORTED, "batched replicas need L % 64 == 0 and L <= 256");
     if (!dev_mem || (reinterpret_cast<uintptr_t>(dev_mem) & 255u))
         return fail(QZ_EINVAL, "device buffer must be non-null and 256-byte aligned");
+    std::map<uint32_t, uint32_t> tz_in;
+    uint32_t graph_in = 0;
+    bool has_graph = false;
+    if (tuning_json) {
+        if (!parse_tuning(tuning_json, &tz_in, &graph_in, &has_graph))
+            return fail(QZ_EINVAL, "tuning_json is not of the form "
+                                   "{\"graph_sweeps\": G, \"tz\": {\"L\": Tz, ...}}");
+        for (const auto &kv : tz_in)
+            if (!qz::batch_size_ok(kv.first) || kv.second == 0 || kv.first % kv.second)
+                return fail(QZ_EINVAL, "tuning_json: each Tz must divide its L");
+    }
     Layout lay;
     plan(specs, n, trace_cap, &lay);
     if (dev_bytes < lay.total)
@@ -314,6 +518,9 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
     b->every = trace_every;
     b->cap = trace_every ? trace_cap : 1;
     b->specs.assign(specs, specs + n);
+    b->cap_L.resize(n);
+    for (size_t i = 0; i < n; ++i)
+        b->cap_L[i] = specs[i].L;
     b->d_reps = reinterpret_cast<qz::BatchReplica *>(b->base + lay.reps_off);
     b->d_tiles = reinterpret_cast<qz::BatchTile *>(b->base + lay.tiles_off);
     b->d_groups = reinterpret_cast<qz::BatchGroup *>(b->base + lay.groups_off);
@@ -323,9 +530,12 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
     b->stage_bytes = lay.stage_bytes;
     b->counters = reinterpret_cast<unsigned long long *>(b->base + lay.counters_off);
     b->corr = reinterpret_cast<unsigned long long *>(b->base + lay.corr_off);
-    b->graph_sweeps = std::min<uint32_t>(16u, group_limit(b));
+    b->graph_sweeps = std::min<uint32_t>(has_graph ? graph_in : kDefaultGraphSweeps,
+                                         group_limit(b));
     b->graph_ok = false;
     b->failed = false;
+    b->tz = tz_in;
+    b->tune_source = tuning_json ? "json" : "autotune";
     b->host_reps.resize(n);
     unsigned long long *traces = reinterpret_cast<unsigned long long *>(b->base + lay.trace_off);
     for (size_t i = 0; i < n; ++i) {
@@ -334,6 +544,7 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
         r.trace = trace_every ? traces + i * (size_t)trace_cap : nullptr;
         r.seed = specs[i].seed;
         r.t = 0;
+        r.t_max = specs[i].t_max;
         r.cur = 0;
         r.active = 1;
     }
@@ -345,12 +556,13 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
     }
     int rc = build_tables(b);
     if (rc == QZ_OK)
-        rc = push_reps(b);
-    for (size_t i = 0; rc == QZ_OK && i < n; ++i) {
-        e = qz::bit_init(b->st, specs[i].L, specs[i].seed, slot_plane(b, i, 0, 0),
-                         slot_plane(b, i, 0, 1));
-        if (e != hipSuccess)
-            rc = dev_fail(b, e, "init kernel");
+        rc = draw_starts(b);
+    if (rc == QZ_OK && !tuning_json) {
+        // no tuning given: time the candidates on the drawn starts, then draw
+        // the starts again
+        rc = autotune(b);
+        if (rc == QZ_OK)
+            rc = draw_starts(b);
     }
     if (rc != QZ_OK) {
         (void)hipStreamDestroy(b->cap_st);
@@ -383,15 +595,17 @@ QZ_EXPORT int qz_batch_set_tuning(qz_batch *b, uint32_t L, uint32_t Tz, uint32_t
         b->tz[L] = Tz;
     }
     b->graph_sweeps = std::min<uint32_t>(graph_sweeps, group_limit(b));
+    b->tune_source = "set";
     drop_graph(b);
     return build_tables(b);
 }
 
-QZ_EXPORT int qz_batch_run(qz_batch *b, uint64_t n_sweeps)
+namespace {
+// Advance every active slot by n sweeps (asynchronous): graph replays of
+// graph_sweeps sweeps, then the rest as one or more plain groups.
+int run_sweeps(qz_batch *b, uint64_t n_sweeps)
 {
-    int rc = check(b);
-    if (rc != QZ_OK)
-        return rc;
+    int rc;
     if (b->dirty) {
         rc = push_reps(b);
         if (rc != QZ_OK)
@@ -413,6 +627,58 @@ QZ_EXPORT int qz_batch_run(qz_batch *b, uint64_t n_sweeps)
         left -= k;
     }
     return QZ_OK;
+}
+}  // namespace
+
+QZ_EXPORT int qz_batch_run(qz_batch *b, uint64_t n_sweeps, uint64_t trace_every,
+                           uint64_t *host_traces)
+{
+    int rc = check(b);
+    if (rc != QZ_OK)
+        return rc;
+    if (trace_every == 0 || host_traces == nullptr)
+        return run_sweeps(b, n_sweeps);
+    if (b->every == 0 || trace_every != b->every)
+        return fail(QZ_EINVAL, "trace_every must equal the batch's trace_every");
+    const size_t n = b->specs.size();
+    const uint64_t every = b->every;
+    const uint64_t P = (n_sweeps + every - 1) / every;     // entries per slot
+    for (size_t i = 0; i < n * P; ++i)
+        host_traces[i] = ~0ull;
+    if ((rc = pull_reps(b)) != QZ_OK)
+        return rc;
+    // per slot: first traced time tau at or after t0, and where the run ends
+    std::vector<uint64_t> t0(n), tau(n), t_end(n);
+    for (size_t i = 0; i < n; ++i) {
+        const qz::BatchReplica &r = b->host_reps[i];
+        uint64_t m = r.active ? n_sweeps : 0;
+        if (r.t_max > 0)
+            m = r.t >= r.t_max ? 0 : std::min<uint64_t>(m, r.t_max - r.t);
+        t0[i] = r.t;
+        tau[i] = (r.t + every - 1) / every * every;
+        t_end[i] = r.t + m;
+    }
+    // pieces of at most cap * every sweeps, so that no ring entry of a piece
+    // is overwritten before it is read
+    const uint64_t piece = (uint64_t)b->cap * every;
+    std::vector<unsigned long long> ring((size_t)b->cap * n);
+    unsigned long long *d_ring = b->host_reps[0].trace;   // the slots' rings are contiguous
+    for (uint64_t done = 0; done < n_sweeps;) {
+        const uint64_t m = std::min<uint64_t>(piece, n_sweeps - done);
+        if ((rc = run_sweeps(b, m)) != QZ_OK)
+            return rc;
+        BZ_HIP(b, hipMemcpyAsync(ring.data(), d_ring, ring.size() * 8, hipMemcpyDeviceToHost,
+                                 b->st));
+        BZ_HIP(b, hipStreamSynchronize(b->st));
+        for (size_t i = 0; i < n; ++i) {
+            const uint64_t a = std::max(tau[i], t0[i] + done);
+            const uint64_t z = std::min(t_end[i], t0[i] + done + m);
+            for (uint64_t t = (a + every - 1) / every * every; t < z; t += every)
+                host_traces[i * P + (t - tau[i]) / every] = ring[i * b->cap + (t / every) % b->cap];
+        }
+        done += m;
+    }
+    return pull_reps(b);
 }
 
 QZ_EXPORT int qz_batch_sync(qz_batch *b)
@@ -455,6 +721,50 @@ QZ_EXPORT int qz_batch_slot_reset(qz_batch *b, size_t slot, uint64_t seed)
     BZ_HIP(b, qz::bit_init(b->st, b->specs[slot].L, seed, slot_plane(b, slot, 0, 0),
                            slot_plane(b, slot, 0, 1)));
     return push_reps(b);
+}
+
+QZ_EXPORT int qz_batch_slot_replace(qz_batch *b, size_t slot, const qz_replica_spec *spec)
+{
+    int rc = check_slot(b, slot);
+    if (rc != QZ_OK)
+        return rc;
+    if (!spec)
+        return fail(QZ_EINVAL, "null replica spec");
+    if (!qz::batch_size_ok(spec->L))
+        return fail(QZ_EUNSUPPORTED, "batched replicas need L % 64 == 0 and L <= 256");
+    if (spec->L > b->cap_L[slot])
+        return fail(QZ_EINVAL, "the slot's memory was sized for a smaller L");
+    rc = pull_reps(b);
+    if (rc != QZ_OK)
+        return rc;
+    const bool new_L = spec->L != b->specs[slot].L;
+    b->specs[slot] = *spec;
+    qz::BatchReplica &r = b->host_reps[slot];
+    r.seed = spec->seed;
+    r.t = 0;
+    r.t_max = spec->t_max;
+    r.cur = 0;
+    r.active = 1;
+    if (new_L) {
+        // the launch's tiles and groups follow the slots' sides
+        drop_graph(b);
+        if ((rc = build_tables(b)) != QZ_OK)
+            return rc;
+    }
+    BZ_HIP(b, qz::bit_init(b->st, spec->L, spec->seed, slot_plane(b, slot, 0, 0),
+                           slot_plane(b, slot, 0, 1)));
+    return push_reps(b);
+}
+
+QZ_EXPORT int qz_batch_tuning_json(const qz_batch *b, char *buf, size_t len)
+{
+    if (!b || !buf)
+        return fail(QZ_EINVAL, "null argument");
+    const std::string t = tuning_text(b);
+    if (t.size() + 1 > len)
+        return fail(QZ_EINVAL, "buffer too small for the tuning text");
+    memcpy(buf, t.c_str(), t.size() + 1);
+    return QZ_OK;
 }
 
 QZ_EXPORT int qz_batch_slot_active(qz_batch *b, size_t slot, int active)

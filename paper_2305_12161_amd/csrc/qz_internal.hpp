@@ -135,6 +135,7 @@ struct BatchReplica {
     unsigned long long *trace;      // bond-count ring (cap slots), or null
     uint64_t seed;
     uint64_t t;                     // time at the start of the current group of sweeps
+    uint64_t t_max;                 // the replica stops at this time (0: never)
     uint32_t cur;                   // copy holding the state at time t
     uint32_t active;                // 0: skipped by the sweeps
 };

@@ -57,6 +57,8 @@ class GpuBackend:
                  single_streams: int = 8, single_pass: int = 2):
         import torch
         from . import binding
+        if every <= 0 or chunk <= 0 or chunk % every:
+            raise ValueError("chunk must be a positive multiple of every")
         self.qz = binding
         self.torch = torch
         self.every, self.chunk = every, chunk
@@ -79,9 +81,18 @@ class GpuBackend:
         if specs:
             cap = t_max_cap // every + 2
             self.batch_bytes = binding.batch_state_bytes(specs, cap)
+            # the autotuner's stored launch shape with one graph per chunk, or,
+            # for sizes never tuned, the library's own autotune at creation
+            import json
+            from . import tune
+            gs = chunk if graph_sweeps is None else graph_sweeps
+            tuning = tune.batch_tuning_json(sorted(batch_slots))
+            if tuning is not None:
+                tuning = dict(json.loads(tuning), graph_sweeps=gs)
             self.batch = binding.Batch(specs, trace_every=every, trace_cap=cap, device=self.device,
-                                       stream=self.stream)
-            self.batch.set_tuning(64, 0, chunk if graph_sweeps is None else graph_sweeps)
+                                       stream=self.stream, tuning=tuning)
+            if tuning is None:
+                self.batch.set_tuning(min(batch_slots), 0, gs)
             for slot, (L, _) in enumerate(specs):
                 self.batch.set_active(slot, False)
                 self.free_batch[L].append(slot)
@@ -106,9 +117,12 @@ class GpuBackend:
         return self.single_used + self.single_bytes(L) <= self.single_budget
 
     def admit(self, req) -> None:
+        if req.t_max % self.chunk:
+            raise ValueError("t_max must be a multiple of the chunk")
         if self.batch is not None and self.free_batch.get(req.L):
             slot = self.free_batch[req.L].pop()
-            self.batch.reset(slot, req.seed)
+            # the slot stops by itself at t_max, on the device
+            self.batch.replace(slot, req.L, req.seed, req.t_max)
             self.live[req.idx] = {"kind": "batch", "slot": slot, "t": 0, "t_max": req.t_max}
             return
         st = self.single_streams[self._next_stream % len(self.single_streams)] \

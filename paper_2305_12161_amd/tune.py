@@ -47,6 +47,17 @@ def best_batch(L: int):
     return (v["Tz"], v["graph_sweeps"]) if v else None
 
 
+def batch_tuning_json(sizes):
+    """The stored batch winners for every side in `sizes` as the library's
+    tuning text, or None (the library then autotunes) if a side was never
+    tuned."""
+    d = _load()["batch"]
+    if not sizes or any(str(L) not in d for L in sizes):
+        return None
+    graph = min(int(d[str(L)]["graph_sweeps"]) for L in sizes)
+    return json.dumps({"graph_sweeps": graph, "tz": {str(L): int(d[str(L)]["Tz"]) for L in sizes}})
+
+
 def single_candidates(L: int):
     W = L // 64
     out = []
@@ -147,45 +158,37 @@ def tune_batch(specs, sweeps: int = 200, verbose: bool = True):
     sizes = sorted({L for L, _ in specs})
     chosen = {L: None for L in sizes}
     results = {}
-    for L in sizes:
-        for Tz in (2, 4, 8, 16, 32):
-            if Tz > L or L % Tz:
-                continue
-            b = binding.Batch(specs)
-            for L2 in sizes:
-                if chosen[L2]:
-                    b.set_tuning(L2, chosen[L2], 50)
-            b.set_tuning(L, Tz, 50)
-            b.run(50)
-            b.sync()
-            t0 = time.perf_counter()
-            b.run(sweeps)
-            b.sync()
-            ms = (time.perf_counter() - t0) * 1e3 / sweeps
-            if verbose:
-                print(json.dumps({"L": L, "Tz": Tz, "ms_per_sweep": round(ms, 5)}), flush=True)
-            if L not in results or ms < results[L][1]:
-                results[L] = (Tz, ms)
-            del b
-            torch.cuda.empty_cache()
-        chosen[L] = results[L][0]
-    best_graph = None
-    for gs in (10, 25, 50, 100, 200):
-        b = binding.Batch(specs)
-        for L in sizes:
-            b.set_tuning(L, chosen[L], gs)
-        b.run(gs)
+
+    def time_batch(tz, graph):
+        b = binding.Batch(specs, tuning={"graph_sweeps": graph,
+                                         "tz": {str(L): v for L, v in tz.items() if v}})
+        b.run(graph)
         b.sync()
         t0 = time.perf_counter()
         b.run(sweeps)
         b.sync()
         ms = (time.perf_counter() - t0) * 1e3 / sweeps
+        del b
+        torch.cuda.empty_cache()
+        return ms
+
+    for L in sizes:
+        for Tz in (2, 4, 8, 16, 32):
+            if Tz > L or L % Tz:
+                continue
+            ms = time_batch({**chosen, L: Tz}, 50)
+            if verbose:
+                print(json.dumps({"L": L, "Tz": Tz, "ms_per_sweep": round(ms, 5)}), flush=True)
+            if L not in results or ms < results[L][1]:
+                results[L] = (Tz, ms)
+        chosen[L] = results[L][0]
+    best_graph = None
+    for gs in (10, 25, 50, 100, 200):
+        ms = time_batch(chosen, gs)
         if verbose:
             print(json.dumps({"graph_sweeps": gs, "ms_per_sweep": round(ms, 5)}), flush=True)
         if best_graph is None or ms < best_graph[1]:
             best_graph = (gs, ms)
-        del b
-        torch.cuda.empty_cache()
     d = _load()
     for L in sizes:
         d["batch"][str(L)] = {"Tz": chosen[L], "graph_sweeps": best_graph[0]}
@@ -197,7 +200,12 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--L", type=int, nargs="*", default=[])
     ap.add_argument("--batch-config4", action="store_true")
+    ap.add_argument("--out", type=str, default="",
+                    help="write the winners to this file instead of tuned.json next to tune.py")
     args = ap.parse_args()
+    if args.out:
+        global CACHE
+        CACHE = os.path.abspath(args.out)
     for L in args.L:
         print(json.dumps({"L": L, "best_one_sweep": tune_single(L)}), flush=True)
         print(json.dumps({"L": L, "best_two_sweep": tune_pass2(L)}), flush=True)

@@ -27,9 +27,44 @@ def lib():
 
 def test_header_declares_expected_calls():
     names = declared_functions()
-    for need in ("qz_create", "qz_run", "qz_bonds", "qz_corr", "qz_destroy", "qz_state_bytes",
-                 "qz_download_spins", "qz_upload_spins", "qz_download_window", "qz_last_error"):
+    # the single-lattice and batch calls of the boundary
+    for need in ("qz_create", "qz_run", "qz_bonds", "qz_corr", "qz_time", "qz_destroy",
+                 "qz_state_bytes", "qz_download_spins", "qz_upload_spins", "qz_download_window",
+                 "qz_status_string", "qz_last_error", "qz_batch_state_bytes", "qz_batch_create",
+                 "qz_batch_run", "qz_batch_slot_replace", "qz_batch_destroy"):
         assert need in names
+
+
+class _Spec(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("t_max", ctypes.c_uint64)]
+
+
+def test_batch_rejects_bad_arguments_without_device(lib):
+    """Batch creation checks sizes, memory and the tuning text before any
+    device work: a well-formed text gets as far as the memory check."""
+    lib.qz_batch_state_bytes.restype = ctypes.c_size_t
+    lib.qz_batch_state_bytes.argtypes = [ctypes.POINTER(_Spec), ctypes.c_size_t, ctypes.c_uint32]
+    lib.qz_batch_create.restype = ctypes.c_int
+    lib.qz_batch_create.argtypes = [ctypes.POINTER(_Spec), ctypes.c_size_t, ctypes.c_uint32,
+                                    ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_void_p, ctypes.c_char_p,
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    specs = (_Spec * 3)(_Spec(64, 1, 0), _Spec(128, 2, 1000), _Spec(256, 3, 0))
+    need = lib.qz_batch_state_bytes(specs, 3, 16)
+    assert need >= 2 * (64 ** 3 + 128 ** 3 + 256 ** 3) // 8
+    bad = (_Spec * 1)(_Spec(96, 1, 0))
+    assert lib.qz_batch_state_bytes(bad, 1, 16) == 0
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: every call below fails first
+    args = (specs, 3, 4, 16, fake)
+    assert lib.qz_batch_create(bad, 1, 4, 16, fake, 1 << 30, None, None, ctypes.byref(h)) == -5
+    assert lib.qz_batch_create(specs, 3, 4, 0, fake, 1 << 30, None, None, ctypes.byref(h)) == -1
+    for text in (b"", b"{", b'{"tz": {"64": 3}}', b'{"tz": {"96": 8}}', b'{"graph": 5}',
+                 b'{"graph_sweeps": -1}', b'{"tz": {"64": 8}} x', b'{"tz": [8]}'):
+        assert lib.qz_batch_create(*args, 1 << 30, None, text, ctypes.byref(h)) == -1, text
+    for text in (None, b"{}", b'{"graph_sweeps": 100, "tz": {"64": 8, "128": 16, "256": 4}}',
+                 b' { "tz" : { } , "graph_sweeps" : 0 } '):
+        assert lib.qz_batch_create(*args, need - 1, None, text, ctypes.byref(h)) == -2, text
 
 
 def test_library_exports_every_declared_symbol(lib):
@@ -39,7 +74,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_abi_version_and_sizes(lib):
     lib.qz_abi_version.restype = ctypes.c_int
-    assert lib.qz_abi_version() == 1
+    assert lib.qz_abi_version() == 2
     lib.qz_state_bytes.restype = ctypes.c_size_t
     lib.qz_state_bytes.argtypes = [ctypes.c_uint32, ctypes.c_int]
     # int8: N bytes of spins; bit: two copies of N/8 bytes

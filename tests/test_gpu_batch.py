@@ -157,3 +157,93 @@ def test_batch_rejects_bad_sizes(qz):
     b = qz.Batch([(64, 1)])
     with pytest.raises(qz.QuenchError):
         b.set_tuning(64, 3, 5)       # Tz must divide L
+
+
+# --------------------------------------------------------------------------
+# the batch boundary: traces returned by the run, t_max, slot replacement,
+# the tuning text and the library's own autotune
+# --------------------------------------------------------------------------
+def test_batch_run_returns_traces_and_stops_at_t_max(qz):
+    """qz_batch_run's host trace: entry i of a slot is B(tau + i * every); a
+    slot with t_max stops there on the device (even inside a graph), and
+    its later entries read -1."""
+    every = 3
+    specs = [(64, 31, 0), (128, 32, 20), (192, 33, 9), (256, 34, 0), (64, 35, 1)]
+    b = qz.Batch(specs, trace_every=every, trace_cap=8, tuning={"graph_sweeps": 6})
+    print("batch trace run, tuning", b.tuning(), flush=True)
+    n1, n2 = 12, 17
+    tr1 = b.run(n1, every)
+    tr2 = b.run(n2, every)
+    assert tr1.shape == (5, 4) and tr2.shape == (5, 6)
+    for slot, (L, seed, t_max) in enumerate(specs):
+        end = t_max if t_max else n1 + n2
+        assert b.time(slot) == end, slot
+        ref = qz.Lattice(L, seed, "bit")
+        full = ref.run(30, 1)                     # B(0) .. B(29)
+        # the first run starts at t = 0, the second at t = 12
+        for tr, t0, n in ((tr1, 0, n1), (tr2, n1, n2)):
+            tau = -(-t0 // every) * every
+            for i in range(tr.shape[1]):
+                t = tau + i * every
+                want = int(full[t]) if (t < t0 + n and t < end) else -1
+                assert int(tr[slot, i]) == want, (slot, t)
+        lat = qz.Lattice(L, seed, "bit")
+        lat.run(end)
+        assert np.array_equal(b.download(slot), lat.download()), slot
+
+
+def test_batch_slot_replace(qz):
+    """A slot takes a new replica of any side up to the one it was created
+    with; the new replica follows its lone trajectory, and the others are
+    unaffected (the launch's tiles are rebuilt when a side changes)."""
+    specs = [(256, 41), (128, 42), (64, 43)]
+    b = qz.Batch(specs, trace_every=2, trace_cap=16, tuning={"graph_sweeps": 4})
+    b.run(8)
+    b.replace(0, 64, 77, 10)           # a 256 slot now holds an L = 64 replica, t_max 10
+    b.replace(2, 64, 78)               # same side, new seed
+    with pytest.raises(qz.QuenchError):
+        b.replace(1, 256, 79)          # larger than the slot was sized for
+    with pytest.raises(qz.QuenchError):
+        b.replace(1, 96, 79)           # not a batch size
+    b.run(12)
+    b.sync()
+    assert [b.time(k) for k in range(3)] == [10, 20, 12]
+    for slot, (L, seed, n) in enumerate(((64, 77, 10), (128, 42, 20), (64, 78, 12))):
+        lat = qz.Lattice(L, seed, "bit")
+        tr = lat.run(n, 2)
+        first = 8 if slot == 1 else 0
+        assert np.array_equal(b.trace(slot, first, (n - first) // 2), tr[first // 2:]), slot
+        assert np.array_equal(b.download(slot), lat.download()), slot
+    # back to the full side
+    b.replace(0, 256, 80)
+    b.run(4)
+    lat = qz.Lattice(256, 80, "bit")
+    lat.run(4)
+    assert np.array_equal(b.download(0), lat.download())
+
+
+def test_batch_autotune_and_tuning_text(qz):
+    """Without a tuning the library times candidate plane counts at creation
+    and draws the starts again; with a tuning text it uses the text.  Both
+    follow the lone trajectories."""
+    specs = [(64, 51), (128, 52), (256, 53), (192, 54)]
+    auto = qz.Batch(specs, trace_every=2, trace_cap=16, tuning=None)
+    given = qz.Batch(specs, trace_every=2, trace_cap=16,
+                     tuning='{"graph_sweeps": 5, "tz": {"64": 4, "256": 16}}')
+    ta, tg = auto.tuning(), given.tuning()
+    print("autotuned", ta, "given", tg, flush=True)
+    assert ta["source"] == "autotune" and tg["source"] == "json"
+    assert tg["graph_sweeps"] == 5
+    assert tg["tz"] == {"64": 4, "128": 8, "192": 8, "256": 16}
+    for L, tz in ta["tz"].items():
+        assert int(L) % tz == 0
+    for b in (auto, given):
+        assert [b.time(k) for k in range(4)] == [0, 0, 0, 0]
+        b.run(10)
+        b.sync()
+    for slot, (L, seed) in enumerate(specs):
+        lat = qz.Lattice(L, seed, "bit")
+        tr = lat.run(10, 2)
+        for b in (auto, given):
+            assert np.array_equal(b.trace(slot, 0, 5), tr), slot
+            assert np.array_equal(b.download(slot), lat.download()), slot

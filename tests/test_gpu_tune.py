@@ -50,10 +50,15 @@ def test_tune_batch(qz, tune):
     assert set(chosen) == {64, 128} and ms > 0
     for L, Tz in chosen.items():
         assert L % Tz == 0 and tune.best_batch(L) == (Tz, graph)
-    ref = qz.Batch(specs, trace_every=4, trace_cap=8)
-    b = qz.Batch(specs, trace_every=4, trace_cap=8)
-    for L, Tz in chosen.items():
-        b.set_tuning(L, Tz, graph)
+    # the stored winners reach the library through the batch's tuning text
+    text = tune.batch_tuning_json(sorted(chosen))
+    assert text is not None
+    ref = qz.Batch(specs, trace_every=4, trace_cap=8, tuning=None)     # library autotune
+    b = qz.Batch(specs, trace_every=4, trace_cap=8, tuning=text)
+    got = b.tuning()
+    assert got["source"] == "json" and got["graph_sweeps"] == min(graph, 8 * 4)
+    assert {int(k): v for k, v in got["tz"].items()} == chosen
+    assert ref.tuning()["source"] == "autotune"
     ref.run(16)
     b.run(16)
     ref.sync()
