@@ -61,6 +61,7 @@ def parse():
                          "log-spaced times of the run, as the L=2048 configuration asks")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-replica workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-request workload")
+    ap.add_argument("--no-int8", action="store_true", help="skip the int8 configurations")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the mixed-cycle, double-checkerboard and FFT measurements")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -222,6 +223,83 @@ def next_rows_workload(binding, torch, L, seed):
     out["fft_corr_L1024_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
     del f
     torch.cuda.empty_cache()
+    return out
+
+
+def int8_workloads(binding, torch, workloads):
+    """The two int8 configurations, run in full: L = 32 (seed 1, 1e3 MCS, B
+    every 10 MCS) and L = 256 (seed 2, 1e4 MCS, B and the axis correlation at
+    the 40 log-spaced times).  The sweep is two in-place launches of the
+    16-byte half-sweep kernel; its algorithmic bytes are 2N per sweep (each
+    byte read once and written once), N per launch.  Both lattices stay in the
+    on-chip caches (32 KiB, 16 MiB), so a device copy of the same footprint is
+    timed beside them."""
+    st = torch.cuda.current_stream()
+    out = {}
+
+    def copy_probe(nbytes):
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        reps = 200
+        a.record(st)
+        for _ in range(reps):
+            dst.copy_(src)
+        b.record(st)
+        torch.cuda.synchronize()
+        return 2 * nbytes * reps / (a.elapsed_time(b) * 1e6)   # GB/s (read + write)
+
+    def launch_ms(lat, n):
+        lat.run(4)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        lat.run(n)
+        b.record(st)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / (2 * n)        # two half-sweep launches per sweep
+
+    for cfg in (workloads.CONFIG1, workloads.CONFIG2):
+        L, N = cfg.L, cfg.L ** 3
+        lat = binding.Lattice(L, cfg.seed, "i8", stream=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        corr = 0.0
+        if cfg.trace_every:
+            lat.run(cfg.t_max, cfg.trace_every)
+        else:
+            for tc in cfg.corr_times:
+                lat.run(tc - lat.t)
+                torch.cuda.synchronize()
+                c0 = time.perf_counter()
+                lat.corr()
+                lat.bonds()
+                corr += time.perf_counter() - c0
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        assert lat.t == cfg.t_max
+        half_ms = launch_ms(lat, 200)
+        achieved = N / (half_ms * 1e6)              # GB/s: N bytes per half-sweep launch
+        copy_gbs = copy_probe(N)
+        out[cfg.name] = {
+            "workload": (f"L={L} int8, seed {cfg.seed}, {cfg.t_max} MCS, " +
+                         (f"B every {cfg.trace_every} MCS" if cfg.trace_every else
+                          f"B and C(r) at the {len(cfg.corr_times)} log-spaced times")),
+            "attempts_per_ns": round(N * cfg.t_max / (wall * 1e9), 2),
+            "wall_s": round(wall, 4),
+            "measurement_s": round(corr, 4),
+            "sweep_attempts_per_ns": round(N / (2 * half_ms * 1e6), 2),
+            "roofline": {"bound": "hbm", "kernel": "k_i8_half16 (one colour, in place)",
+                         "alg_bytes_per_launch": N, "avg_launch_ms": round(half_ms, 5),
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "copy_same_footprint_GBs": round(copy_gbs, 1),
+                         "frac_of_copy": round(achieved / copy_gbs, 4)},
+        }
+        del lat
     return out
 
 
@@ -498,6 +576,8 @@ def main():
     if not args.no_serve:
         rate = args.serve_rate if args.serve_rate else workloads.SERVE_RATE_PER_S
         leg("served", lambda: served_workload(binding, torch, workloads, args.serve_requests, rate))
+    if not args.no_int8:
+        leg("int8", lambda: int8_workloads(binding, torch, workloads))
     if not args.no_next:
         leg("next_rows", lambda: next_rows_workload(binding, torch, L, seed))
     if not args.no_cpu_baseline:

@@ -56,29 +56,35 @@ __global__ void __launch_bounds__(kThreads) k_i8_init(uint64_t N, uint32_t k0, u
     }
 }
 
-// Half-sweep number `which` (0 = first, 1 = second) of sweep t: thread per
-// colour index j (consecutive lanes hold consecutive j, so a wave shares one
-// Philox block and evaluates it once).  The colour updated is p = which in the
-// 01 cycle; in the mixed cycle the first colour is bit 0 of Philox block
-// (0, t, 2, 0) (Supplementary Methods I B: order drawn per sweep).
-__global__ void __launch_bounds__(kThreads)
-    k_i8_half(uint32_t L, uint64_t half_n, uint32_t k0, uint32_t k1, uint32_t t, uint32_t which,
-              uint32_t mixed, int8_t *s, unsigned long long *bond_acc,
-              unsigned long long *flip_acc)
+// The colour updated by half-sweep `which` (0 = first, 1 = second) of sweep
+// t: p = which in the 01 cycle; in the mixed cycle the first colour is bit 0
+// of Philox block (0, t, 2, 0) (Supplementary Methods I B: order drawn per
+// sweep).
+__device__ __forceinline__ uint32_t half_colour(uint32_t which, uint32_t mixed, uint32_t t,
+                                                uint32_t k0, uint32_t k1)
 {
     const uint32_t first = mixed ? (philox10(0u, t, 2u, 0u, k0, k1).w[0] & 1u) : 0u;
-    const uint32_t p = which ^ first;
-    const uint32_t H = L >> 1;
+    return which ^ first;
+}
+
+// Half-sweep of any even L: thread per colour site of one plane (blockIdx.y =
+// z), consecutive lanes at consecutive colour indices j, so a wave shares one
+// Philox block and evaluates it once.
+__global__ void __launch_bounds__(kThreads)
+    k_i8_half(uint32_t L, uint32_t k0, uint32_t k1, uint32_t t, uint32_t which, uint32_t mixed,
+              int8_t *s, unsigned long long *bond_acc, unsigned long long *flip_acc)
+{
+    const uint32_t p = half_colour(which, mixed, t, k0, k1);
+    const uint32_t H = L >> 1, z = blockIdx.y;
+    const uint32_t q = blockIdx.x * kThreads + threadIdx.x;   // colour site within the plane
     unsigned long long acc = 0, flips = 0;
-    for (uint64_t j = (uint64_t)blockIdx.x * kThreads + threadIdx.x; j < half_n;
-         j += (uint64_t)gridDim.x * kThreads) {
-        const uint32_t xh = (uint32_t)(j % H);
-        const uint64_t row = j / H;
-        const uint32_t y = (uint32_t)(row % L), z = (uint32_t)(row / L);
+    if (q < L * H) {
+        const uint32_t xh = q % H, y = q / H;
         const uint32_t x = 2 * xh + ((p + y + z) & 1u);
         const uint64_t LL = (uint64_t)L * L;
         const uint64_t zo = (uint64_t)z * LL, yo = (uint64_t)y * L;
         const uint64_t i = zo + yo + x;
+        const uint64_t j = (uint64_t)z * L * H + q;
         const int8_t me = s[i];
         uint32_t a = 0;
         a += s[zo + yo + wrap_up(x, L)] != me;
@@ -87,7 +93,7 @@ __global__ void __launch_bounds__(kThreads)
         a += s[zo + (uint64_t)wrap_dn(y, L) * L + x] != me;
         a += s[(uint64_t)wrap_up(z, L) * LL + yo + x] != me;
         a += s[(uint64_t)wrap_dn(z, L) * LL + yo + x] != me;
-        acc += a;
+        acc = a;
         bool flip = a >= 4;
         if (a == 3) {
             const Words4 r = philox10((uint32_t)(j >> 7), t, p, 0u, k0, k1);
@@ -95,7 +101,7 @@ __global__ void __launch_bounds__(kThreads)
         }
         if (flip) {
             s[i] = (int8_t)-me;
-            ++flips;
+            flips = 1;
         }
     }
     if (bond_acc != nullptr)
@@ -104,20 +110,116 @@ __global__ void __launch_bounds__(kThreads)
         block_add_u64(flips, flip_acc);
 }
 
-// Per-axis unsatisfied bonds: [s_i != s_{i+e_x}], [.. e_y], [.. e_z].
-__global__ void __launch_bounds__(kThreads) k_i8_bonds(uint32_t L, uint64_t N, const int8_t *s,
+// Sum of the four bytes of v (each at most 63).
+__device__ __forceinline__ uint32_t byte_sum(uint32_t v) { return (v * 0x01010101u) >> 24; }
+
+// Half-sweep for L % 16 == 0 on 16-byte chunks along x: thread per chunk of
+// one plane (blockIdx.y = z).  A site's spin becomes a bit per byte (1 where
+// it is -1); its six neighbour bits come from 16-byte loads of the rows y +-
+// 1 and planes z +- 1, and for x from the chunk itself shifted by one byte,
+// with one byte loaded at each end.  The anti-aligned count a (0..6) is then
+// a bytewise sum of six XORs, four sites per 32-bit word; a >= 4 flips, a ==
+// 3 flips on the site's tie bit.  The chunk's 8 sites of colour p have
+// consecutive colour indices j0 .. j0 + 7, i.e. one byte of one Philox
+// output word.
+__global__ void __launch_bounds__(kThreads)
+    k_i8_half16(uint32_t L, uint32_t k0, uint32_t k1, uint32_t t, uint32_t which, uint32_t mixed,
+                int8_t *s, unsigned long long *bond_acc, unsigned long long *flip_acc)
+{
+    const uint32_t p = half_colour(which, mixed, t, k0, k1);
+    const uint32_t C = L >> 4, z = blockIdx.y;
+    const uint32_t q = blockIdx.x * kThreads + threadIdx.x;   // chunk within the plane
+    uint32_t asum = 0, fsum = 0;
+    if (q < L * C) {
+        const uint32_t cx = q % C, y = q / C, x0 = cx << 4;
+        const uint64_t LL = (uint64_t)L * L;
+        const uint64_t rb = (uint64_t)z * LL + (uint64_t)y * L;
+        const uint4 vme = *reinterpret_cast<const uint4 *>(s + rb + x0);
+        const uint4 vym =
+            *reinterpret_cast<const uint4 *>(s + (uint64_t)z * LL + (uint64_t)wrap_dn(y, L) * L + x0);
+        const uint4 vyp =
+            *reinterpret_cast<const uint4 *>(s + (uint64_t)z * LL + (uint64_t)wrap_up(y, L) * L + x0);
+        const uint4 vzm =
+            *reinterpret_cast<const uint4 *>(s + (uint64_t)wrap_dn(z, L) * LL + (uint64_t)y * L + x0);
+        const uint4 vzp =
+            *reinterpret_cast<const uint4 *>(s + (uint64_t)wrap_up(z, L) * LL + (uint64_t)y * L + x0);
+        const uint32_t lbit = ((uint32_t)(uint8_t)s[rb + (x0 == 0 ? L - 1 : x0 - 1)] >> 7) & 1u;
+        const uint32_t rbit = ((uint32_t)(uint8_t)s[rb + (x0 + 16 == L ? 0 : x0 + 16)] >> 7) & 1u;
+        constexpr uint32_t kOnes = 0x01010101u;
+        const uint32_t me[4] = {vme.x, vme.y, vme.z, vme.w};
+        const uint32_t ym[4] = {vym.x, vym.y, vym.z, vym.w};
+        const uint32_t yp[4] = {vyp.x, vyp.y, vyp.z, vyp.w};
+        const uint32_t zm[4] = {vzm.x, vzm.y, vzm.z, vzm.w};
+        const uint32_t zp[4] = {vzp.x, vzp.y, vzp.z, vzp.w};
+        uint32_t u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            u[k] = (me[k] >> 7) & kOnes;
+        // bytes of colour p: those whose offset k in the chunk has the parity
+        // (p + y + z) & 1 (x0 is even); as 0x01 flags per byte
+        const uint32_t kpar = (p + y + z) & 1u;
+        const uint32_t cm = kpar ? 0x01000100u : 0x00010001u;
+        const uint64_t j0 = (uint64_t)z * L * (L >> 1) + (uint64_t)y * (L >> 1) + (x0 >> 1);
+        uint32_t ge4[4], eq3[4], ties = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t xl = (u[k] << 8) | (k == 0 ? lbit : u[k - 1] >> 24);
+            const uint32_t xr = (u[k] >> 8) | ((k == 3 ? rbit : u[k + 1]) << 24);
+            const uint32_t a = (u[k] ^ xl) + (u[k] ^ xr) + (u[k] ^ ((ym[k] >> 7) & kOnes)) +
+                               (u[k] ^ ((yp[k] >> 7) & kOnes)) + (u[k] ^ ((zm[k] >> 7) & kOnes)) +
+                               (u[k] ^ ((zp[k] >> 7) & kOnes));
+            asum += byte_sum(a & (cm * 7u));
+            ge4[k] = (a >> 2) & cm;                          // a <= 6: bit 2 set iff a >= 4
+            eq3[k] = a & (a >> 1) & ~(a >> 2) & cm;          // a == 3
+            ties |= eq3[k];
+        }
+        uint32_t r[4] = {0u, 0u, 0u, 0u};
+        if (ties) {
+            const Words4 w = philox10((uint32_t)(j0 >> 7), t, p, 0u, k0, k1);
+            const uint32_t bits = (w.w[(j0 >> 5) & 3] >> (j0 & 31)) & 0xFFu;
+            // site m (j0 + m) is byte 2m + kpar of the chunk
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                r[k] = (((bits >> (2 * k)) & 1u) << (8 * kpar)) |
+                       (((bits >> (2 * k + 1)) & 1u) << (8 * (2 + kpar)));
+        }
+        uint32_t out[4], any = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t f = ge4[k] | (eq3[k] & r[k]);
+            fsum += byte_sum(f);
+            out[k] = me[k] ^ (f * 0xFEu);                    // +1 (0x01) <-> -1 (0xFF)
+            any |= f;
+        }
+        if (any)
+            *reinterpret_cast<uint4 *>(s + rb + x0) = make_uint4(out[0], out[1], out[2], out[3]);
+    }
+    if (bond_acc != nullptr)
+        block_add_u64(asum, bond_acc);
+    if (flip_acc != nullptr)
+        block_add_u64(fsum, flip_acc);
+}
+
+// Per-axis unsatisfied bonds: [s_i != s_{i+e_x}], [.. e_y], [.. e_z]; thread
+// per column (x, y), looping over z.
+__global__ void __launch_bounds__(kThreads) k_i8_bonds(uint32_t L, const int8_t *s,
                                                        unsigned long long *acc3)
 {
     unsigned long long bx = 0, by = 0, bz = 0;
-    const uint64_t LL = (uint64_t)L * L;
-    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < N;
-         i += (uint64_t)gridDim.x * kThreads) {
-        const uint32_t x = (uint32_t)(i % L), y = (uint32_t)((i / L) % L);
-        const uint64_t z = i / LL;
-        const int8_t me = s[i];
-        bx += s[i - x + wrap_up(x, L)] != me;
-        by += s[z * LL + (uint64_t)wrap_up(y, L) * L + x] != me;
-        bz += s[(uint64_t)wrap_up((uint32_t)z, L) * LL + (uint64_t)y * L + x] != me;
+    const uint32_t col = blockIdx.x * kThreads + threadIdx.x;
+    if (col < L * L) {
+        const uint32_t x = col % L, y = col / L;
+        const uint64_t LL = (uint64_t)L * L;
+        const uint64_t ox = (uint64_t)y * L + wrap_up(x, L), oy = (uint64_t)wrap_up(y, L) * L + x;
+        int8_t nz = s[col];
+        for (uint32_t z = 0; z < L; ++z) {
+            const uint64_t zo = (uint64_t)z * LL;
+            const int8_t me = nz;
+            nz = s[(uint64_t)wrap_up(z, L) * LL + col];
+            bx += s[zo + ox] != me;
+            by += s[zo + oy] != me;
+            bz += nz != me;
+        }
     }
     block_add_u64(bx, acc3 + 0);
     block_add_u64(by, acc3 + 1);
@@ -125,28 +227,31 @@ __global__ void __launch_bounds__(kThreads) k_i8_bonds(uint32_t L, uint64_t N, c
 }
 
 // Correlation sums: blockIdx.y = a*(L/2+1) + r for the pair (axis a, shift r),
-// and blockIdx.y = 3*(L/2+1) for the magnetisation.
-__global__ void __launch_bounds__(kThreads) k_i8_corr(uint32_t L, uint64_t N, const int8_t *s,
+// and blockIdx.y = 3*(L/2+1) for the magnetisation; thread per column (x, y),
+// looping over z.
+__global__ void __launch_bounds__(kThreads) k_i8_corr(uint32_t L, const int8_t *s,
                                                       unsigned long long *S)
 {
     const uint32_t R = L / 2 + 1;
     const uint32_t q = blockIdx.y;
+    const uint32_t col = blockIdx.x * kThreads + threadIdx.x;
     const uint64_t LL = (uint64_t)L * L;
     long long acc = 0;
-    if (q == 3 * R) {
-        for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < N;
-             i += (uint64_t)gridDim.x * kThreads)
-            acc += s[i];
-    } else {
-        const uint32_t a = q / R, r = q % R;
-        for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < N;
-             i += (uint64_t)gridDim.x * kThreads) {
-            uint32_t x = (uint32_t)(i % L), y = (uint32_t)((i / L) % L);
-            uint32_t z = (uint32_t)(i / LL);
-            if (a == 0) x = (x + r) % L;
-            else if (a == 1) y = (y + r) % L;
-            else z = (z + r) % L;
-            acc += (int)s[i] * (int)s[(uint64_t)z * LL + (uint64_t)y * L + x];
+    if (col < L * L) {
+        const uint32_t x = col % L, y = col / L;
+        if (q == 3 * R) {
+            for (uint32_t z = 0; z < L; ++z)
+                acc += s[(uint64_t)z * LL + col];
+        } else {
+            const uint32_t a = q / R, r = q % R;
+            const uint32_t xs = (a == 0) ? (x + r >= L ? x + r - L : x + r) : x;
+            const uint32_t ys = (a == 1) ? (y + r >= L ? y + r - L : y + r) : y;
+            const uint64_t other = (uint64_t)ys * L + xs;
+            const uint32_t dz = (a == 2) ? r : 0u;
+            for (uint32_t z = 0; z < L; ++z) {
+                const uint32_t zs = z + dz >= L ? z + dz - L : z + dz;
+                acc += (int)s[(uint64_t)z * LL + col] * (int)s[(uint64_t)zs * LL + other];
+            }
         }
     }
     block_add_u64((unsigned long long)acc, S + q);
@@ -208,17 +313,23 @@ hipError_t i8_half_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, 
                          bool mixed, int8_t *s, unsigned long long *bond_acc,
                          unsigned long long *flip_acc)
 {
-    const uint64_t half_n = (uint64_t)L * L * L / 2;
-    hipLaunchKernelGGL(k_i8_half, dim3(grid_for(half_n, 8192)), dim3(kThreads), 0, st, L, half_n,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), t, (uint32_t)which,
-                       mixed ? 1u : 0u, s, bond_acc, flip_acc);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (L % 16 == 0) {
+        const dim3 grid((L * (L / 16) + kThreads - 1) / kThreads, L);
+        hipLaunchKernelGGL(k_i8_half16, grid, dim3(kThreads), 0, st, L, k0, k1, t,
+                           (uint32_t)which, mixed ? 1u : 0u, s, bond_acc, flip_acc);
+    } else {
+        const dim3 grid((L * (L / 2) + kThreads - 1) / kThreads, L);
+        hipLaunchKernelGGL(k_i8_half, grid, dim3(kThreads), 0, st, L, k0, k1, t, (uint32_t)which,
+                           mixed ? 1u : 0u, s, bond_acc, flip_acc);
+    }
     return hipGetLastError();
 }
 
 hipError_t i8_bonds(hipStream_t st, uint32_t L, const int8_t *s, unsigned long long *acc3)
 {
-    const uint64_t N = (uint64_t)L * L * L;
-    hipLaunchKernelGGL(k_i8_bonds, dim3(grid_for(N, 2048)), dim3(kThreads), 0, st, L, N, s, acc3);
+    hipLaunchKernelGGL(k_i8_bonds, dim3((L * L + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
+                       L, s, acc3);
     return hipGetLastError();
 }
 
@@ -226,10 +337,9 @@ hipError_t i8_corr(hipStream_t st, uint32_t L, const int8_t *s, long long *S, lo
 {
     // S and M are contiguous: M sits at S[3*(L/2+1)].
     (void)M;
-    const uint64_t N = (uint64_t)L * L * L;
     const uint32_t R = L / 2 + 1;
-    hipLaunchKernelGGL(k_i8_corr, dim3(grid_for(N, 128), 3 * R + 1), dim3(kThreads), 0, st, L, N,
-                       s, reinterpret_cast<unsigned long long *>(S));
+    hipLaunchKernelGGL(k_i8_corr, dim3((L * L + kThreads - 1) / kThreads, 3 * R + 1),
+                       dim3(kThreads), 0, st, L, s, reinterpret_cast<unsigned long long *>(S));
     return hipGetLastError();
 }
 
