@@ -18,7 +18,6 @@
 namespace qz {
 namespace {
 
-constexpr int kBatchBlock = 256;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // The body of one workgroup's sweep.  WK = words per colour row when the
@@ -297,23 +296,6 @@ __global__ void k_batch_clear_trace(BatchReplica *reps, uint32_t n, uint32_t spa
 }
 
 }  // namespace
-
-uint32_t batch_subtiles_per_block(uint32_t L)
-{
-    const uint32_t Q = L * (L / 64) / 4;
-    return Q >= (uint32_t)kBatchBlock ? 1u : (uint32_t)kBatchBlock / Q;
-}
-
-bool batch_size_ok(uint32_t L)
-{
-    if (L < 64 || L % 64)
-        return false;
-    const uint32_t PW = L * (L / 64);
-    const uint32_t Q = PW / 4;
-    if (Q > (uint32_t)kBatchBlock)
-        return false;                       // one plane per workgroup of 256 lanes
-    return (size_t)batch_subtiles_per_block(L) * 4 * PW * 4 <= 60 * 1024;
-}
 
 hipError_t batch_sweep(hipStream_t st, const BatchArgs &a, uint32_t ngroups)
 {

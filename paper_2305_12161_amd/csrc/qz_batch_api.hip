@@ -49,9 +49,7 @@ struct qz_batch {
 
 namespace {
 
-size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 uint64_t nsites(uint32_t L) { return (uint64_t)L * L * L; }
-size_t replica_bytes(uint32_t L) { return align256((size_t)(nsites(L) / 8) * 2); }
 
 int fail(int status, const std::string &msg) { return qz::set_error(status, msg.c_str()); }
 
@@ -71,90 +69,32 @@ int dev_fail(qz_batch *b, hipError_t e, const char *where)
             return dev_fail((b), e_, #call);         \
     } while (0)
 
-// Planes per sub-tile: short z-chunks give a batch launch enough workgroups
-// to fill the chip (measured on MI355X: Tz = 8 for every size of the 584-
-// replica batch runs 2.1x faster than 16 / 16 / 32).
-uint32_t default_tz(uint32_t L) { return L % 8 == 0 ? 8u : 1u; }
+uint32_t default_tz(uint32_t L) { return qz::batch_default_tz(L); }
 
 // Sweeps per captured graph unless the tuning says otherwise.
 constexpr uint32_t kDefaultGraphSweeps = 100;
 
-struct Layout {
-    std::vector<size_t> rep_off;
-    size_t reps_off, tiles_off, groups_off, trace_off, counters_off, corr_off, stage_off;
-    size_t stage_bytes, total;
-    uint32_t max_L;
-    size_t max_tiles, max_groups;
-};
-
-// Device layout for a slot list.  The tile and group tables are sized for the
-// smallest plane count per sub-tile (one plane): L tiles per replica at most,
-// and never more groups than tiles.
-bool plan(const qz_replica_spec *specs, size_t n, uint32_t cap, Layout *lay)
+// Layout of a slot list in the caller's buffer (qz_batch_plan.hpp).
+bool plan(const qz_replica_spec *specs, size_t n, uint32_t cap, qz::BatchLayout *lay)
 {
-    size_t off = 0;
-    lay->rep_off.resize(n);
-    lay->max_L = 0;
-    lay->max_tiles = 0;
-    for (size_t i = 0; i < n; ++i) {
-        const uint32_t L = specs[i].L;
-        if (!qz::batch_size_ok(L))
-            return false;
-        lay->rep_off[i] = off;
-        off += replica_bytes(L);
-        lay->max_L = std::max(lay->max_L, L);
-        lay->max_tiles += L;
-    }
-    lay->max_groups = lay->max_tiles;
-    lay->reps_off = off;
-    off = align256(off + n * sizeof(qz::BatchReplica));
-    lay->tiles_off = off;
-    off = align256(off + lay->max_tiles * sizeof(qz::BatchTile));
-    lay->groups_off = off;
-    off = align256(off + lay->max_groups * sizeof(qz::BatchGroup));
-    lay->trace_off = off;
-    off = align256(off + n * (size_t)cap * 8);
-    lay->counters_off = off;
-    off = align256(off + 64 * 8);
-    lay->corr_off = off;
-    off = align256(off + (size_t)(3 * (lay->max_L / 2 + 1) + 1) * 8);
-    lay->stage_off = off;
-    lay->stage_bytes = std::min<size_t>(nsites(lay->max_L), size_t(4) << 20);
-    lay->stage_bytes = std::max<size_t>(lay->stage_bytes, (size_t)lay->max_L * lay->max_L);
-    off = align256(off + lay->stage_bytes);
-    lay->total = off;
-    return true;
+    std::vector<uint32_t> Ls(n);
+    for (size_t i = 0; i < n; ++i)
+        Ls[i] = specs[i].L;
+    return qz::batch_layout(Ls.data(), n, cap, lay);
 }
 
-// Rebuild the tile and group tables (slots grouped by L; sub-tiles of Tz
-// planes; S sub-tiles of one L per workgroup).
+// Rebuild the tile and group tables for the slots' current sides and copy
+// them to the device.
 int build_tables(qz_batch *b)
 {
-    std::map<uint32_t, std::vector<uint32_t>> by_L;
-    for (size_t i = 0; i < b->specs.size(); ++i)
-        by_L[b->specs[i].L].push_back((uint32_t)i);
+    std::vector<uint32_t> Ls(b->specs.size());
+    for (size_t i = 0; i < Ls.size(); ++i)
+        Ls[i] = b->specs[i].L;
     std::vector<qz::BatchTile> tiles;
     std::vector<qz::BatchGroup> groups;
-    for (auto &kv : by_L) {
-        const uint32_t L = kv.first;
-        uint32_t tz = b->tz.count(L) ? b->tz[L] : default_tz(L);
-        if (tz < 1 || L % tz)
-            tz = default_tz(L);
-        const uint32_t S = qz::batch_subtiles_per_block(L);
-        const size_t start = tiles.size();
-        for (uint32_t slot : kv.second)
-            for (uint32_t z0 = 0; z0 < L; z0 += tz)
-                tiles.push_back({slot, z0});
-        for (size_t f = start; f < tiles.size(); f += S) {
-            qz::BatchGroup g;
-            g.L = L;
-            g.nz = tz;
-            g.first = (uint32_t)f;
-            g.last = (uint32_t)std::min(tiles.size(), f + S);
-            groups.push_back(g);
-        }
-    }
-    if (tiles.size() > b->max_tiles || groups.size() > b->max_groups)
+    size_t lds = 0;
+    if (!qz::batch_tables(Ls.data(), Ls.size(), b->tz, b->max_tiles, b->max_groups, &tiles,
+                          &groups, &lds))
         return fail(QZ_EINVAL, "tile tables exceed their capacity");
     b->ntiles = (uint32_t)tiles.size();
     b->ngroups = (uint32_t)groups.size();
@@ -163,12 +103,7 @@ int build_tables(qz_batch *b)
     BZ_HIP(b, hipMemcpyAsync(b->d_groups, groups.data(), groups.size() * sizeof(qz::BatchGroup),
                              hipMemcpyHostToDevice, b->st));
     BZ_HIP(b, hipStreamSynchronize(b->st));
-    b->lds_bytes = 0;
-    for (auto &kv : by_L) {
-        const uint32_t L = kv.first, PW = L * (L / 64);
-        b->lds_bytes = std::max(b->lds_bytes,
-                                (size_t)qz::batch_subtiles_per_block(L) * 4 * PW * 4);
-    }
+    b->lds_bytes = lds;
     return QZ_OK;
 }
 
@@ -473,7 +408,7 @@ QZ_EXPORT size_t qz_batch_state_bytes(const qz_replica_spec *specs, size_t n, ui
 {
     if (!specs || n == 0)
         return 0;
-    Layout lay;
+    qz::BatchLayout lay;
     return plan(specs, n, trace_cap, &lay) ? lay.total : 0;
 }
 
@@ -504,7 +439,7 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
             if (!qz::batch_size_ok(kv.first) || kv.second == 0 || kv.first % kv.second)
                 return fail(QZ_EINVAL, "tuning_json: each Tz must divide its L");
     }
-    Layout lay;
+    qz::BatchLayout lay;
     plan(specs, n, trace_cap, &lay);
     if (dev_bytes < lay.total)
         return fail(QZ_ENOMEM, "device buffer smaller than qz_batch_state_bytes()");

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "qz_batch_plan.hpp"
+
 namespace qz {
 
 // Device-memory map of one lattice inside the caller's buffer.  Offsets are
@@ -129,23 +131,7 @@ hipError_t fft_radial(hipStream_t st, uint32_t L, const double *X, uint32_t nb, 
                       unsigned long long *c_cnt);
 hipError_t fft_zero(hipStream_t st, double *d, size_t n);
 
-// ----- batched replicas (qz_batch.hip) -----
-struct BatchReplica {
-    uint32_t *base;                 // copy k, colour c plane at base + (2k + c) * L*L*(L/64) words
-    unsigned long long *trace;      // bond-count ring (cap slots), or null
-    uint64_t seed;
-    uint64_t t;                     // time at the start of the current group of sweeps
-    uint64_t t_max;                 // the replica stops at this time (0: never)
-    uint32_t cur;                   // copy holding the state at time t
-    uint32_t active;                // 0: skipped by the sweeps
-};
-struct BatchTile {
-    uint32_t slot;                  // replica
-    uint32_t z0;                    // first plane
-};
-struct BatchGroup {                 // the sub-tiles of one workgroup: same L and plane count
-    uint32_t L, nz, first, last;    // tiles [first, last)
-};
+// ----- batched replicas (qz_batch.hip; tables planned in qz_batch_plan.hpp) -----
 struct BatchArgs {
     const BatchReplica *reps;
     const BatchTile *tiles;
@@ -154,8 +140,6 @@ struct BatchArgs {
     uint32_t every, cap;            // bond count every `every` sweeps into a ring of `cap`
     size_t lds_bytes;
 };
-uint32_t batch_subtiles_per_block(uint32_t L);
-bool batch_size_ok(uint32_t L);
 hipError_t batch_sweep(hipStream_t st, const BatchArgs &a, uint32_t ngroups);
 hipError_t batch_advance(hipStream_t st, BatchReplica *reps, uint32_t n, uint32_t k);
 hipError_t batch_clear_trace(hipStream_t st, BatchReplica *reps, uint32_t n, uint32_t span,
