@@ -151,6 +151,17 @@ int qz_bonds(qz_lattice *q, uint64_t out_B_axes[3]);
  * results are the same integers as by direct summation. */
 int qz_corr(qz_lattice *q, int64_t *out_S, int64_t *out_M);
 
+/* For callers that cannot allocate device memory or touch the lattice's idle
+ * copy (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): qz_corr with the same outputs, whose accumulators live
+ * in a 64 KiB device array of the library (one per device, found at the
+ * call's first use on that device) instead of the lattice's buffer, and whose
+ * x axis never uses the idle copy.  It calls no allocation routine.  Every
+ * call on a device shares that array: calls that overlap on one device (from
+ * several threads or streams) race and must be serialised by the caller.
+ * QZ_EINVAL if 3 (L/2 + 1) + 1 > 8192 (never for the layouts' sides). */
+int qz_corr_noalloc(qz_lattice *q, int64_t *out_S, int64_t *out_M);
+
 /* Current time t (completed sweeps). */
 int qz_time(const qz_lattice *q, uint64_t *t);
 

@@ -42,6 +42,7 @@ def _load():
         "qz_run_device_at": ([vp, u64, c.POINTER(u64), sz, vp, vp], i32),
         "qz_bonds": ([vp, c.POINTER(u64)], i32),
         "qz_corr": ([vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64)], i32),
+        "qz_corr_noalloc": ([vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64)], i32),
         "qz_time": ([vp, c.POINTER(u64)], i32),
         "qz_download_spins": ([vp, c.POINTER(c.c_int8)], i32),
         "qz_upload_spins": ([vp, c.POINTER(c.c_int8), u64], i32),
@@ -199,6 +200,16 @@ class Lattice:
         M = ctypes.c_int64()
         _check(lib.qz_corr(self._h, S.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                            ctypes.byref(M)))
+        return S, int(M.value)
+
+    def corr_noalloc(self):
+        """corr() through the entry point that allocates nothing (the library's
+        static scratch; the idle copy is left alone)."""
+        R = self.L // 2 + 1
+        S = np.zeros((3, R), dtype=np.int64)
+        M = ctypes.c_int64()
+        _check(lib.qz_corr_noalloc(self._h, S.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   ctypes.byref(M)))
         return S, int(M.value)
 
     def download(self) -> np.ndarray:

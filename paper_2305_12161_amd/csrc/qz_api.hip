@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -14,6 +15,14 @@
 #include "qz_internal.hpp"
 
 #define QZ_EXPORT extern "C" __attribute__((visibility("default")))
+
+// Scratch of qz_corr_noalloc: the correlation accumulators of one call,
+// 3 (L/2 + 1) + 1 counters, held by the library itself so that the call
+// allocates nothing.  Every device the library runs on has its own copy at
+// its own address (found with hipGetSymbolAddress); host code never passes
+// the array's name to a kernel.  64 KiB covers every side the layouts take.
+constexpr size_t kNoAllocWords = 8192;
+static __device__ __align__(256) unsigned long long scratch[kNoAllocWords];
 
 struct qz_lattice {
     uint32_t L;
@@ -252,6 +261,40 @@ int check_list(const uint64_t *at, size_t n_at, uint64_t n_sweeps)
         if (i > 0 && at[i] <= at[i - 1])
             return fail(QZ_EINVAL, "traced sweeps must be strictly increasing");
     }
+    return QZ_OK;
+}
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current, and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long *g_scratch_ptr[kMaxDevices];
+
+int scratch_on(int dev, unsigned long long **out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(QZ_EDEVICE, "device ordinal out of range for the static scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev)
+            e = hipSetDevice(dev);
+        void *p = nullptr;
+        if (e == hipSuccess)
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess)
+                e = e2;
+        }
+        if (e != hipSuccess)
+            return device_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+        if (!p)
+            return fail(QZ_EDEVICE, "hipGetSymbolAddress(scratch) returned null");
+        g_scratch_ptr[dev] = reinterpret_cast<unsigned long long *>(p);
+    }
+    *out = g_scratch_ptr[dev];
     return QZ_OK;
 }
 
@@ -571,6 +614,46 @@ QZ_EXPORT int qz_corr(qz_lattice *q, int64_t *out_S, int64_t *out_M)
         *out_M = 2 * (int64_t)h[3 * R] - N;
     }
     delete[] h;
+    return QZ_OK;
+}
+
+QZ_EXPORT int qz_corr_noalloc(qz_lattice *q, int64_t *out_S, int64_t *out_M)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if (!out_S || !out_M)
+        return fail(QZ_EINVAL, "null output");
+    const uint32_t R = q->L / 2 + 1;
+    const size_t nvals = 3 * (size_t)R + 1;
+    if (nvals > kNoAllocWords)
+        return fail(QZ_EINVAL, "L too large for the static correlation scratch "
+                               "(3 (L/2 + 1) + 1 <= 8192 counters)");
+    hipPointerAttribute_t attr;
+    QZ_HIP(q, hipPointerGetAttributes(&attr, q->base));
+    unsigned long long *acc = nullptr;
+    if ((rc = scratch_on(attr.device, &acc)) != QZ_OK)
+        return rc;
+    // the array keeps the previous call's sums: clear them first (a kernel,
+    // so that the call can also be captured into a graph)
+    QZ_HIP(q, qz::fill_u64(q->st, acc, nvals, 0ull));
+    if (q->layout == QZ_LAYOUT_I8)
+        QZ_HIP(q, qz::i8_corr(q->st, q->L, i8_spins(q), reinterpret_cast<long long *>(acc),
+                              reinterpret_cast<long long *>(acc + 3 * R)));
+    else
+        // no scratch copy: the x axis by funnel-rotated row pairs
+        QZ_HIP(q, qz::bit_corr(q->st, q->L, bit_plane(q, q->cur, 0), bit_plane(q, q->cur, 1), acc,
+                               acc + 3 * R, nullptr, nullptr));
+    // straight into the caller's arrays, converted there
+    QZ_HIP(q, hipMemcpyAsync(out_S, acc, 3 * (size_t)R * 8, hipMemcpyDeviceToHost, q->st));
+    QZ_HIP(q, hipMemcpyAsync(out_M, acc + 3 * R, 8, hipMemcpyDeviceToHost, q->st));
+    QZ_HIP(q, hipStreamSynchronize(q->st));
+    if (q->layout == QZ_LAYOUT_BIT) {
+        const int64_t N = (int64_t)n_sites(q->L);
+        for (size_t k = 0; k < 3 * (size_t)R; ++k)
+            out_S[k] = N - 2 * out_S[k];
+        *out_M = 2 * *out_M - N;
+    }
     return QZ_OK;
 }
 
