@@ -278,6 +278,121 @@ __global__ void k_batch_advance(BatchReplica *reps, uint32_t n, uint32_t k)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Replicas of side 64 entirely on chip.  Both colour planes of one replica
+// (2 x 4096 words, 32 KiB) fit in the LDS of a workgroup, so one workgroup
+// runs all k sweeps of a group for its replica without leaving the chip: per
+// half-sweep every lane updates two quads of colour p in place from the other
+// colour (a colour-p update reads only colour 1 - p, so no site is read after
+// another lane wrote it), and a barrier separates the half-sweeps.  There are
+// no halo planes and no launch per sweep; the lattice is read from and
+// written back to the replica's buffer once per group.  Word g = 64 z + y of a
+// plane holds row (y, z) (one word per colour row at L = 64), so a quad is
+// four consecutive rows of one plane and one Philox block of tie bits.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kOnchipBlock = 512;
+constexpr uint32_t kOnchipWords = 4096;     // words of one colour plane set at L = 64
+
+__global__ void __launch_bounds__(kOnchipBlock)
+    k_batch_onchip64(const BatchReplica *reps, const uint32_t *slots, uint32_t k, uint32_t every,
+                     uint32_t cap)
+{
+    __shared__ u32x4 planes[2 * kOnchipWords / 4];
+    __shared__ unsigned long long part[kOnchipBlock / 64];
+    uint32_t *P = reinterpret_cast<uint32_t *>(planes);
+    const uint32_t tid = threadIdx.x;
+    const BatchReplica R = reps[slots[blockIdx.x]];
+    const uint32_t m = batch_steps(R, k);          // the same in every lane
+    if (m == 0u)
+        return;
+    const uint32_t *src = R.base + (size_t)(2u * R.cur) * kOnchipWords;
+    for (uint32_t i = tid; i < 2u * kOnchipWords / 4; i += kOnchipBlock)
+        planes[i] = *(const __attribute__((address_space(1))) u32x4 *)(src + 4u * i);
+    __syncthreads();
+    const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
+    for (uint32_t s = 0; s < m; ++s) {
+        const uint64_t t64 = R.t + s;
+        const uint32_t t = (uint32_t)t64;
+        const bool counting = every != 0u && R.trace != nullptr && (t64 % every) == 0u;
+        int bonds = 0;
+        for (uint32_t p = 0; p < 2u; ++p) {
+            const uint32_t *O = P + (1u - p) * kOnchipWords;
+            uint32_t *Q = P + p * kOnchipWords;
+#pragma unroll
+            for (uint32_t h = 0; h < 2u; ++h) {
+                const uint32_t qd = tid + kOnchipBlock * h;      // quad: words 4 qd .. 4 qd + 3
+                const uint32_t g0 = 4u * qd, z = g0 >> 6, y0 = g0 & 63u;
+                const uint32_t zmo = ((z + 63u) & 63u) << 6, zpo = ((z + 1u) & 63u) << 6;
+                const u32x4 so = *reinterpret_cast<const u32x4 *>(O + g0);
+                const u32x4 sm = *reinterpret_cast<const u32x4 *>(O + zmo + y0);
+                const u32x4 sp = *reinterpret_cast<const u32x4 *>(O + zpo + y0);
+                const u32x4 ow = *reinterpret_cast<const u32x4 *>(Q + g0);
+                const uint32_t below = O[(z << 6) + ((y0 + 63u) & 63u)];
+                const uint32_t above = O[(z << 6) + ((y0 + 4u) & 63u)];
+                const uint32_t same[4] = {so.x, so.y, so.z, so.w};
+                const uint32_t zmn[4] = {sm.x, sm.y, sm.z, sm.w};
+                const uint32_t zpn[4] = {sp.x, sp.y, sp.z, sp.w};
+                const uint32_t own[4] = {ow.x, ow.y, ow.z, ow.w};
+                const uint32_t ym[4] = {below, same[0], same[1], same[2]};
+                const uint32_t yp[4] = {same[1], same[2], same[3], above};
+                uint32_t xa[4], ma[4], xb[4], mb[4], ties = 0u;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    // the x neighbours: the same word and its rotation by one
+                    // site, towards lower or higher x by the row's parity
+                    const uint32_t pi = (p + y0 + (uint32_t)v + z) & 1u;
+                    const uint32_t sh = pi ? funnel(same[v], same[v], 1) : funnel(same[v], same[v], 31);
+                    xa[v] = xor3(same[v], sh, ym[v]);
+                    ma[v] = maj3(same[v], sh, ym[v]);
+                    xb[v] = xor3(yp[v], zmn[v], zpn[v]);
+                    mb[v] = maj3(yp[v], zmn[v], zpn[v]);
+                    ties |= (xa[v] ^ xb[v]) & (ma[v] ^ mb[v]);
+                }
+                uint32_t r[4] = {0u, 0u, 0u, 0u};
+                if (ties != 0u) {
+                    const Words4 rb = philox10(qd, t, p, 0u, k0, k1);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        r[v] = rb.w[v];
+                }
+                uint32_t out[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    out[v] = maj3(ma[v], mb[v], maj3(xa[v], xb[v], own[v] ^ r[v]));
+                *reinterpret_cast<u32x4 *>(Q + g0) = u32x4{out[0], out[1], out[2], out[3]};
+                if (counting && p == 0u) {
+                    uint32_t ones = 0, twos = 0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        ones = popc_acc(xa[v] ^ own[v], popc_acc(xb[v] ^ own[v], ones));
+                        twos = popc_acc(ma[v] ^ own[v], popc_acc(mb[v] ^ own[v], twos));
+                    }
+                    bonds += (int)(ones + 2u * twos);
+                }
+            }
+            __syncthreads();
+        }
+        if (counting) {
+            // the replica's bond count entering sweep t: one workgroup owns
+            // the replica, so its ring entry is written, not accumulated
+            const unsigned long long w = wave_sum_u64((unsigned long long)bonds);
+            if ((tid & 63u) == 0u)
+                part[tid >> 6] = w;
+            __syncthreads();
+            if (tid == 0u) {
+                unsigned long long tot = 0;
+                for (uint32_t i = 0; i < kOnchipBlock / 64; ++i)
+                    tot += part[i];
+                R.trace[(t64 / every) % cap] = tot;
+            }
+            __syncthreads();
+        }
+    }
+    uint32_t *dst = R.base + (size_t)(2u * ((R.cur ^ m) & 1u)) * kOnchipWords;
+    for (uint32_t i = tid; i < 2u * kOnchipWords / 4; i += kOnchipBlock)
+        *(__attribute__((address_space(1))) u32x4 *)(dst + 4u * i) = planes[i];
+}
+
 // Zero trace slots of active replicas for times [t0, t0 + span) before they
 // are accumulated (launched as a kernel so that it can sit inside a graph).
 __global__ void k_batch_clear_trace(BatchReplica *reps, uint32_t n, uint32_t span, uint32_t every,
@@ -302,6 +417,16 @@ hipError_t batch_sweep(hipStream_t st, const BatchArgs &a, uint32_t ngroups)
     if (ngroups == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_batch_sweep, dim3(ngroups), dim3(kBatchBlock), a.lds_bytes, st, a);
+    return hipGetLastError();
+}
+
+hipError_t batch_onchip64(hipStream_t st, const BatchReplica *reps, const uint32_t *slots,
+                          uint32_t nslots, uint32_t k, uint32_t every, uint32_t cap)
+{
+    if (nslots == 0 || k == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_batch_onchip64, dim3(nslots), dim3(kOnchipBlock), 0, st, reps, slots, k,
+                       every, cap);
     return hipGetLastError();
 }
 

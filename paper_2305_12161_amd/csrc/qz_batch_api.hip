@@ -31,7 +31,9 @@ struct qz_batch {
     qz::BatchReplica *d_reps;
     qz::BatchTile *d_tiles;
     qz::BatchGroup *d_groups;
-    uint32_t ntiles, ngroups;
+    uint32_t *d_onchip;                      // slots run by the on-chip kernel (side 64)
+    uint32_t ntiles, ngroups, nonchip;
+    bool onchip;                             // side-64 slots on chip (else sub-tiles)
     size_t max_tiles, max_groups;            // capacity of the device tile / group tables
     size_t lds_bytes;
     int8_t *stage;
@@ -92,12 +94,17 @@ int build_tables(qz_batch *b)
         Ls[i] = b->specs[i].L;
     std::vector<qz::BatchTile> tiles;
     std::vector<qz::BatchGroup> groups;
+    std::vector<uint32_t> onchip;
     size_t lds = 0;
     if (!qz::batch_tables(Ls.data(), Ls.size(), b->tz, b->max_tiles, b->max_groups, &tiles,
-                          &groups, &lds))
+                          &groups, &lds, b->onchip, &onchip))
         return fail(QZ_EINVAL, "tile tables exceed their capacity");
     b->ntiles = (uint32_t)tiles.size();
     b->ngroups = (uint32_t)groups.size();
+    b->nonchip = (uint32_t)onchip.size();
+    if (!onchip.empty())
+        BZ_HIP(b, hipMemcpyAsync(b->d_onchip, onchip.data(), onchip.size() * sizeof(uint32_t),
+                                 hipMemcpyHostToDevice, b->st));
     BZ_HIP(b, hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(qz::BatchTile),
                              hipMemcpyHostToDevice, b->st));
     BZ_HIP(b, hipMemcpyAsync(b->d_groups, groups.data(), groups.size() * sizeof(qz::BatchGroup),
@@ -134,6 +141,10 @@ hipError_t enqueue_group(qz_batch *b, hipStream_t s, uint32_t k)
 {
     hipError_t e = qz::batch_clear_trace(s, b->d_reps, (uint32_t)b->specs.size(), k, b->every,
                                          b->cap);
+    if (e != hipSuccess)
+        return e;
+    // the side-64 replicas: all k sweeps in one launch, on chip
+    e = qz::batch_onchip64(s, b->d_reps, b->d_onchip, b->nonchip, k, b->every, b->cap);
     if (e != hipSuccess)
         return e;
     qz::BatchArgs a;
@@ -265,10 +276,11 @@ struct JsonIn {
 };
 
 bool parse_tuning(const char *text, std::map<uint32_t, uint32_t> *tz, uint32_t *graph_sweeps,
-                  bool *has_graph)
+                  bool *has_graph, bool *onchip, bool *has_onchip)
 {
     JsonIn in{text};
     *has_graph = false;
+    *has_onchip = false;
     if (!in.lit('{'))
         return false;
     if (in.lit('}'))
@@ -283,6 +295,12 @@ bool parse_tuning(const char *text, std::map<uint32_t, uint32_t> *tz, uint32_t *
                 return false;
             *graph_sweeps = (uint32_t)v;
             *has_graph = true;
+        } else if (key == "onchip") {
+            uint64_t v;
+            if (!in.num(&v) || v > 1)
+                return false;
+            *onchip = v != 0;
+            *has_onchip = true;
         } else if (key == "tz") {
             if (!in.lit('{'))
                 return false;
@@ -316,7 +334,8 @@ std::string tuning_text(const qz_batch *b)
     for (const auto &sp : b->specs)
         Ls.insert(sp.L);
     std::string o = "{\"source\": \"" + b->tune_source +
-                    "\", \"graph_sweeps\": " + std::to_string(b->graph_sweeps) + ", \"tz\": {";
+                    "\", \"graph_sweeps\": " + std::to_string(b->graph_sweeps) +
+                    ", \"onchip\": " + (b->onchip ? "1" : "0") + ", \"tz\": {";
     bool first = true;
     for (uint32_t L : Ls) {
         auto it = b->tz.find(L);
@@ -327,9 +346,10 @@ std::string tuning_text(const qz_batch *b)
     return o + "}}";
 }
 
-// Autotune: for each side L in the batch, in turn, time whole-batch sweeps
-// with each plane count per sub-tile that divides L and keep the fastest
-// (the others held at their current choice).  The sweeps run on the drawn
+// Autotune: first whether the side-64 replicas run on chip, then, for each
+// side that runs as sub-tiles, in turn, time whole-batch sweeps with each
+// plane count per sub-tile that divides L and keep the fastest (the others
+// held at their current choice).  The sweeps run on the drawn
 // starts, which are drawn again afterwards: results never depend on this.
 int autotune(qz_batch *b)
 {
@@ -359,7 +379,21 @@ int autotune(qz_batch *b)
             x = hipEventElapsedTime(ms, e0, e1);
         return x == hipSuccess ? QZ_OK : dev_fail(b, x, "autotune timing");
     };
+    // side-64 replicas: on chip (k sweeps per launch) or as sub-tiles
+    if (Ls.count(qz::kOnchipSide)) {
+        float ms[2] = {0.0f, 0.0f};
+        for (int on = 0; on < 2 && rc == QZ_OK; ++on) {
+            b->onchip = on != 0;
+            if ((rc = build_tables(b)) == QZ_OK)
+                rc = time_batch(&ms[on]);
+        }
+        b->onchip = ms[1] <= ms[0];
+    }
     for (uint32_t L : Ls) {
+        if (rc != QZ_OK)
+            break;
+        if (b->onchip && L == qz::kOnchipSide)
+            continue;
         uint32_t best = default_tz(L);
         float best_ms = 0.0f;
         bool have = false;
@@ -430,11 +464,11 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
         return fail(QZ_EINVAL, "device buffer must be non-null and 256-byte aligned");
     std::map<uint32_t, uint32_t> tz_in;
     uint32_t graph_in = 0;
-    bool has_graph = false;
+    bool has_graph = false, onchip_in = true, has_onchip = false;
     if (tuning_json) {
-        if (!parse_tuning(tuning_json, &tz_in, &graph_in, &has_graph))
-            return fail(QZ_EINVAL, "tuning_json is not of the form "
-                                   "{\"graph_sweeps\": G, \"tz\": {\"L\": Tz, ...}}");
+        if (!parse_tuning(tuning_json, &tz_in, &graph_in, &has_graph, &onchip_in, &has_onchip))
+            return fail(QZ_EINVAL, "tuning_json is not of the form {\"graph_sweeps\": G, "
+                                   "\"onchip\": 0 | 1, \"tz\": {\"L\": Tz, ...}}");
         for (const auto &kv : tz_in)
             if (!qz::batch_size_ok(kv.first) || kv.second == 0 || kv.first % kv.second)
                 return fail(QZ_EINVAL, "tuning_json: each Tz must divide its L");
@@ -459,6 +493,9 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
     b->d_reps = reinterpret_cast<qz::BatchReplica *>(b->base + lay.reps_off);
     b->d_tiles = reinterpret_cast<qz::BatchTile *>(b->base + lay.tiles_off);
     b->d_groups = reinterpret_cast<qz::BatchGroup *>(b->base + lay.groups_off);
+    b->d_onchip = reinterpret_cast<uint32_t *>(b->base + lay.onchip_off);
+    b->nonchip = 0;
+    b->onchip = has_onchip ? onchip_in : true;
     b->max_tiles = lay.max_tiles;
     b->max_groups = lay.max_groups;
     b->stage = reinterpret_cast<int8_t *>(b->base + lay.stage_off);

@@ -72,7 +72,8 @@ inline size_t batch_replica_bytes(uint32_t L)
 // tiles per slot at most, and never more groups than tiles.
 struct BatchLayout {
     std::vector<size_t> rep_off;
-    size_t reps_off, tiles_off, groups_off, trace_off, counters_off, corr_off, stage_off;
+    size_t reps_off, tiles_off, groups_off, onchip_off, trace_off, counters_off, corr_off,
+        stage_off;
     size_t stage_bytes, total;
     uint32_t max_L;
     size_t max_tiles, max_groups;
@@ -100,6 +101,8 @@ inline bool batch_layout(const uint32_t *Ls, size_t n, uint32_t cap, BatchLayout
     off = batch_align256(off + lay->max_tiles * sizeof(BatchTile));
     lay->groups_off = off;
     off = batch_align256(off + lay->max_groups * sizeof(BatchGroup));
+    lay->onchip_off = off;                      // slot list of the on-chip kernel
+    off = batch_align256(off + n * sizeof(uint32_t));
     lay->trace_off = off;
     off = batch_align256(off + n * (size_t)cap * 8);
     lay->counters_off = off;
@@ -115,18 +118,30 @@ inline bool batch_layout(const uint32_t *Ls, size_t n, uint32_t cap, BatchLayout
     return true;
 }
 
+// Side of the replicas the on-chip kernel can hold (both colour planes in
+// one workgroup's LDS).
+constexpr uint32_t kOnchipSide = 64;
+
 // The sweep launch's tables for the slots' current sides: slots grouped by L,
 // each cut into sub-tiles of Tz planes (tz[L], else the default; a value that
 // does not divide L falls back to the default), S sub-tiles of one L per
-// workgroup.  Returns false, leaving the outputs unspecified, if the tables
-// would exceed their capacity.  lds_bytes receives the largest workgroup LDS.
+// workgroup.  With onchip set, the slots of side 64 go to the on-chip
+// kernel's list instead.  Returns false, leaving the outputs unspecified, if
+// the tables would exceed their capacity.  lds_bytes receives the largest
+// workgroup LDS of the sub-tile launch.
 inline bool batch_tables(const uint32_t *slot_L, size_t n, const std::map<uint32_t, uint32_t> &tz,
                          size_t max_tiles, size_t max_groups, std::vector<BatchTile> *tiles,
-                         std::vector<BatchGroup> *groups, size_t *lds_bytes)
+                         std::vector<BatchGroup> *groups, size_t *lds_bytes, bool onchip,
+                         std::vector<uint32_t> *onchip_slots)
 {
     std::map<uint32_t, std::vector<uint32_t>> by_L;
-    for (size_t i = 0; i < n; ++i)
-        by_L[slot_L[i]].push_back((uint32_t)i);
+    onchip_slots->clear();
+    for (size_t i = 0; i < n; ++i) {
+        if (onchip && slot_L[i] == kOnchipSide)
+            onchip_slots->push_back((uint32_t)i);
+        else
+            by_L[slot_L[i]].push_back((uint32_t)i);
+    }
     tiles->clear();
     groups->clear();
     *lds_bytes = 0;

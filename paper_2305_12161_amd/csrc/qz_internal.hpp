@@ -142,6 +142,9 @@ struct BatchArgs {
 };
 hipError_t batch_sweep(hipStream_t st, const BatchArgs &a, uint32_t ngroups);
 hipError_t batch_advance(hipStream_t st, BatchReplica *reps, uint32_t n, uint32_t k);
+// k sweeps of the listed replicas of side 64, each held on chip by one workgroup
+hipError_t batch_onchip64(hipStream_t st, const BatchReplica *reps, const uint32_t *slots,
+                          uint32_t nslots, uint32_t k, uint32_t every, uint32_t cap);
 hipError_t batch_clear_trace(hipStream_t st, BatchReplica *reps, uint32_t n, uint32_t span,
                              uint32_t every, uint32_t cap);
 

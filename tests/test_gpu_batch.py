@@ -247,3 +247,40 @@ def test_batch_autotune_and_tuning_text(qz):
         for b in (auto, given):
             assert np.array_equal(b.trace(slot, 0, 5), tr), slot
             assert np.array_equal(b.download(slot), lat.download()), slot
+
+
+@pytest.mark.parametrize("graph_sweeps", [0, 5, 12])
+def test_batch_onchip_side64(qz, orc, graph_sweeps):
+    """Side-64 replicas held on chip (all sweeps of a group in one launch)
+    against the same batch run as sub-tiles, against lone runs, and against
+    the oracle: traces at every sweep, a t_max inside a group, parking."""
+    specs = [(64, 61, 0), (128, 62, 0), (64, 63, 17), (192, 64, 0), (64, 2**63 + 65, 0),
+             (64, 66, 3)]
+    n, every = 30, 1
+    runs = {}
+    for onchip in (1, 0):
+        b = qz.Batch(specs, trace_every=every, trace_cap=64,
+                     tuning={"onchip": onchip, "graph_sweeps": graph_sweeps})
+        assert b.tuning()["onchip"] == onchip
+        b.run(10)
+        b.set_active(4, False)          # parked for 10 sweeps
+        b.run(10)
+        b.set_active(4, True)
+        b.run(10)
+        b.sync()
+        runs[onchip] = [(b.time(k), b.trace(k, 0, min(b.time(k), 30)), b.download(k))
+                        for k in range(len(specs))]
+    for k, (L, seed, t_max) in enumerate(specs):
+        t_end = 20 if k == 4 else (t_max or n)
+        (t1, tr1, s1), (t0, tr0, s0) = runs[1][k], runs[0][k]
+        assert t1 == t0 == t_end, (k, t1, t0)
+        assert np.array_equal(tr1, tr0) and np.array_equal(s1, s0), k
+        lat = qz.Lattice(L, seed, "bit")
+        tr = lat.run(t_end, 1)
+        assert np.array_equal(tr1, tr), k
+        assert np.array_equal(s1, lat.download()), k
+        if L == 64 and k < 3:
+            s = orc.init(L, seed)
+            want = orc.run(s, seed, 0, t_end, 1)
+            assert np.array_equal(tr1.astype(np.int64), want), k
+            assert np.array_equal(s1, s), k

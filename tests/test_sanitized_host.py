@@ -35,7 +35,7 @@ PLAN_DRIVER = r"""
 using namespace qz;
 
 static void check_tables(const std::vector<uint32_t> &cap_L, const std::vector<uint32_t> &now_L,
-                         const std::map<uint32_t, uint32_t> &tz)
+                         const std::map<uint32_t, uint32_t> &tz, bool onchip = false)
 {
     const size_t n = cap_L.size();
     BatchLayout lay;
@@ -48,19 +48,29 @@ static void check_tables(const std::vector<uint32_t> &cap_L, const std::vector<u
         CHECK(batch_replica_bytes(now_L[i]) <= batch_replica_bytes(cap_L[i]));
     }
     CHECK(end <= lay.reps_off);
-    const size_t offs[] = {lay.reps_off, lay.tiles_off, lay.groups_off, lay.trace_off,
-                           lay.counters_off, lay.corr_off, lay.stage_off, lay.total};
+    const size_t offs[] = {lay.reps_off, lay.tiles_off, lay.groups_off, lay.onchip_off,
+                           lay.trace_off, lay.counters_off, lay.corr_off, lay.stage_off,
+                           lay.total};
     for (size_t k = 0; k + 1 < sizeof offs / sizeof offs[0]; ++k)
         CHECK(offs[k] % 256 == 0 && offs[k] <= offs[k + 1]);
     CHECK(lay.tiles_off - lay.reps_off >= n * sizeof(BatchReplica));
     CHECK(lay.groups_off - lay.tiles_off >= lay.max_tiles * sizeof(BatchTile));
-    CHECK(lay.trace_off - lay.groups_off >= lay.max_groups * sizeof(BatchGroup));
+    CHECK(lay.onchip_off - lay.groups_off >= lay.max_groups * sizeof(BatchGroup));
+    CHECK(lay.trace_off - lay.onchip_off >= n * sizeof(uint32_t));
     CHECK(lay.counters_off - lay.trace_off >= n * 7 * 8);
     CHECK(lay.stage_bytes >= (size_t)lay.max_L * lay.max_L);
     std::vector<BatchTile> tiles;
     std::vector<BatchGroup> groups;
+    std::vector<uint32_t> oc;
     size_t lds = 0;
-    CHECK(batch_tables(now_L.data(), n, tz, lay.max_tiles, lay.max_groups, &tiles, &groups, &lds));
+    CHECK(batch_tables(now_L.data(), n, tz, lay.max_tiles, lay.max_groups, &tiles, &groups, &lds,
+                       onchip, &oc));
+    // the on-chip list: exactly the side-64 slots when enabled, in order
+    std::vector<uint32_t> want_oc;
+    for (size_t i = 0; onchip && i < n; ++i)
+        if (now_L[i] == kOnchipSide)
+            want_oc.push_back((uint32_t)i);
+    CHECK(oc == want_oc);
     CHECK(tiles.size() <= lay.max_tiles && groups.size() <= lay.max_groups);
     CHECK(lds <= 60 * 1024);
     std::set<std::pair<uint32_t, uint32_t>> seen;
@@ -86,6 +96,8 @@ static void check_tables(const std::vector<uint32_t> &cap_L, const std::vector<u
     size_t want = 0;
     for (size_t i = 0; i < n; ++i) {
         const uint32_t L = now_L[i];
+        if (onchip && L == kOnchipSide)
+            continue;
         auto it = tz.find(L);
         const bool given = it != tz.end() && it->second >= 1 && L % it->second == 0;
         want += L / (given ? it->second : batch_default_tz(L));
@@ -105,7 +117,8 @@ int main()
             for (size_t n : {1, 2, 3, 17}) {
                 std::vector<uint32_t> Ls(n, L);
                 check_tables(Ls, Ls, {{L, tz}});
-                ++cases;
+                check_tables(Ls, Ls, {{L, tz}}, true);
+                cases += 2;
             }
         }
     }
@@ -121,14 +134,16 @@ int main()
         for (uint32_t b : {1u, 8u, 128u})
             for (uint32_t c : {1u, 4u, 256u, 3u, 0u}) {
                 check_tables(mix, mix, {{64, a}, {128, b}, {256, c}});
-                ++cases;
+                check_tables(mix, mix, {{64, a}, {128, b}, {256, c}}, true);
+                cases += 2;
             }
     // slots refilled with smaller sides (serving), one plane per sub-tile
     std::vector<uint32_t> cap = {256, 256, 192, 128, 64, 256};
     std::vector<uint32_t> now = {64, 192, 128, 128, 64, 256};
     for (uint32_t tz : {1u, 2u, 8u}) {
         check_tables(cap, now, {{64, tz}, {128, tz}, {192, tz}, {256, tz}});
-        ++cases;
+        check_tables(cap, now, {{64, tz}, {128, tz}, {192, tz}, {256, tz}}, true);
+        cases += 2;
     }
     std::printf("ok %zu\n", cases);
     return 0;
