@@ -11,17 +11,17 @@ Backends:
   * GpuBackend -- the HIP library: lattice sizes the batched engine takes
     (L % 64 == 0, L <= 256) live in fixed batch slots advanced by one graph
     replay per chunk; other sizes run as single lattices (the 1-bit layout when
-    L % 64 == 0, else int8) spread over a few streams so that their short
-    sweeps overlap.
-  * Any object with the same methods (tests use a CPU one).
+    L % 64 == 0, else int8) spread over a few streams, each quenched to its
+    t_max in one enqueue as soon as it is admitted.  Completions are noticed
+    through events: nothing waits for the whole device.
+  * Any object with the lock-step methods (tests use a CPU one).
 
 Results never depend on what else is running: every lattice follows exactly
 its own (L, seed) trajectory.
 """
 import collections
-import heapq
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -101,6 +101,7 @@ class GpuBackend:
             raise ValueError("batch slots exceed the memory budget")
         self.single_used = 0
         self.live: Dict[int, dict] = {}          # request idx -> placement
+        self._batch_event = None                 # completion of the batch's chunk in flight
 
     @staticmethod
     def layout_for(L: int) -> str:
@@ -137,25 +138,72 @@ class GpuBackend:
             lat.set_pass(self.single_pass)
         self.single_used += self.single_bytes(req.L)
         self.live[req.idx] = {"kind": "single", "lat": lat, "trace": tr, "t": 0,
-                              "t_max": req.t_max, "bytes": self.single_bytes(req.L)}
+                              "t_max": req.t_max, "bytes": self.single_bytes(req.L),
+                              "stream": st}
 
     def advance(self) -> None:
-        """One chunk of sweeps for every live lattice (asynchronous)."""
+        """One chunk of sweeps for every live lattice (asynchronous); the
+        lock-step protocol, kept for callers that step the backend by hand."""
         if self.batch is not None and any(p["kind"] == "batch" for p in self.live.values()):
             self.batch.run(self.chunk)
         for p in self.live.values():
-            if p["kind"] == "single":
+            if p["kind"] == "single" and p["t"] < p["t_max"]:
                 t = p["t"]
                 sl = p["trace"][t // self.every: (t + self.chunk) // self.every]
                 p["lat"].run_device(self.chunk, self.every, sl)
         for p in self.live.values():
-            p["t"] += self.chunk
+            p["t"] = min(p["t"] + self.chunk, p["t_max"])
 
     def sync(self) -> None:
         self.torch.cuda.synchronize(self.device)
 
     def finished(self) -> List[int]:
         return [i for i, p in self.live.items() if p["t"] >= p["t_max"]]
+
+    # ---- the asynchronous protocol: no device-wide synchronisation --------
+    # A single lattice gets its whole run enqueued on its own stream at
+    # admission, followed by an event; the batch advances one chunk (one
+    # graph replay) at a time, followed by an event.  poll() reports the
+    # requests whose work has completed, kick() starts the batch's next chunk.
+    def start(self, idx: int) -> None:
+        p = self.live[idx]
+        if p["kind"] == "single":
+            p["lat"].run_device(p["t_max"], self.every, p["trace"])
+            ev = self.torch.cuda.Event()
+            ev.record(p["stream"])
+            p["event"] = ev
+
+    def poll(self) -> List[int]:
+        out = []
+        for i, p in self.live.items():
+            if p["kind"] == "single" and p.get("event") is not None and p["event"].query():
+                p["t"] = p["t_max"]
+                out.append(i)
+        if self._batch_event is not None and self._batch_event.query():
+            self._batch_event = None
+            for i, p in self.live.items():
+                if p["kind"] == "batch" and p["t"] < p["t_max"] and p.get("running"):
+                    p["t"] = min(p["t"] + self.chunk, p["t_max"])
+                    p["running"] = False
+                    if p["t"] >= p["t_max"]:
+                        out.append(i)
+        return out
+
+    def kick(self) -> None:
+        if self.batch is None or self._batch_event is not None:
+            return
+        todo = [p for p in self.live.values() if p["kind"] == "batch" and p["t"] < p["t_max"]]
+        if not todo:
+            return
+        self.batch.run(self.chunk)
+        for p in todo:
+            p["running"] = True
+        ev = self.torch.cuda.Event()
+        ev.record(self.stream)
+        self._batch_event = ev
+
+    def busy(self) -> bool:
+        return bool(self.live)
 
     def retire(self, idx: int) -> dict:
         p = self.live.pop(idx)
@@ -174,9 +222,16 @@ class GpuBackend:
             self.single_used -= p["bytes"]
         return {"trace": trace, "final_B": final_B}
 
-
 class Server:
-    """Event loop: admit arrivals at chunk boundaries, advance, retire."""
+    """Event loop: admit arrivals as room frees up, keep the device busy,
+    retire finished requests.
+
+    With a backend that offers poll()/kick()/start() (the GPU backend) the
+    loop never waits for the whole device: single lattices run their whole
+    quench on their own streams as soon as they are admitted, the batch runs
+    chunk after chunk, and each completion (an event) is noticed and answered
+    on its own.  Other backends (a CPU one in the tests) are stepped in lock
+    step, one chunk for every live lattice per round."""
 
     def __init__(self, backend, chunk: int):
         self.backend = backend
@@ -187,46 +242,62 @@ class Server:
         """Serve `requests` (objects with idx, L, seed, t_max, arrival_s), arrivals
         replayed in real time (arrival_s * time_scale after the start).
         progress(done, total, seconds) is called after each retirement."""
+        be = self.backend
+        asynchronous = all(hasattr(be, k) for k in ("poll", "kick", "start"))
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
         waiting: collections.deque = collections.deque()
         results: Dict[int, Result] = {}
         t_start = clock()
         done = 0
         total = len(pending)
+
+        def finish(idx):
+            nonlocal done
+            out = be.retire(idx)
+            res = results[idx]
+            res.trace = out["trace"]
+            res.final_B = out["final_B"]
+            res.done_s = clock() - t_start
+            done += 1
+            if progress is not None:
+                progress(done, total, res.done_s)
+
         while done < total:
             now = clock() - t_start
             while pending and pending[0].arrival_s * time_scale <= now:
                 r = pending.popleft()
                 waiting.append(r)
                 results[r.idx] = Result(r.idx, r.L, r.seed, r.t_max, r.arrival_s * time_scale)
+            if asynchronous:
+                for idx in be.poll():
+                    finish(idx)
             # admit in arrival order, skipping requests whose size has no room yet
             still = collections.deque()
             while waiting:
                 r = waiting.popleft()
-                if self.backend.can_admit(r.L):
-                    self.backend.admit(r)
+                if be.can_admit(r.L):
+                    be.admit(r)
                     results[r.idx].admitted_s = clock() - t_start
+                    if asynchronous:
+                        be.start(r.idx)
                 else:
                     still.append(r)
             waiting = still
-            if not self.backend.live:
+            if not be.live:
                 if pending:
                     # idle until the next arrival
                     wait = pending[0].arrival_s * time_scale - (clock() - t_start)
                     if wait > 0:
                         time.sleep(min(wait, 0.01))
                 continue
-            self.backend.advance()
-            self.backend.sync()
-            for idx in self.backend.finished():
-                out = self.backend.retire(idx)
-                res = results[idx]
-                res.trace = out["trace"]
-                res.final_B = out["final_B"]
-                res.done_s = clock() - t_start
-                done += 1
-                if progress is not None:
-                    progress(done, total, res.done_s)
+            if asynchronous:
+                be.kick()
+                time.sleep(0.0002)        # the device is busy; look again shortly
+                continue
+            be.advance()
+            be.sync()
+            for idx in be.finished():
+                finish(idx)
         return [results[k] for k in sorted(results)]
 
 

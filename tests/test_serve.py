@@ -69,6 +69,46 @@ def test_scheduler_with_oracle_backend(orc):
     assert stats["requests"] == len(reqs) and stats["p99_latency_s"] >= stats["p50_latency_s"]
 
 
+class AsyncOracleBackend(OracleBackend):
+    """The asynchronous protocol on the CPU: start() queues a request's whole
+    quench, kick() runs at most one queued quench, poll() reports finished
+    ones once -- so requests finish out of step with each other."""
+
+    def __init__(self, orc, slots, every):
+        super().__init__(orc, slots, every, chunk=None)
+        self.queue = collections.deque()
+        self.done = []
+
+    def start(self, idx):
+        self.queue.append(idx)
+
+    def kick(self):
+        if self.queue:
+            idx = self.queue.popleft()
+            p = self.live[idx]
+            tr = self.orc.run(p["s"], p["seed"], 0, p["t_max"], self.every)
+            p["trace"] = [int(v) for v in tr]
+            p["t"] = p["t_max"]
+            self.done.append(idx)
+
+    def poll(self):
+        out, self.done = self.done, []
+        return out
+
+
+def test_scheduler_asynchronous_protocol(orc):
+    reqs = wl.request_stream(n=20, rate_per_s=300.0, master_seed=11, sizes=(4, 6, 8),
+                             t_maxes=(10, 30))
+    be = AsyncOracleBackend(orc, slots=4, every=5)
+    res = serve.Server(be, chunk=10).serve(reqs)
+    assert len(res) == len(reqs) and be.max_live <= 4
+    for r in res:
+        s = orc.init(r.L, r.seed)
+        assert np.array_equal(r.trace, orc.run(s, r.seed, 0, r.t_max, 5))
+        assert r.final_B == int(orc.bonds(s).sum())
+        assert r.done_s >= r.admitted_s >= r.arrival_s - 1e-9
+
+
 def test_request_stream_is_seeded():
     a = wl.request_stream(n=50, rate_per_s=10.0)
     b = wl.request_stream(n=50, rate_per_s=10.0)
