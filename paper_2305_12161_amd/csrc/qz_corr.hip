@@ -346,23 +346,22 @@ __global__ void __launch_bounds__(kBlock) k_corr_x(uint32_t L, uint32_t W, const
 // site has one partner at +r: the pairs with at least one up spin number
 // 2 N_up - T(r), of which T(r) are up-up.
 //
-// G is a plain int8 matrix product: each wave owns a 128 x 32 NB tile of G
-// (4 x NB blocks of v_mfma_i32_32x32x32_i8) over a chunk of the lines; G is
+// G is a plain matrix product of 0/1 entries: each wave owns a 128 x 32 NB
+// tile of G (4 x NB blocks of 32 x 32) over a chunk of the lines; G is
 // symmetric, so only tiles that reach the diagonal or beyond are computed and
-// their entries below it are skipped.  A row's lines come
-// as 32-bit words: word kappa = (o * 2 + p) * W + w holds the 32 lines
-// (o, x = 64 w + 2 j + p) of row u, o being the third coordinate, from colour
-// plane (p + u + o) & 1.  Both operands of an instruction must pair the same
-// 32 lines in the same order, and which 32 does not matter: lane half h of a
-// wave takes word kk = kappa0 + 4h + s of the row (s = 0..3) and expands bits
-// {j, 8 + j, 16 + j, 24 + j} into the four bytes of dword j (j = 0..3 for one
-// instruction, 4..7 for the next), so 8 words feed 8 instructions per block.
+// their entries below it are skipped.  The products run on the matrix cores
+// with four-bit operands (E2M1: 0 and 0.5 are exact, so each up-up pair adds
+// exactly 0.25 to a float accumulator), the densest exact form gfx950 has.
+// A row's lines come as 32-bit words: word kappa = (o * 2 + p) * W + w holds
+// the 32 lines (o, x = 64 w + 2 j + p) of row u, o being the third
+// coordinate, from colour plane (p + u + o) & 1.  Both operands of an
+// instruction must pair the same lines in the same order, and which ones does
+// not matter: lane half h of a wave takes word kk = kappa0 + 4h + s of the
+// row (s = 0..3) for instruction s, so 8 words feed 4 instructions per block.
 // ---------------------------------------------------------------------------
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr uint32_t kGramTile = 128;   // rows of a wave's tile
-constexpr int kGramNB = 2;            // 32-column blocks of a wave's tile
+constexpr int kGramNB = 4;            // 32-column blocks of a wave's tile (128 x 128)
 
 struct GramGeom {
     uint32_t L, W, nT;     // nT = L / 128 row blocks
@@ -373,18 +372,30 @@ struct GramGeom {
     uint32_t NK;           // words per row, 2 L W
 };
 
-__device__ __forceinline__ v4i expand_bits(uint32_t y, uint32_t j0)
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// The 32 lines of a word as 32 four-bit E2M1 values, 0 (down) or 0.5 (up,
+// code 0001): dword d holds bits d, 4 + d, ..., 28 + d in its eight nibbles.
+// Every operand expands its words the same way, so both sides of an
+// instruction pair the same lines; the upper four dwords are not read.
+__device__ __forceinline__ v8i expand_fp4(uint32_t y)
 {
-    v4i f;
-    f[0] = (int)((y >> j0) & 0x01010101u);
-    f[1] = (int)((y >> (j0 + 1u)) & 0x01010101u);
-    f[2] = (int)((y >> (j0 + 2u)) & 0x01010101u);
-    f[3] = (int)((y >> (j0 + 3u)) & 0x01010101u);
+    v8i f;
+    f[0] = (int)(y & 0x11111111u);
+    f[1] = (int)((y >> 1) & 0x11111111u);
+    f[2] = (int)((y >> 2) & 0x11111111u);
+    f[3] = (int)((y >> 3) & 0x11111111u);
+    f[4] = f[5] = f[6] = f[7] = 0;
     return f;
 }
 
 // NB = 4: 128 x 128 tiles, one wave per SIMD (256 accumulator registers);
-// NB = 2: 128 x 64 tiles, two waves per SIMD.
+// NB = 2: 128 x 64 tiles, two waves per SIMD.  Each instruction
+// (v_mfma_scale_f32_32x32x64_f8f6f4 on four-bit operands, unit scales)
+// takes one word of 32 lines per row and lane half: 64 lines, products of
+// 0.25 per up-up pair, exact in the float accumulators while a chunk holds
+// fewer than 2^24 lines.
 template <int AX, int NB>
 __global__ void __launch_bounds__(256, 4 / NB) k_corr_gram(GramGeom g, const uint32_t *P0,
                                                   const uint32_t *P1, unsigned long long *tb)
@@ -412,23 +423,22 @@ __global__ void __launch_bounds__(256, 4 / NB) k_corr_gram(GramGeom g, const uin
     const uint32_t L = g.L, W = g.W, W2 = 2u * g.W;
     const uint32_t k_begin = split * g.kchunk, k_end = min(g.NK, k_begin + g.kchunk);
 
-    v16i acc[4][NB];
+    v16f acc[4][NB];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < NB; ++n)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                acc[m][n][r] = 0;
+                acc[m][n][r] = 0.0f;
     auto row_words = [&](uint32_t u, uint32_t o, uint32_t p, uint32_t w) -> uint4 {
         const uint32_t *P = ((p + u + o) & 1u) ? P1 : P0;
         const size_t off = (AX == 1) ? ((size_t)o * L + u) * W + w : ((size_t)u * L + o) * W + w;
         return *reinterpret_cast<const uint4 *>(P + off);
     };
-    // Software pipeline over the instruction steps (8 per 8 words): the words
-    // of the next 8 are loaded while these are multiplied, and the bytes of
-    // the next step are expanded between the 16 MFMAs of this one (one wave
-    // per SIMD: nothing else hides the load latency or the expansion).
+    // Software pipeline over the instruction steps (4 per 8 words): the words
+    // of the next 8 are loaded while these are multiplied, and the operands
+    // of the next step are expanded between the MFMAs of this one.
     uint4 na[4], nb[NB];
     auto fetch = [&](uint32_t k0) {
         const uint32_t kk = k0 + 4u * h;
@@ -444,7 +454,7 @@ __global__ void __launch_bounds__(256, 4 / NB) k_corr_gram(GramGeom g, const uin
         return s == 0 ? q.x : s == 1 ? q.y : s == 2 ? q.z : q.w;
     };
     fetch(k_begin);
-    uint4 ca[4], cb[NB];   // words of the current 8 steps
+    uint4 ca[4], cb[NB];   // words of the current 4 steps
 #pragma unroll
     for (int m = 0; m < 4; ++m)
         ca[m] = na[m];
@@ -452,34 +462,32 @@ __global__ void __launch_bounds__(256, 4 / NB) k_corr_gram(GramGeom g, const uin
     for (int n = 0; n < NB; ++n)
         cb[n] = nb[n];
     fetch(min(k_begin + 8u, k_end - 8u));
-    v4i fa[4], fb[NB];
+    v8i fa[4], fb[NB];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-        fa[m] = expand_bits(ca[m].x, 0u);
+        fa[m] = expand_fp4(ca[m].x);
 #pragma unroll
     for (int n = 0; n < NB; ++n)
-        fb[n] = expand_bits(cb[n].x, 0u);
+        fb[n] = expand_fp4(cb[n].x);
     for (uint32_t k0 = k_begin; k0 < k_end; k0 += 8u) {
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            // next step's bytes: word (st + 1) / 2, bit groups 0..3 or 4..7;
-            // after the 8th step the first of the prefetched words
-            v4i ga[4], gb[NB];
-            const int s1 = (st + 1) / 2;
-            const uint32_t j1 = ((st + 1) % 2) ? 4u : 0u;
+        for (int st = 0; st < 4; ++st) {
+            // next step's operands: word st + 1, after the 4th step the first
+            // of the prefetched words
+            v8i ga[4], gb[NB];
 #pragma unroll
             for (int m = 0; m < 4; ++m)
-                ga[m] = expand_bits(st < 7 ? word(ca[m], s1) : na[m].x, j1);
+                ga[m] = expand_fp4(st < 3 ? word(ca[m], st + 1) : na[m].x);
 #pragma unroll
             for (int n = 0; n < NB; ++n)
-                gb[n] = expand_bits(st < 7 ? word(cb[n], s1) : nb[n].x, j1);
+                gb[n] = expand_fp4(st < 3 ? word(cb[n], st + 1) : nb[n].x);
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
                 for (int n = 0; n < NB; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[m], fb[n], acc[m][n],
-                                                                      0, 0, 0);
+                    acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        fa[m], fb[n], acc[m][n], 4, 4, 0, 127, 0, 127);
             // one MFMA, then up to four VALU instructions, for each MFMA
 #pragma unroll
             for (int q = 0; q < 4 * NB; ++q) {
@@ -516,9 +524,9 @@ __global__ void __launch_bounds__(256, 4 / NB) k_corr_gram(GramGeom g, const uin
             for (int r = 0; r < 16; ++r) {
                 const int row = 32 * m + 8 * (r / 4) + 4 * (int)h + (r % 4);
                 const int col = 32 * n + (int)i;
-                const int v = acc[m][n][r];
-                if (v != 0 && dbase + 127 + col - row >= 0)
-                    atomicAdd(ds + (col - row + 127), (uint32_t)v);
+                const uint32_t v = (uint32_t)(acc[m][n][r] * 4.0f);   // 0.25 per pair
+                if (v != 0u && dbase + 127 + col - row >= 0)
+                    atomicAdd(ds + (col - row + 127), v);
             }
     // fold: an entry at separation d (u < u') is the pair (u, u') at +d and
     // the pair (u', u) at +(L - d); T keeps r = 0 .. L/2
@@ -597,7 +605,7 @@ __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, con
     // out whole.
     extern __shared__ uint32_t sm[];
     uint32_t *out = sm;                   // [256 rows][2 parity slots][W]: slot 0 = even x'
-    uint32_t *in = sm + 512u * W;         // [64 rows z][2 parity slots][4 words]: slot 0 = even x
+    uint32_t *in = sm + 512u * W;         // [2 buffers][64 rows z][2 parity slots][4 words]
     const uint32_t ngroups = W / 4;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // a y's groups share an XCD
     const uint32_t y = tile / ngroups, xg = tile % ngroups;
@@ -606,7 +614,9 @@ __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, con
                                    0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
                                    0x3333333333333333ull, 0x5555555555555555ull};
     // words 4 xg .. 4 xg + 3 of rows z = 64 zb + r, both parities: entry
-    // k = threadIdx.x + 256 i of block zb, loaded one block ahead
+    // k = threadIdx.x + 256 i of block zb.  Blocks are loaded kAhead ahead,
+    // so that several loads per lane are in flight (the loads of one block
+    // are small: without depth the kernel waits on their latency).
     auto fetch = [&](uint32_t zb, uint32_t i) -> uint32_t {
         const uint32_t k = threadIdx.x + 256u * i;
         const uint32_t j = k & 3u, slot = (k >> 2) & 1u, r = k >> 3;
@@ -614,17 +624,31 @@ __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, con
         const uint32_t c = slot ^ ((y + z) & 1u);   // colour holding the parity slot
         return (c ? P1 : P0)[((size_t)z * L + y) * W + 4u * xg + j];
     };
-    uint32_t pre0 = fetch(0, 0), pre1 = fetch(0, 1);
+    constexpr uint32_t kAhead = 4;
+    uint32_t pre[kAhead][2];
+#pragma unroll
+    for (uint32_t a = 0; a < kAhead; ++a) {
+        pre[a][0] = a < W ? fetch(a, 0) : 0u;
+        pre[a][1] = a < W ? fetch(a, 1) : 0u;
+    }
     for (uint32_t zb = 0; zb < W; ++zb) {
-        in[threadIdx.x] = pre0;
-        in[threadIdx.x + 256u] = pre1;
-        __syncthreads();
-        if (zb + 1 < W) {
-            pre0 = fetch(zb + 1, 0);
-            pre1 = fetch(zb + 1, 1);
+        // the block's words into this iteration's buffer; the other buffer was
+        // last read before the previous barrier
+        uint32_t *ib = in + (zb & 1u) * 512u;
+        ib[threadIdx.x] = pre[0][0];
+        ib[threadIdx.x + 256u] = pre[0][1];
+#pragma unroll
+        for (uint32_t a = 0; a + 1 < kAhead; ++a) {
+            pre[a][0] = pre[a + 1][0];
+            pre[a][1] = pre[a + 1][1];
         }
+        if (zb + kAhead < W) {
+            pre[kAhead - 1][0] = fetch(zb + kAhead, 0);
+            pre[kAhead - 1][1] = fetch(zb + kAhead, 1);
+        }
+        __syncthreads();
         // wave wv: block xb = 4 xg + wv; lane = row z - 64 zb
-        const uint32_t we = in[lane * 8u + wv], wo = in[lane * 8u + 4u + wv];
+        const uint32_t we = ib[lane * 8u + wv], wo = ib[lane * 8u + 4u + wv];
         uint64_t v = spread_bits(we) | (spread_bits(wo) << 1);
 #pragma unroll
         for (int st = 0; st < 6; ++st) {
@@ -639,8 +663,8 @@ __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, con
         const uint32_t row = 64u * wv + lane;
         out[(row * 2u + 0u) * W + zb] = compact_bits(v);
         out[(row * 2u + 1u) * W + zb] = compact_bits(v >> 1);
-        __syncthreads();
     }
+    __syncthreads();
     // rows z' = 256 xg + row: parity slot p' goes to colour (p' + y + z') & 1
     for (uint32_t k = threadIdx.x; k < 512u * W; k += blockDim.x) {
         const uint32_t w = k % W, slot = (k / W) & 1u, row = k / (2u * W);
@@ -665,13 +689,15 @@ GramGeom gram_geom(uint32_t L, uint32_t NB)
     // at least two rounds of resident waves over the launch (1024 SIMDs,
     // 4 / NB waves each), chunks of at most 2048 words (all rows of a chunk:
     // 16 MiB at L = 2048, so the chunks in flight fit in the last-level
-    // cache), at least 64 words, and per-wave diagonal sums below 2^32
+    // cache), at least 64 words, fewer than 2^24 lines per chunk (each float
+    // accumulator then counts up-up pairs exactly in units of 0.25) and
+    // per-wave diagonal sums below 2^32
     const uint32_t waves = 2 * 1024 * (4 / NB);
     uint32_t nsplit = std::max((waves + g.ntile - 1) / g.ntile, (g.NK + 2047) / 2048);
     uint32_t kchunk = ((g.NK + nsplit - 1) / nsplit + 7) / 8 * 8;
     if (kchunk < 64)
         kchunk = 64;
-    const uint32_t kmax = (1u << 20) - 8;   // 32 lines per word, 128 entries per diagonal
+    const uint32_t kmax = (1u << 19) - 8;   // 32 lines per word, 128 entries per diagonal
     if (kchunk > kmax)
         kchunk = kmax;
     g.kchunk = kchunk;
@@ -748,7 +774,7 @@ hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32
         if (gram_x) {
             // x: the z axis of the lattice with x and z swapped (into Q)
             hipLaunchKernelGGL(k_bit_swap_xz, dim3(L * (W / 4)), dim3(256),
-                               (size_t)(512 * W + 512) * 4, st, L, W, P0, P1, Q0, Q1);
+                               (size_t)(512 * W + 1024) * 4, st, L, W, P0, P1, Q0, Q1);
             hipLaunchKernelGGL((k_corr_gram<2, kGramNB>), grid_gram, dim3(256), 0, st, gg, Q0, Q1,
                                anti);
         }
