@@ -2,7 +2,7 @@
 """Benchmark of the zero-temperature checkerboard quench on one MI355X.
 
 Workload: the L=2048 quench (1-bit layout, seed 3, infinite-temperature start,
-1e5 MCS) with the unsatisfied-bond count (and the accepted flips) fused into
+1e5 MCS) with the unsatisfied-bond count fused into
 the sweeps at the 40 log-spaced times (--trace-every N: every N MCS instead)
 and the axis correlation sums taken at the same times.  A
 "step" is one Monte Carlo sweep of that run, including the measurements that
@@ -32,6 +32,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 counters, per kernel (one or two sweeps per launch)
 TRAFFIC_FILES = {1: os.path.join(ROOT, "profiles", "traffic_sweep_bit_L2048.json"),
                  2: os.path.join(ROOT, "profiles", "traffic_sweep2_bit_L2048.json")}
+# VALU instructions per launch of the uncounted two-sweep kernel, from rocprofv3 counters
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_sweep2_bit_L2048.json")
+# wave64 VALU issue limit: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction
+# per SIMD every 4 cycles (16 lanes per SIMD; the same unit count gives the
+# 78.6 TFLOP/s fp64 vector peak)
+VALU_PEAK_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 KERNEL_SOURCES = ["paper_2305_12161_amd/csrc/qz_bit.hip", "paper_2305_12161_amd/csrc/qz_bit2.hip",
                   "paper_2305_12161_amd/csrc/qz_bitops.hpp", "paper_2305_12161_amd/csrc/qz_device.hpp"]
 
@@ -57,7 +63,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-corr", action="store_true", help="skip the correlation measurements")
     ap.add_argument("--trace-every", type=int, default=0,
-                    help="trace B (and accepted flips) every N MCS; 0 (default): at the 40 "
+                    help="trace B every N MCS; 0 (default): at the 40 "
                          "log-spaced times of the run, as the L=2048 configuration asks")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-replica workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-request workload")
@@ -359,7 +365,7 @@ def main():
     corr_times = [] if args.no_corr else [t for t in workloads.log_times(t_max) if W < t <= W + K]
     N = L ** 3
     every = args.trace_every
-    # sweeps whose entering B (and accepted flips) are traced: the log-spaced
+    # sweeps whose entering B is traced: the log-spaced
     # times, or every `every` MCS; the last sweep always (for the final lengths)
     if every > 0:
         trace_times = list(range(0, W + K, every))
@@ -379,7 +385,6 @@ def main():
     pcfg = lat.pass_config()
     per_launch = pcfg[0]   # sweeps carried by one launch of the dominant kernel
     trace = torch.zeros(len(trace_times), dtype=torch.int64, device="cuda")
-    flips = torch.zeros(len(trace_times), dtype=torch.int64, device="cuda")
     print(f"# L={L} seed={seed} tuning={tune} warmup={W} steps={K} corr_times={len(corr_times)}",
           file=sys.stderr, flush=True)
 
@@ -387,7 +392,7 @@ def main():
         """Sweeps t_from..t_to-1: whole launches of the pass kernel first (two
         sweeps each by default), then at most one single sweep; the traced
         times among them are listed to the library, which counts B and the
-        flips inside whichever launch runs that sweep."""
+        inside whichever launch runs that sweep."""
         n = t_to - t_from
         whole = n - n % per_launch
         for ta, m in ((t_from, whole), (t_from + whole, n - whole)):
@@ -399,8 +404,7 @@ def main():
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
                 a.record(stream)
-            lat.run_device_at(m, [x - ta for x in listed], trace[i0:i0 + len(listed)],
-                              flips[i0:i0 + len(listed)])
+            lat.run_device_at(m, [x - ta for x in listed], trace[i0:i0 + len(listed)], None)
             if timing is not None:
                 b.record(stream)
                 timing.append((a, b, m, ta, m % per_launch == 0 and m >= per_launch))
@@ -430,6 +434,11 @@ def main():
     wall = time.perf_counter() - t0
     assert lat.t == W + K
 
+    # the accepted flips of one sweep right after the window (untimed): the
+    # timed sweeps trace the bond count only, since counting the flips of a
+    # pass's first sweep makes that pass about a fifth slower
+    _, F_after = lat.run_at(2, [0])
+    flips_after = int(F_after[0])
     sweep_ms = sum(a.elapsed_time(b) for a, b, _, _, _ in timing)
     n_timed = sum(n for _, _, n, _, _ in timing)
     avg_sweep_s = sweep_ms / 1e3 / max(1, n_timed)
@@ -468,7 +477,7 @@ def main():
         lat.corr()
         corr_ms.append((time.perf_counter() - c0) * 1e3)
     corr_s = sum(corr_ms) / len(corr_ms) / 1e3 if corr_ms else 0.0
-    # whole-job rate: a sweep as timed in the window (B and flips fused at the
+    # whole-job rate: a sweep as timed in the window (B fused at the
     # traced sweeps) plus the correlation at the job's own density, 40
     # measurements per t_max sweeps.  A short window near t = 0 holds far
     # more of the log-spaced times than its share; its raw wall-clock rate is
@@ -488,6 +497,17 @@ def main():
             tr = json.load(f)
         if tr.get("kernel_sha") == kernel_sha() and tr.get("L") == L:
             traffic = tr.get("bytes_per_launch")
+    # the uncounted two-sweep kernel's VALU instructions per launch (counters),
+    # against the issue limit over the same launch time: its real bound
+    valu = None
+    if per_launch == 2 and os.path.exists(VALU_FILE):
+        with open(VALU_FILE) as f:
+            vf = json.load(f)
+        if vf.get("kernel_sha") == kernel_sha() and vf.get("L") == L:
+            instr = vf["SQ_INSTS_VALU"]
+            valu = {"wave_instr_per_launch": instr, "peak_wave_instr_per_s": VALU_PEAK_WAVE_INSTR_PER_S,
+                    "frac_t_ge_1e4": round(instr / late_launch_s / VALU_PEAK_WAVE_INSTR_PER_S, 4),
+                    "source": os.path.relpath(VALU_FILE, ROOT)}
 
     from paper_2305_12161_amd import measure
     B_last = int(trace[trace_index[W + K - 1]].item())
@@ -541,8 +561,9 @@ def main():
                              if traffic else None),
             "traffic_frac_t_ge_1e4": (round(traffic / late_launch_s / 1e9 / HBM_PEAK_GBS, 4)
                                       if traffic else None),
+            "valu": valu,
         },
-        "value_basis": ("per sweep: the timed window's sweeps (bond count and flips fused at "
+        "value_basis": ("per sweep: the timed window's sweeps (bond count fused at "
                         "the traced sweeps) plus the axis correlation charged at the job's density "
                         f"of {n_corr_job} measurements per {t_max} MCS"),
         "window_wall": {"attempts_per_ns": round(N * K / (wall * 1e9), 2),
@@ -552,12 +573,9 @@ def main():
         "corr_ms_mean": round(sum(corr_ms) / len(corr_ms), 3) if corr_ms else None,
         "corr_count": len(corr_ms),          # in the window, or one after it
         "ell_E_final": round(measure.energy_length(B_last, N), 4),
-        # accepted moves (a physics output, not the work unit): flips per site in
-        # the traced sweeps of the timed window, and in the last one
-        "accepted_flips_per_site_window_mean": round(
-            float(flips[window].double().mean().item()) / N, 7),
-        "accepted_flips_per_site_last": round(
-            int(flips[trace_index[W + K - 1]].item()) / N, 7),
+        # accepted moves (a physics output, not the work unit): spins flipped
+        # per site by the sweep right after the window, taken apart from it
+        "accepted_flips_per_site_after_window": round(flips_after / N, 7),
         "ell_C_final": (round(measure.crossing_length(ells[-1][1], ells[-1][2], N), 4)
                         if ells else None),
     }
