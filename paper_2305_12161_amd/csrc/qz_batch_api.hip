@@ -190,6 +190,13 @@ void drop_graph(qz_batch *b)
     b->graph_ok = false;
 }
 
+void release_streams(qz_batch *b)
+{
+    if (b->cap_st)
+        (void)hipStreamDestroy(b->cap_st);
+    b->cap_st = nullptr;
+}
+
 int check(qz_batch *b)
 {
     if (!b)
@@ -364,13 +371,17 @@ int autotune(qz_batch *b)
         return dev_fail(b, e, "hipEventCreate");
     }
     int rc = QZ_OK;
-    const uint32_t warm = 2, timed = 8;
+    // groups as long as the graphs will be (up to 16 sweeps): the on-chip
+    // kernel reads and writes its replicas once per group
+    const uint32_t G = std::max<uint32_t>(
+        1u, std::min<uint32_t>({b->graph_sweeps ? b->graph_sweeps : 1u, 16u, group_limit(b)}));
+    const uint32_t timed = std::max<uint32_t>(1u, 16u / G);
     auto time_batch = [&](float *ms) -> int {
-        hipError_t x = enqueue_group(b, b->st, warm);
+        hipError_t x = enqueue_group(b, b->st, G);
         if (x == hipSuccess)
             x = hipEventRecord(e0, b->st);
         for (uint32_t k = 0; x == hipSuccess && k < timed; ++k)
-            x = enqueue_group(b, b->st, 1);
+            x = enqueue_group(b, b->st, G);
         if (x == hipSuccess)
             x = hipEventRecord(e1, b->st);
         if (x == hipSuccess)
@@ -537,7 +548,7 @@ QZ_EXPORT int qz_batch_create(const qz_replica_spec *specs, size_t n, uint32_t t
             rc = draw_starts(b);
     }
     if (rc != QZ_OK) {
-        (void)hipStreamDestroy(b->cap_st);
+        release_streams(b);
         delete b;
         return rc;
     }
@@ -550,8 +561,7 @@ QZ_EXPORT int qz_batch_destroy(qz_batch *b)
     if (!b)
         return fail(QZ_EINVAL, "null batch handle");
     drop_graph(b);
-    if (b->cap_st)
-        (void)hipStreamDestroy(b->cap_st);
+    release_streams(b);
     delete b;
     return QZ_OK;
 }

@@ -55,7 +55,10 @@ def batch_tuning_json(sizes):
     if not sizes or any(str(L) not in d for L in sizes):
         return None
     graph = min(int(d[str(L)]["graph_sweeps"]) for L in sizes)
-    return json.dumps({"graph_sweeps": graph, "tz": {str(L): int(d[str(L)]["Tz"]) for L in sizes}})
+    out = {"graph_sweeps": graph, "tz": {str(L): int(d[str(L)]["Tz"]) for L in sizes}}
+    if 64 in sizes and "onchip" in d["64"]:
+        out["onchip"] = int(d["64"]["onchip"])
+    return json.dumps(out)
 
 
 def single_candidates(L: int):
@@ -159,8 +162,8 @@ def tune_batch(specs, sweeps: int = 200, verbose: bool = True):
     chosen = {L: None for L in sizes}
     results = {}
 
-    def time_batch(tz, graph):
-        b = binding.Batch(specs, tuning={"graph_sweeps": graph,
+    def time_batch(tz, graph, onchip=0):
+        b = binding.Batch(specs, tuning={"graph_sweeps": graph, "onchip": onchip,
                                          "tz": {str(L): v for L, v in tz.items() if v}})
         b.run(graph)
         b.sync()
@@ -182,9 +185,16 @@ def tune_batch(specs, sweeps: int = 200, verbose: bool = True):
             if L not in results or ms < results[L][1]:
                 results[L] = (Tz, ms)
         chosen[L] = results[L][0]
+    # side-64 replicas on chip (all sweeps of a graph in one launch) or as sub-tiles
+    onchip = 0
+    if 64 in sizes:
+        t_sub, t_chip = time_batch(chosen, 50, 0), time_batch(chosen, 50, 1)
+        if verbose:
+            print(json.dumps({"onchip": {"0": round(t_sub, 5), "1": round(t_chip, 5)}}), flush=True)
+        onchip = int(t_chip < t_sub)
     best_graph = None
     for gs in (10, 25, 50, 100, 200):
-        ms = time_batch(chosen, gs)
+        ms = time_batch(chosen, gs, onchip)
         if verbose:
             print(json.dumps({"graph_sweeps": gs, "ms_per_sweep": round(ms, 5)}), flush=True)
         if best_graph is None or ms < best_graph[1]:
@@ -192,6 +202,8 @@ def tune_batch(specs, sweeps: int = 200, verbose: bool = True):
     d = _load()
     for L in sizes:
         d["batch"][str(L)] = {"Tz": chosen[L], "graph_sweeps": best_graph[0]}
+        if L == 64:
+            d["batch"][str(L)]["onchip"] = onchip
     _save(d)
     return chosen, best_graph
 
