@@ -20,6 +20,7 @@ Results never depend on what else is running: every lattice follows exactly
 its own (L, seed) trajectory.
 """
 import collections
+import concurrent.futures
 import time
 from dataclasses import dataclass
 from typing import Dict, List, Optional
@@ -63,11 +64,19 @@ class GpuBackend:
         self.torch = torch
         self.every, self.chunk = every, chunk
         self.device = torch.device("cuda") if device is None else torch.device(device)
-        self.stream = torch.cuda.current_stream(self.device)
+        # the batch's own stream (default priority): synchronising it never
+        # waits for the single lattices' streams
+        self.stream = torch.cuda.Stream(device=self.device)
         # single lattices are spread over a few streams (default priority) so
         # that the short sweeps of mid-size lattices overlap on the GPU
         self.single_streams = [torch.cuda.Stream(device=self.device) for _ in range(single_streams)]
         self._next_stream = 0
+        # one host thread per stream enqueues the single lattices' runs: a run
+        # is thousands of launches, and the library call releases the
+        # interpreter lock, so the streams are fed in parallel while the
+        # serving loop goes on
+        self._feeders = [concurrent.futures.ThreadPoolExecutor(max_workers=1)
+                         for _ in self.single_streams]
         # sweeps per pass of the single bit lattices (two halves the launches
         # per chunk; the trajectories are the same)
         self.single_pass = single_pass
@@ -126,8 +135,8 @@ class GpuBackend:
             self.batch.replace(slot, req.L, req.seed, req.t_max)
             self.live[req.idx] = {"kind": "batch", "slot": slot, "t": 0, "t_max": req.t_max}
             return
-        st = self.single_streams[self._next_stream % len(self.single_streams)] \
-            if self.single_streams else self.stream
+        wi = self._next_stream % len(self.single_streams) if self.single_streams else -1
+        st = self.single_streams[wi] if self.single_streams else self.stream
         self._next_stream += 1
         # the library zeroes each trace chunk on the lattice's stream before
         # writing it; every earlier use of this memory ended at the last sync()
@@ -139,7 +148,7 @@ class GpuBackend:
         self.single_used += self.single_bytes(req.L)
         self.live[req.idx] = {"kind": "single", "lat": lat, "trace": tr, "t": 0,
                               "t_max": req.t_max, "bytes": self.single_bytes(req.L),
-                              "stream": st}
+                              "stream": st, "feeder": wi}
 
     def advance(self) -> None:
         """One chunk of sweeps for every live lattice (asynchronous); the
@@ -167,16 +176,32 @@ class GpuBackend:
     # requests whose work has completed, kick() starts the batch's next chunk.
     def start(self, idx: int) -> None:
         p = self.live[idx]
-        if p["kind"] == "single":
-            p["lat"].run_device(p["t_max"], self.every, p["trace"])
-            ev = self.torch.cuda.Event()
-            ev.record(p["stream"])
-            p["event"] = ev
+        if p["kind"] != "single":
+            return
+        torch, device = self.torch, self.device
+
+        def feed():
+            with torch.cuda.device(device):
+                p["lat"].run_device(p["t_max"], self.every, p["trace"])
+                ev = torch.cuda.Event()
+                ev.record(p["stream"])
+            return ev
+
+        if p["feeder"] >= 0:
+            p["future"] = self._feeders[p["feeder"]].submit(feed)
+        else:
+            p["event"] = feed()
 
     def poll(self) -> List[int]:
         out = []
         for i, p in self.live.items():
-            if p["kind"] == "single" and p.get("event") is not None and p["event"].query():
+            if p["kind"] != "single":
+                continue
+            fut = p.get("future")
+            if fut is not None and fut.done():
+                p["event"] = fut.result()        # raises what the feeder raised
+                p["future"] = None
+            if p.get("event") is not None and p["event"].query():
                 p["t"] = p["t_max"]
                 out.append(i)
         if self._batch_event is not None and self._batch_event.query():
@@ -216,7 +241,14 @@ class GpuBackend:
             L = self.batch.specs[slot][0]
             self.free_batch[L].append(slot)
         else:
-            trace = p["trace"].cpu().numpy().astype(np.int64)
+            # an asynchronous copy into pinned memory on the lattice's own
+            # stream, whose work is complete: a plain copy to pageable memory
+            # would wait for every stream on the device
+            host = self.torch.empty(p["trace"].numel(), dtype=p["trace"].dtype, pin_memory=True)
+            with self.torch.cuda.stream(p["stream"]):
+                host.copy_(p["trace"], non_blocking=True)
+            p["stream"].synchronize()
+            trace = host.numpy().astype(np.int64)
             final_B = int(p["lat"].bonds().sum())
             p["lat"].close()
             self.single_used -= p["bytes"]
