@@ -143,6 +143,13 @@ int qz_run_device_at(qz_lattice *q, uint64_t n_sweeps, const uint64_t *at, size_
 /* Per-axis unsatisfied-bond counts [B_x, B_y, B_z] of the current state. */
 int qz_bonds(qz_lattice *q, uint64_t out_B_axes[3]);
 
+/* As qz_bonds, but the three counts go to caller device memory dev_B_axes
+ * (8-byte aligned, zeroed by the library) on the lattice's stream, and the
+ * call never synchronises: a caller can enqueue it behind a run and read the
+ * counts when its own event on that stream has completed.  Errors: QZ_EINVAL
+ * (null or misaligned pointer), QZ_ESTATE, QZ_EDEVICE. */
+int qz_bonds_device(qz_lattice *q, uint64_t *dev_B_axes);
+
 /* Axis correlation sums of the current state: out_S[a*(L/2+1) + r] = S_a(r)
  * for a = 0 (x), 1 (y), 2 (z) and r = 0..L/2, and *out_M = M.  For the bit
  * layout with L a multiple of 256 they come from the matrix cores (Gram

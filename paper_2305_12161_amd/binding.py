@@ -41,6 +41,7 @@ def _load():
         "qz_run_at": ([vp, u64, c.POINTER(u64), sz, c.POINTER(u64), c.POINTER(u64)], i32),
         "qz_run_device_at": ([vp, u64, c.POINTER(u64), sz, vp, vp], i32),
         "qz_bonds": ([vp, c.POINTER(u64)], i32),
+        "qz_bonds_device": ([vp, vp], i32),
         "qz_corr": ([vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64)], i32),
         "qz_corr_noalloc": ([vp, c.POINTER(c.c_int64), c.POINTER(c.c_int64)], i32),
         "qz_time": ([vp, c.POINTER(u64)], i32),
@@ -111,8 +112,11 @@ class Lattice:
             code = QZ_EUNSUPPORTED if (L >= 4 and L % 2 == 0) else QZ_EINVAL
             raise QuenchError(code, f"L={L} is not valid for the {layout} layout")
         device = torch.device("cuda") if device is None else torch.device(device)
-        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream, sh = _stream_handle(stream)
+        # allocated from the pool of the stream that uses it: when the lattice
+        # is dropped, the memory is reused only behind the work queued there
+        with torch.cuda.stream(self.stream):
+            self.mem = torch.empty(nbytes, dtype=torch.uint8, device=device)
         h = ctypes.c_void_p()
         _check(lib.qz_create(self.L, self.seed & (2**64 - 1), LAYOUTS[layout],
                              ctypes.c_void_p(self.mem.data_ptr()), nbytes, sh, ctypes.byref(h)))
@@ -193,6 +197,11 @@ class Lattice:
         out = np.zeros(3, dtype=np.uint64)
         _check(lib.qz_bonds(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
         return out.astype(np.int64)
+
+    def bonds_device(self, dev_out) -> None:
+        """Asynchronous bonds(): [B_x, B_y, B_z] into the first three values of
+        a 64-bit device tensor, on the lattice's stream."""
+        _check(lib.qz_bonds_device(self._h, _dev_buf(dev_out, 3)))
 
     def corr(self):
         R = self.L // 2 + 1
@@ -353,8 +362,9 @@ class Batch:
         if isinstance(tuning, dict):
             tuning = json.dumps(tuning)
         device = torch.device("cuda") if device is None else torch.device(device)
-        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.stream, sh = _stream_handle(stream)
+        with torch.cuda.stream(self.stream):
+            self.mem = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.trace_every, self.trace_cap = int(trace_every), int(trace_cap)
         h = ctypes.c_void_p()
         _check(lib.qz_batch_create(arr, len(self.specs), self.trace_every, self.trace_cap,

@@ -573,6 +573,22 @@ QZ_EXPORT int qz_bonds(qz_lattice *q, uint64_t out_B_axes[3])
     return QZ_OK;
 }
 
+QZ_EXPORT int qz_bonds_device(qz_lattice *q, uint64_t *dev_B_axes)
+{
+    int rc = check_handle(q);
+    if (rc != QZ_OK)
+        return rc;
+    if (!dev_B_axes || (reinterpret_cast<uintptr_t>(dev_B_axes) & 7u))
+        return fail(QZ_EINVAL, "null or misaligned device output");
+    unsigned long long *c = reinterpret_cast<unsigned long long *>(dev_B_axes);
+    QZ_HIP(q, qz::fill_u64(q->st, c, 3, 0ull));
+    if (q->layout == QZ_LAYOUT_I8)
+        QZ_HIP(q, qz::i8_bonds(q->st, q->L, i8_spins(q), c));
+    else
+        QZ_HIP(q, qz::bit_bonds(q->st, q->L, bit_plane(q, q->cur, 0), bit_plane(q, q->cur, 1), c));
+    return QZ_OK;
+}
+
 QZ_EXPORT int qz_corr(qz_lattice *q, int64_t *out_S, int64_t *out_M)
 {
     int rc = check_handle(q);

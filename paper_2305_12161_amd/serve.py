@@ -138,17 +138,29 @@ class GpuBackend:
         wi = self._next_stream % len(self.single_streams) if self.single_streams else -1
         st = self.single_streams[wi] if self.single_streams else self.stream
         self._next_stream += 1
-        # the library zeroes each trace chunk on the lattice's stream before
-        # writing it; every earlier use of this memory ended at the last sync()
-        tr = self.torch.empty(req.t_max // self.every, dtype=self.torch.int64, device=self.device)
-        lat = self.qz.Lattice(req.L, req.seed, self.layout_for(req.L), device=self.device,
-                              stream=st)
-        if self.layout_for(req.L) == "bit" and self.single_pass:
-            lat.set_pass(self.single_pass)
+        # the memory is booked here; the lattice itself is made by whoever
+        # enqueues its work (a feeder thread in the asynchronous protocol),
+        # since its first kernel may have to wait for room in a busy queue
         self.single_used += self.single_bytes(req.L)
-        self.live[req.idx] = {"kind": "single", "lat": lat, "trace": tr, "t": 0,
+        self.live[req.idx] = {"kind": "single", "L": req.L, "seed": req.seed, "t": 0,
                               "t_max": req.t_max, "bytes": self.single_bytes(req.L),
                               "stream": st, "feeder": wi}
+
+    def _materialize(self, p) -> None:
+        """Device state of a single lattice: the lattice and its trace buffer
+        (the trace, then the three final bond counts; the library zeroes each
+        part on the lattice's stream before writing it), both from the pool of
+        the lattice's stream."""
+        if "lat" in p:
+            return
+        with self.torch.cuda.device(self.device), self.torch.cuda.stream(p["stream"]):
+            p["trace"] = self.torch.empty(p["t_max"] // self.every + 3, dtype=self.torch.int64,
+                                          device=self.device)
+            lat = self.qz.Lattice(p["L"], p["seed"], self.layout_for(p["L"]), device=self.device,
+                                  stream=p["stream"])
+        if self.layout_for(p["L"]) == "bit" and self.single_pass:
+            lat.set_pass(self.single_pass)
+        p["lat"] = lat
 
     def advance(self) -> None:
         """One chunk of sweeps for every live lattice (asynchronous); the
@@ -157,6 +169,7 @@ class GpuBackend:
             self.batch.run(self.chunk)
         for p in self.live.values():
             if p["kind"] == "single" and p["t"] < p["t_max"]:
+                self._materialize(p)
                 t = p["t"]
                 sl = p["trace"][t // self.every: (t + self.chunk) // self.every]
                 p["lat"].run_device(self.chunk, self.every, sl)
@@ -180,11 +193,23 @@ class GpuBackend:
             return
         torch, device = self.torch, self.device
 
+        n = p["t_max"] // self.every
+
         def feed():
+            # the lattice, its whole quench, the final bond counts and the
+            # download of both into pinned memory, then the event: retiring the
+            # request reads host memory only, and never waits for later work
+            # that other lattices have queued on the same stream
+            self._materialize(p)
             with torch.cuda.device(device):
-                p["lat"].run_device(p["t_max"], self.every, p["trace"])
+                p["lat"].run_device(p["t_max"], self.every, p["trace"][:n])
+                p["lat"].bonds_device(p["trace"][n:])
+                host = torch.empty(n + 3, dtype=torch.int64, pin_memory=True)
+                with torch.cuda.stream(p["stream"]):
+                    host.copy_(p["trace"], non_blocking=True)
                 ev = torch.cuda.Event()
                 ev.record(p["stream"])
+            p["host"] = host
             return ev
 
         if p["feeder"] >= 0:
@@ -233,6 +258,13 @@ class GpuBackend:
     def retire(self, idx: int) -> dict:
         p = self.live.pop(idx)
         n = p["t_max"] // self.every
+        if p.get("host") is not None:
+            # filled on the lattice's stream before the event that finished
+            # it: no device call here
+            out = p["host"].numpy()
+            p["lat"].close()
+            self.single_used -= p["bytes"]
+            return {"trace": out[:n].astype(np.int64), "final_B": int(out[n:n + 3].sum())}
         if p["kind"] == "batch":
             slot = p["slot"]
             trace = self.batch.trace(slot, 0, n).astype(np.int64)
@@ -244,9 +276,9 @@ class GpuBackend:
             # an asynchronous copy into pinned memory on the lattice's own
             # stream, whose work is complete: a plain copy to pageable memory
             # would wait for every stream on the device
-            host = self.torch.empty(p["trace"].numel(), dtype=p["trace"].dtype, pin_memory=True)
+            host = self.torch.empty(n, dtype=p["trace"].dtype, pin_memory=True)
             with self.torch.cuda.stream(p["stream"]):
-                host.copy_(p["trace"], non_blocking=True)
+                host.copy_(p["trace"][:n], non_blocking=True)
             p["stream"].synchronize()
             trace = host.numpy().astype(np.int64)
             final_B = int(p["lat"].bonds().sum())

@@ -376,6 +376,14 @@ def test_bonds_and_corr_match_oracle(qz, orc, layout, L):
             orc.run(s, seed, lat.t - n, n)
         assert np.array_equal(lat.download(), s)
         assert np.array_equal(lat.bonds(), orc.bonds(s))
+        # the asynchronous form, into device memory after a stale fill
+        import torch
+        dev = torch.full((5,), -1, dtype=torch.int64, device="cuda")
+        lat.bonds_device(dev[1:])
+        torch.cuda.synchronize()
+        got = dev.cpu().numpy()
+        assert got[0] == -1 and got[4] == -1
+        assert np.array_equal(got[1:4], orc.bonds(s))
         S, M = lat.corr()
         So, Mo = orc.corr(s)
         assert M == Mo
