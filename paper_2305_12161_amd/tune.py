@@ -154,44 +154,53 @@ def tune_single(L: int, sweeps: int = 30, verbose: bool = True):
     return best
 
 
-def tune_batch(specs, sweeps: int = 200, verbose: bool = True):
-    """Per lattice size of the batch: planes per sub-tile, then sweeps per graph."""
+def tune_batch(specs, sweeps: int = 10000, verbose: bool = True):
+    """The on-chip path for side 64, then planes per sub-tile for every side
+    the sub-tile launch runs, then sweeps per graph.  Each candidate runs the whole
+    job of `sweeps` MCS from the random start: the cost of a sweep falls as the
+    domains grow (fewer spins flip), so timing only the first sweeps would
+    weigh the early times the job barely spends any time in."""
     import torch
     from . import binding
     sizes = sorted({L for L, _ in specs})
     chosen = {L: None for L in sizes}
     results = {}
+    warm = 200          # a multiple of every graph length tried; captures the graphs
 
     def time_batch(tz, graph, onchip=0):
         b = binding.Batch(specs, tuning={"graph_sweeps": graph, "onchip": onchip,
                                          "tz": {str(L): v for L, v in tz.items() if v}})
-        b.run(graph)
+        b.run(warm)
         b.sync()
         t0 = time.perf_counter()
-        b.run(sweeps)
+        b.run(sweeps - warm)
         b.sync()
-        ms = (time.perf_counter() - t0) * 1e3 / sweeps
+        ms = (time.perf_counter() - t0) * 1e3 / (sweeps - warm)
         del b
         torch.cuda.empty_cache()
         return ms
 
-    for L in sizes:
-        for Tz in (2, 4, 8, 16, 32):
-            if Tz > L or L % Tz:
-                continue
-            ms = time_batch({**chosen, L: Tz}, 50)
-            if verbose:
-                print(json.dumps({"L": L, "Tz": Tz, "ms_per_sweep": round(ms, 5)}), flush=True)
-            if L not in results or ms < results[L][1]:
-                results[L] = (Tz, ms)
-        chosen[L] = results[L][0]
-    # side-64 replicas on chip (all sweeps of a graph in one launch) or as sub-tiles
+    # side-64 replicas on chip (all sweeps of a graph in one launch) or as
+    # sub-tiles; decided first, since it changes how many sub-tiles the other
+    # sides share the sweep launch with
     onchip = 0
     if 64 in sizes:
         t_sub, t_chip = time_batch(chosen, 50, 0), time_batch(chosen, 50, 1)
         if verbose:
             print(json.dumps({"onchip": {"0": round(t_sub, 5), "1": round(t_chip, 5)}}), flush=True)
         onchip = int(t_chip < t_sub)
+    for L in sizes:
+        if L == 64 and onchip:
+            continue
+        for Tz in (2, 4, 8, 16, 32):
+            if Tz > L or L % Tz:
+                continue
+            ms = time_batch({**chosen, L: Tz}, 50, onchip)
+            if verbose:
+                print(json.dumps({"L": L, "Tz": Tz, "ms_per_sweep": round(ms, 5)}), flush=True)
+            if L not in results or ms < results[L][1]:
+                results[L] = (Tz, ms)
+        chosen[L] = results[L][0]
     best_graph = None
     for gs in (10, 25, 50, 100, 200):
         ms = time_batch(chosen, gs, onchip)
@@ -201,7 +210,7 @@ def tune_batch(specs, sweeps: int = 200, verbose: bool = True):
             best_graph = (gs, ms)
     d = _load()
     for L in sizes:
-        d["batch"][str(L)] = {"Tz": chosen[L], "graph_sweeps": best_graph[0]}
+        d["batch"][str(L)] = {"Tz": chosen[L] or 8, "graph_sweeps": best_graph[0]}
         if L == 64:
             d["batch"][str(L)]["onchip"] = onchip
     _save(d)
