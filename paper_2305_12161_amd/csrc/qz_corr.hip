@@ -376,16 +376,17 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 // The 32 lines of a word as 32 four-bit E2M1 values, 0 (down) or 0.5 (up,
-// code 0001): dword d holds bits d, 4 + d, ..., 28 + d in its eight nibbles.
+// code 0001): dword d holds bits d, 4 + d, ..., 28 + d in its eight nibbles
+// (mask 0x11111111; mask 0 gives all zeros).
 // Every operand expands its words the same way, so both sides of an
 // instruction pair the same lines; the upper four dwords are not read.
-__device__ __forceinline__ v8i expand_fp4(uint32_t y)
+__device__ __forceinline__ v8i expand_fp4(uint32_t y, uint32_t mask)
 {
     v8i f;
-    f[0] = (int)(y & 0x11111111u);
-    f[1] = (int)((y >> 1) & 0x11111111u);
-    f[2] = (int)((y >> 2) & 0x11111111u);
-    f[3] = (int)((y >> 3) & 0x11111111u);
+    f[0] = (int)(y & mask);
+    f[1] = (int)((y >> 1) & mask);
+    f[2] = (int)((y >> 2) & mask);
+    f[3] = (int)((y >> 3) & mask);
     f[4] = f[5] = f[6] = f[7] = 0;
     return f;
 }
@@ -431,57 +432,67 @@ __global__ void __launch_bounds__(256, 4 / NB) k_corr_gram(GramGeom g, const uin
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 acc[m][n][r] = 0.0f;
-    auto row_words = [&](uint32_t u, uint32_t o, uint32_t p, uint32_t w) -> uint4 {
-        const uint32_t *P = ((p + u + o) & 1u) ? P1 : P0;
-        const size_t off = (AX == 1) ? ((size_t)o * L + u) * W + w : ((size_t)u * L + o) * W + w;
-        return *reinterpret_cast<const uint4 *>(P + off);
-    };
-    // Software pipeline over the instruction steps (4 per 8 words): the words
-    // of the next 8 are loaded while these are multiplied, and the operands
-    // of the next step are expanded between the MFMAs of this one.
-    uint4 na[4], nb[NB];
-    auto fetch = [&](uint32_t k0) {
-        const uint32_t kk = k0 + 4u * h;
+    // Word kk of row u sits at word offset roff(u) + koff(kk) of colour plane
+    // (p + u + o) & 1: roff = u W for y (o = z), u L W for z (o = y).  Every
+    // row of a lane has the parity of i, so one plane serves all its rows.
+    const uint32_t roffs = (AX == 1) ? W : L * W;
+    uint32_t ra[4], rb[NB];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        ra[m] = (bi * kGramTile + 32u * m + i) * roffs;
+#pragma unroll
+    for (int n = 0; n < NB; ++n)
+        rb[n] = (bj * g.CW + 32u * n + i) * roffs;
+    // Words come in groups of 8 (4 instruction steps).  Three groups are in
+    // flight in three named buffers, so that a group's loads are issued about
+    // two groups of multiplies before their first use (with one buffer copied
+    // into another each group, the compiler waits for the loads at the top of
+    // the next group instead).  The loop runs a multiple of 3 groups with no
+    // branch inside, since a branch makes the compiler wait for every load at
+    // the loop's head: a group past the chunk reloads the last group and is
+    // multiplied with its A operand masked to zero, adding nothing.
+    const uint32_t ng = (k_end - k_begin) / 8u;
+    auto fetch = [&](uint4 (&xa)[4], uint4 (&xb)[NB], uint32_t gi) {
+        const uint32_t kk = k_begin + 8u * min(gi, ng - 1u) + 4u * h;
         const uint32_t o = kk / W2, p = (kk / W) & 1u, w = kk % W;
+        const uint32_t koff = (AX == 1) ? o * L * W + w : o * W + w;
+        const uint32_t *P = ((p + i + o) & 1u) ? P1 : P0;
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-            na[m] = row_words(bi * kGramTile + 32u * m + i, o, p, w);
+            xa[m] = *reinterpret_cast<const uint4 *>(P + (ra[m] + koff));
 #pragma unroll
         for (int n = 0; n < NB; ++n)
-            nb[n] = row_words(bj * g.CW + 32u * n + i, o, p, w);
+            xb[n] = *reinterpret_cast<const uint4 *>(P + (rb[n] + koff));
     };
     auto word = [](const uint4 &q, int s) -> uint32_t {
         return s == 0 ? q.x : s == 1 ? q.y : s == 2 ? q.z : q.w;
     };
-    fetch(k_begin);
-    uint4 ca[4], cb[NB];   // words of the current 4 steps
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-        ca[m] = na[m];
-#pragma unroll
-    for (int n = 0; n < NB; ++n)
-        cb[n] = nb[n];
-    fetch(min(k_begin + 8u, k_end - 8u));
+    // expansion mask of group gi's A operands: zero past the chunk
+    auto amask = [&](uint32_t gi) -> uint32_t { return gi < ng ? 0x11111111u : 0u; };
+    uint4 a0[4], b0[NB], a1[4], b1[NB], a2[4], b2[NB];
+    fetch(a0, b0, 0u);
+    fetch(a1, b1, 1u);
+    fetch(a2, b2, 2u);
     v8i fa[4], fb[NB];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-        fa[m] = expand_fp4(ca[m].x);
+        fa[m] = expand_fp4(a0[m].x, amask(0u));
 #pragma unroll
     for (int n = 0; n < NB; ++n)
-        fb[n] = expand_fp4(cb[n].x);
-    for (uint32_t k0 = k_begin; k0 < k_end; k0 += 8u) {
-        __builtin_amdgcn_sched_barrier(0);
+        fb[n] = expand_fp4(b0[n].x, 0x11111111u);
+    // the 4 steps of one group (words ca, cb, A mask mc); the last step
+    // expands the first word of the next group (na, nb, mask mn)
+    auto group = [&](const uint4 (&ca)[4], const uint4 (&cb)[NB], uint32_t mc,
+                     const uint4 (&na)[4], const uint4 (&nb)[NB], uint32_t mn) {
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
-            // next step's operands: word st + 1, after the 4th step the first
-            // of the prefetched words
             v8i ga[4], gb[NB];
 #pragma unroll
             for (int m = 0; m < 4; ++m)
-                ga[m] = expand_fp4(st < 3 ? word(ca[m], st + 1) : na[m].x);
+                ga[m] = st < 3 ? expand_fp4(word(ca[m], st + 1), mc) : expand_fp4(na[m].x, mn);
 #pragma unroll
             for (int n = 0; n < NB; ++n)
-                gb[n] = expand_fp4(st < 3 ? word(cb[n], st + 1) : nb[n].x);
+                gb[n] = expand_fp4(st < 3 ? word(cb[n], st + 1) : nb[n].x, 0x11111111u);
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -502,14 +513,14 @@ __global__ void __launch_bounds__(256, 4 / NB) k_corr_gram(GramGeom g, const uin
             for (int n = 0; n < NB; ++n)
                 fb[n] = gb[n];
         }
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            ca[m] = na[m];
-#pragma unroll
-        for (int n = 0; n < NB; ++n)
-            cb[n] = nb[n];
-        fetch(min(k0 + 16u, k_end - 8u));   // the last steps reload their own words
-        __builtin_amdgcn_sched_barrier(0);
+    };
+    for (uint32_t gi = 0; gi < ng; gi += 3u) {
+        group(a0, b0, amask(gi), a1, b1, amask(gi + 1u));
+        fetch(a0, b0, gi + 3u);
+        group(a1, b1, amask(gi + 1u), a2, b2, amask(gi + 2u));
+        fetch(a1, b1, gi + 4u);
+        group(a2, b2, amask(gi + 2u), a0, b0, amask(gi + 3u));
+        fetch(a2, b2, gi + 5u);
     }
     // diagonals of the tile: entry (row, col) of block (m, n) in register r of
     // this lane is row 32 m + 8 (r / 4) + 4 h + r % 4, column 32 n + i; its
@@ -569,32 +580,65 @@ __global__ void k_corr_gram_finish(unsigned long long *tb, uint32_t R, uint32_t 
 // Swap the x and z axes of a 1-bit lattice into Q: Q holds the lattice s' with
 // s'(x', y, z') = s(z', y, x'), in the same colour-separated layout (the
 // colour x + y + z is unchanged), so the z-axis sums of Q are the x-axis sums
-// of P and the x axis can run on the matrix cores too.  A wave turns a 64 x 64
-// block (z, x) into a 64-bit row per lane (x = 64 xb + 2 b + p at bit
-// 2 b + p), transposes it across the wave in six exchange steps, and lane l
-// then holds word zb of the two colour rows of Q's row (z' = 64 xb + l, y).
+// of P and the x axis can run on the matrix cores too.
+//
+// A block of 64 z by 64 x sites splits by the parities of z and x into four
+// 32 x 32 bit matrices: with z = 2 zh + p and x = 2 xh + q, the word of the
+// x-parity slot q in row z holds bits xh of M_pq[zh].  The word of Q's row
+// z' = x, slot p (the parity of x' = z), holds bit zh of the transpose of
+// M_pq.  A wave holds the 64 rows z of a block, one per lane, with p at lane
+// bit 2 and the five bits of zh at lane bits 0, 1, 3, 4, 5, and transposes
+// its two words (q = 0, 1) in five steps; step j exchanges with the lane that
+// differs in the lane bit of zh's bit j (lane xor 1, 2, 8, 16, 32: quad
+// permutes, a row rotation and the two lane-half swaps, all without LDS)
+// and moves j x j bit blocks with a rotate and a bit select.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t spread_bits(uint32_t v)
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, int lx)
 {
-    uint64_t x = v;
-    x = (x | x << 16) & 0x0000FFFF0000FFFFull;
-    x = (x | x << 8) & 0x00FF00FF00FF00FFull;
-    x = (x | x << 4) & 0x0F0F0F0F0F0F0F0Full;
-    x = (x | x << 2) & 0x3333333333333333ull;
-    x = (x | x << 1) & 0x5555555555555555ull;
-    return x;
+    if (lx == 1)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // quad [1,0,3,2]
+    if (lx == 2)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // quad [2,3,0,1]
+    if (lx == 8)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false); // row_ror:8
+    // the swaps return this lane's own value in one result and the partner's
+    // in the other (equal values make either choice right)
+    if (lx == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return r[0] == v ? r[1] : r[0];
+    }
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return r[0] == v ? r[1] : r[0];
 }
 
-__device__ __forceinline__ uint32_t compact_bits(uint64_t v)
+// One transposition step on the 32-bit row v of this lane: bits k with
+// (k & j) != 0 of the lane whose zh bit j is clear (a) trade places with bits
+// k - j of its partner (b).  a keeps its bits in m and takes the partner's
+// rotated left by j elsewhere; b keeps the bits outside m and takes the
+// partner's rotated right by j in m.
+template <int J, int LX>
+__device__ __forceinline__ uint32_t transpose_step(uint32_t v, uint32_t lane)
 {
-    uint64_t x = v & 0x5555555555555555ull;
-    x = (x | x >> 1) & 0x3333333333333333ull;
-    x = (x | x >> 2) & 0x0F0F0F0F0F0F0F0Full;
-    x = (x | x >> 4) & 0x00FF00FF00FF00FFull;
-    x = (x | x >> 8) & 0x0000FFFF0000FFFFull;
-    x = (x | x >> 16) & 0x00000000FFFFFFFFull;
-    return (uint32_t)x;
+    constexpr uint32_t m = J == 1 ? 0x55555555u : J == 2 ? 0x33333333u : J == 4 ? 0x0F0F0F0Fu
+                         : J == 8 ? 0x00FF00FFu : 0x0000FFFFu;
+    const uint32_t o = xor_lane(v, LX);
+    const bool a = (lane & LX) == 0;
+    const uint32_t t = __builtin_amdgcn_alignbit(o, o, a ? 32 - J : J);
+    const uint32_t keep = a ? m : ~m;
+    return (v & keep) | (t & ~keep);
 }
+
+__device__ __forceinline__ uint32_t transpose32(uint32_t v, uint32_t lane)
+{
+    v = transpose_step<1, 1>(v, lane);
+    v = transpose_step<2, 2>(v, lane);
+    v = transpose_step<4, 8>(v, lane);
+    v = transpose_step<8, 16>(v, lane);
+    return transpose_step<16, 32>(v, lane);
+}
+
+constexpr uint32_t kSwapIn = 520;      // words of a block in LDS: [slot][word][65 rows, padded]
+constexpr uint32_t kSwapOut = 514;     // words per zb in LDS: [row pair][slot][row parity], padded
 
 __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, const uint32_t *P0,
                                                     const uint32_t *P1, uint32_t *Q0, uint32_t *Q1)
@@ -604,73 +648,74 @@ __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, con
     // [256 xg, 256 xg + 256) in LDS, block zb by block zb, and writes them
     // out whole.
     extern __shared__ uint32_t sm[];
-    uint32_t *out = sm;                   // [256 rows][2 parity slots][W]: slot 0 = even x'
-    uint32_t *in = sm + 512u * W;         // [2 buffers][64 rows z][2 parity slots][4 words]
+    uint32_t *out = sm;                   // [zb][128 row pairs][2 slots][2 rows]
+    uint32_t *in = sm + kSwapOut * W;     // [2 buffers][2 blocks][kSwapIn]
     const uint32_t ngroups = W / 4;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // a y's groups share an XCD
     const uint32_t y = tile / ngroups, xg = tile % ngroups;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    constexpr uint64_t kMask[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
-                                   0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
-                                   0x3333333333333333ull, 0x5555555555555555ull};
-    // words 4 xg .. 4 xg + 3 of rows z = 64 zb + r, both parities: entry
-    // k = threadIdx.x + 256 i of block zb.  Blocks are loaded kAhead ahead,
-    // so that several loads per lane are in flight (the loads of one block
-    // are small: without depth the kernel waits on their latency).
-    auto fetch = [&](uint32_t zb, uint32_t i) -> uint32_t {
-        const uint32_t k = threadIdx.x + 256u * i;
-        const uint32_t j = k & 3u, slot = (k >> 2) & 1u, r = k >> 3;
-        const uint32_t z = 64u * zb + r;
-        const uint32_t c = slot ^ ((y + z) & 1u);   // colour holding the parity slot
-        return (c ? P1 : P0)[((size_t)z * L + y) * W + 4u * xg + j];
+    // Words 4 xg .. 4 xg + 3 of row (z, y) of one colour plane are one
+    // 16-byte segment; block zb is the 128 segments of rows z = 64 zb + r,
+    // both parity slots (slot 0 = even x).  Blocks come in pairs, one per half
+    // of the workgroup (thread t: segment t & 127 of block 2 pp + t / 128),
+    // and kAhead pairs are loaded ahead, so that many 16-byte loads per lane
+    // are in flight.
+    const uint32_t seg = threadIdx.x & 127u, half = threadIdx.x >> 7;
+    const uint32_t sr = seg >> 1, sslot = seg & 1u;
+    auto fetch = [&](uint32_t pp) -> uint4 {
+        const uint32_t z = 64u * (2u * pp + half) + sr;
+        const uint32_t c = sslot ^ ((y + z) & 1u);   // colour holding the parity slot
+        return *reinterpret_cast<const uint4 *>((c ? P1 : P0) + ((size_t)z * L + y) * W + 4u * xg);
     };
-    constexpr uint32_t kAhead = 4;
-    uint32_t pre[kAhead][2];
+    constexpr uint32_t kAhead = 8;
+    const uint32_t npairs = W / 2;
+    uint4 pre[kAhead];
 #pragma unroll
-    for (uint32_t a = 0; a < kAhead; ++a) {
-        pre[a][0] = a < W ? fetch(a, 0) : 0u;
-        pre[a][1] = a < W ? fetch(a, 1) : 0u;
-    }
-    for (uint32_t zb = 0; zb < W; ++zb) {
-        // the block's words into this iteration's buffer; the other buffer was
-        // last read before the previous barrier
-        uint32_t *ib = in + (zb & 1u) * 512u;
-        ib[threadIdx.x] = pre[0][0];
-        ib[threadIdx.x + 256u] = pre[0][1];
+    for (uint32_t a = 0; a < kAhead; ++a)
+        pre[a] = fetch(min(a, npairs - 1u));
+    // this lane's row of a block: z = 2 zh + p
+    const uint32_t zh = (lane & 3u) | ((lane >> 3) << 2), p = (lane >> 2) & 1u;
+    const uint32_t rz = 2u * zh + p;
+    for (uint32_t pp = 0; pp < npairs; ++pp) {
+        // the pair's segments into this iteration's buffer; the other buffer
+        // was last read before the previous barrier
+        uint32_t *ib = in + (pp & 1u) * (2u * kSwapIn);
+        {
+            uint32_t *d = ib + half * kSwapIn + sslot * 4u * 65u + sr;
+            d[0] = pre[0].x;
+            d[65] = pre[0].y;
+            d[130] = pre[0].z;
+            d[195] = pre[0].w;
+        }
 #pragma unroll
-        for (uint32_t a = 0; a + 1 < kAhead; ++a) {
-            pre[a][0] = pre[a + 1][0];
-            pre[a][1] = pre[a + 1][1];
-        }
-        if (zb + kAhead < W) {
-            pre[kAhead - 1][0] = fetch(zb + kAhead, 0);
-            pre[kAhead - 1][1] = fetch(zb + kAhead, 1);
-        }
+        for (uint32_t a = 0; a + 1 < kAhead; ++a)
+            pre[a] = pre[a + 1];
+        pre[kAhead - 1] = fetch(min(pp + kAhead, npairs - 1u));
         __syncthreads();
-        // wave wv: block xb = 4 xg + wv; lane = row z - 64 zb
-        const uint32_t we = ib[lane * 8u + wv], wo = ib[lane * 8u + 4u + wv];
-        uint64_t v = spread_bits(we) | (spread_bits(wo) << 1);
 #pragma unroll
-        for (int st = 0; st < 6; ++st) {
-            const uint32_t j = 32u >> st;
-            const uint64_t m = kMask[st];   // bit positions k with (k & j) == 0
-            const uint32_t olo = __shfl_xor((uint32_t)v, (int)j, 64);
-            const uint32_t ohi = __shfl_xor((uint32_t)(v >> 32), (int)j, 64);
-            const uint64_t o = ((uint64_t)ohi << 32) | olo;
-            v = (lane & j) ? ((v & ~m) | ((o & ~m) >> j)) : ((v & m) | ((o & m) << j));
+        for (uint32_t hb = 0; hb < 2; ++hb) {
+            const uint32_t zb = 2u * pp + hb;
+            const uint32_t *bb = ib + hb * kSwapIn;
+            // wave wv: x block 4 xg + wv, word wv of each segment
+            const uint32_t we = transpose32(bb[wv * 65u + rz], lane);          // q = 0
+            const uint32_t wo = transpose32(bb[(4u + wv) * 65u + rz], lane);   // q = 1
+            // rows z' = 64 wv + 2 zh + q of Q's group, slot p, word zb
+            const uint32_t r2 = 32u * wv + zh;
+            *reinterpret_cast<uint2 *>(out + zb * kSwapOut + r2 * 4u + p * 2u) = make_uint2(we, wo);
         }
-        // lane now holds row z' = 64 xb + lane: bit k is x' = 64 zb + k
-        const uint32_t row = 64u * wv + lane;
-        out[(row * 2u + 0u) * W + zb] = compact_bits(v);
-        out[(row * 2u + 1u) * W + zb] = compact_bits(v >> 1);
     }
     __syncthreads();
-    // rows z' = 256 xg + row: parity slot p' goes to colour (p' + y + z') & 1
-    for (uint32_t k = threadIdx.x; k < 512u * W; k += blockDim.x) {
-        const uint32_t w = k % W, slot = (k / W) & 1u, row = k / (2u * W);
+    // rows z' = 256 xg + row: parity slot p' goes to colour (p' + y + z') & 1;
+    // item it: quad w4 of the words of (row, slot), 16 bytes to global memory
+    const uint32_t nq = W / 4;
+    for (uint32_t it = threadIdx.x; it < 512u * nq; it += blockDim.x) {
+        const uint32_t w4 = it % nq, rs = it / nq;
+        const uint32_t row = rs >> 1, slot = rs & 1u;
+        const uint32_t *src = out + (4u * w4) * kSwapOut + (row >> 1) * 4u + slot * 2u + (row & 1u);
+        const uint4 v = make_uint4(src[0], src[kSwapOut], src[2u * kSwapOut], src[3u * kSwapOut]);
         const uint32_t zp = 256u * xg + row;
         const uint32_t c = slot ^ ((y + zp) & 1u);
-        (c ? Q1 : Q0)[((size_t)zp * L + y) * W + w] = out[k];
+        *reinterpret_cast<uint4 *>((c ? Q1 : Q0) + ((size_t)zp * L + y) * W + 4u * w4) = v;
     }
 }
 
@@ -692,16 +737,33 @@ GramGeom gram_geom(uint32_t L, uint32_t NB)
     // cache), at least 64 words, fewer than 2^24 lines per chunk (each float
     // accumulator then counts up-up pairs exactly in units of 0.25) and
     // per-wave diagonal sums below 2^32
-    const uint32_t waves = 2 * 1024 * (4 / NB);
+    const uint32_t resident = 1024 * (4 / NB);   // waves in one round over the chip
+    const uint32_t waves = 2 * resident;
     uint32_t nsplit = std::max((waves + g.ntile - 1) / g.ntile, (g.NK + 2047) / 2048);
-    uint32_t kchunk = ((g.NK + nsplit - 1) / nsplit + 7) / 8 * 8;
-    if (kchunk < 64)
-        kchunk = 64;
     const uint32_t kmax = (1u << 19) - 8;   // 32 lines per word, 128 entries per diagonal
-    if (kchunk > kmax)
-        kchunk = kmax;
-    g.kchunk = kchunk;
-    g.nsplit = (g.NK + kchunk - 1) / kchunk;
+    auto chunk_of = [&](uint32_t ns) {
+        uint32_t kc = ((g.NK + ns - 1) / ns + 7) / 8 * 8;
+        return std::min(std::max(kc, 64u), kmax);
+    };
+    // among slightly fewer chunks (up to a quarter longer, 2560 words at
+    // most), the count whose last round of waves is fullest: the launch takes
+    // rounds x chunk length, plus a fixed cost per wave for its diagonals
+    uint32_t best = nsplit;
+    uint64_t best_cost = ~0ull;
+    for (uint32_t ns = std::max(1u, nsplit - nsplit / 4); ns <= nsplit; ++ns) {
+        const uint32_t kc = chunk_of(ns);
+        if (kc > 2560 && ns != nsplit)
+            continue;
+        const uint32_t n = (g.NK + kc - 1) / kc;
+        const uint64_t rounds = ((uint64_t)g.ntile * n + resident - 1) / resident;
+        const uint64_t cost = rounds * (kc + 128);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = ns;
+        }
+    }
+    g.kchunk = chunk_of(best);
+    g.nsplit = (g.NK + g.kchunk - 1) / g.kchunk;
     return g;
 }
 
@@ -774,7 +836,8 @@ hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32
         if (gram_x) {
             // x: the z axis of the lattice with x and z swapped (into Q)
             hipLaunchKernelGGL(k_bit_swap_xz, dim3(L * (W / 4)), dim3(256),
-                               (size_t)(512 * W + 1024) * 4, st, L, W, P0, P1, Q0, Q1);
+                               (size_t)(kSwapOut * W + 4 * kSwapIn) * 4, st, L, W, P0, P1, Q0,
+                               Q1);
             hipLaunchKernelGGL((k_corr_gram<2, kGramNB>), grid_gram, dim3(256), 0, st, gg, Q0, Q1,
                                anti);
         }
