@@ -21,11 +21,21 @@ its own (L, seed) trajectory.
 """
 import collections
 import concurrent.futures
+import threading
 import time
 from dataclasses import dataclass
 from typing import Dict, List, Optional
 
 import numpy as np
+
+
+class StepError(RuntimeError):
+    """A backend's work for one request failed; the server answers that
+    request as failed and goes on with the others."""
+
+    def __init__(self, idx: int, message: str):
+        super().__init__(message)
+        self.idx = idx
 
 
 @dataclass
@@ -39,6 +49,8 @@ class Result:
     done_s: float = 0.0
     trace: Optional[np.ndarray] = None   # B(0), B(every), ..., B(t_max - every)
     final_B: int = -1
+    status: str = "ok"                   # "ok", "cancelled" or "failed"
+    error: Optional[str] = None          # the failure's message
 
     @property
     def latency_s(self) -> float:
@@ -111,6 +123,10 @@ class GpuBackend:
         self.single_used = 0
         self.live: Dict[int, dict] = {}          # request idx -> placement
         self._batch_event = None                 # completion of the batch's chunk in flight
+        # cancelled or failed single lattices whose queued work has not
+        # drained yet: their memory stays booked until it has
+        self._zombies: List[dict] = []
+        self._failed: Dict[int, str] = {}
 
     @staticmethod
     def layout_for(L: int) -> str:
@@ -218,14 +234,20 @@ class GpuBackend:
             p["event"] = feed()
 
     def poll(self) -> List[int]:
+        self._reap()
         out = []
-        for i, p in self.live.items():
+        for i, p in list(self.live.items()):
             if p["kind"] != "single":
                 continue
             fut = p.get("future")
             if fut is not None and fut.done():
-                p["event"] = fut.result()        # raises what the feeder raised
                 p["future"] = None
+                try:
+                    p["event"] = fut.result()
+                except Exception as e:            # the feeder's library call failed
+                    self._failed[i] = f"{type(e).__name__}: {e}"
+                    self.discard(i)
+                    continue
             if p.get("event") is not None and p["event"].query():
                 p["t"] = p["t_max"]
                 out.append(i)
@@ -254,6 +276,53 @@ class GpuBackend:
 
     def busy(self) -> bool:
         return bool(self.live)
+
+    # ---- cancellation and failures ---------------------------------------
+    def cancel(self, idx: int) -> None:
+        """Stop serving request idx and free its slot.  A batch slot stops at
+        once (the device skips inactive slots; a chunk in flight ends first,
+        stream-ordered before any reuse).  A single lattice's work is already
+        queued on its stream and cannot be taken back: its memory is released
+        once that work has drained."""
+        p = self.live.pop(idx, None)
+        if p is None:
+            return
+        if p["kind"] == "batch":
+            self.batch.set_active(p["slot"], False)
+            self.free_batch[self.batch.specs[p["slot"]][0]].append(p["slot"])
+            return
+        self._zombies.append(p)
+        self._reap()
+
+    discard = cancel
+
+    def failures(self) -> Dict[int, str]:
+        """Requests whose work failed since the last call (idx -> message);
+        their resources are already released or queued for release."""
+        out, self._failed = self._failed, {}
+        return out
+
+    def _reap(self) -> None:
+        keep = []
+        for p in self._zombies:
+            fut = p.get("future")
+            if fut is not None:
+                if not fut.done():
+                    keep.append(p)
+                    continue
+                try:
+                    p["event"] = fut.result()
+                except Exception:
+                    p["event"] = None
+                p["future"] = None
+            ev = p.get("event")
+            if ev is not None and not ev.query():
+                keep.append(p)
+                continue
+            if p.get("lat") is not None:
+                p["lat"].close()
+            self.single_used -= p["bytes"]
+        self._zombies = keep
 
     def retire(self, idx: int) -> dict:
         p = self.live.pop(idx)
@@ -300,54 +369,134 @@ class Server:
     def __init__(self, backend, chunk: int):
         self.backend = backend
         self.chunk = chunk
+        self._cancel_lock = threading.Lock()
+        self._cancels: List[int] = []
+
+    def cancel(self, idx: int) -> None:
+        """Ask for request idx to be cancelled (from any thread, or from the
+        serve loop's callbacks).  It is dropped if it has not been admitted,
+        else stopped and its slot freed; a request already answered is left
+        as it is."""
+        with self._cancel_lock:
+            self._cancels.append(idx)
+
+    def _take_cancels(self) -> List[int]:
+        with self._cancel_lock:
+            out, self._cancels = self._cancels, []
+        return out
 
     def serve(self, requests, clock=time.perf_counter, time_scale: float = 1.0,
-              progress=None) -> List[Result]:
+              progress=None, tick=None) -> List[Result]:
         """Serve `requests` (objects with idx, L, seed, t_max, arrival_s), arrivals
         replayed in real time (arrival_s * time_scale after the start).
-        progress(done, total, seconds) is called after each retirement."""
+        progress(done, total, seconds) is called after each answer (finished,
+        cancelled or failed); tick(server, round) once per round of the loop.
+        A backend step that fails for one request (StepError, or an entry in
+        the backend's failures()) answers that request as failed; the others
+        go on."""
         be = self.backend
         asynchronous = all(hasattr(be, k) for k in ("poll", "kick", "start"))
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival_s))
         waiting: collections.deque = collections.deque()
         results: Dict[int, Result] = {}
+        live: set = set()
         t_start = clock()
         done = 0
         total = len(pending)
 
-        def finish(idx):
+        def answered(res):
             nonlocal done
-            out = be.retire(idx)
-            res = results[idx]
-            res.trace = out["trace"]
-            res.final_B = out["final_B"]
             res.done_s = clock() - t_start
             done += 1
             if progress is not None:
                 progress(done, total, res.done_s)
 
+        def finish(idx):
+            if idx not in live:
+                return
+            live.discard(idx)
+            out = be.retire(idx)
+            res = results[idx]
+            res.trace = out["trace"]
+            res.final_B = out["final_B"]
+            answered(res)
+
+        def fail(idx, message):
+            if idx not in live:
+                return
+            live.discard(idx)
+            if hasattr(be, "discard"):
+                be.discard(idx)
+            res = results[idx]
+            res.status, res.error = "failed", message
+            answered(res)
+
+        def collect_failures():
+            if hasattr(be, "failures"):
+                for idx, message in be.failures().items():
+                    fail(idx, message)
+
+        def guarded(step):
+            try:
+                return step()
+            except StepError as e:
+                fail(e.idx, str(e))
+                return None
+
+        def cancel_requested():
+            for idx in self._take_cancels():
+                res = results.get(idx)
+                if res is not None and (res.status != "ok" or res.trace is not None):
+                    continue                          # already answered
+                if idx in live:
+                    live.discard(idx)
+                    be.cancel(idx)
+                else:
+                    r = next((x for x in waiting if x.idx == idx), None)
+                    if r is not None:
+                        waiting.remove(r)
+                    else:
+                        r = next((x for x in pending if x.idx == idx), None)
+                        if r is None:
+                            continue                  # unknown request
+                        pending.remove(r)
+                        res = results[idx] = Result(r.idx, r.L, r.seed, r.t_max,
+                                                    r.arrival_s * time_scale)
+                res = results[idx]
+                res.status = "cancelled"
+                answered(res)
+
+        rounds = 0
         while done < total:
+            if tick is not None:
+                tick(self, rounds)
+            rounds += 1
             now = clock() - t_start
             while pending and pending[0].arrival_s * time_scale <= now:
                 r = pending.popleft()
                 waiting.append(r)
                 results[r.idx] = Result(r.idx, r.L, r.seed, r.t_max, r.arrival_s * time_scale)
+            cancel_requested()
+            if done >= total:
+                break
             if asynchronous:
-                for idx in be.poll():
+                for idx in guarded(be.poll) or []:
                     finish(idx)
+                collect_failures()
             # admit in arrival order, skipping requests whose size has no room yet
             still = collections.deque()
             while waiting:
                 r = waiting.popleft()
                 if be.can_admit(r.L):
                     be.admit(r)
+                    live.add(r.idx)
                     results[r.idx].admitted_s = clock() - t_start
                     if asynchronous:
-                        be.start(r.idx)
+                        guarded(lambda: be.start(r.idx))
                 else:
                     still.append(r)
             waiting = still
-            if not be.live:
+            if not live:
                 if pending:
                     # idle until the next arrival
                     wait = pending[0].arrival_s * time_scale - (clock() - t_start)
@@ -355,21 +504,28 @@ class Server:
                         time.sleep(min(wait, 0.01))
                 continue
             if asynchronous:
-                be.kick()
+                guarded(be.kick)
+                collect_failures()
                 time.sleep(0.0002)        # the device is busy; look again shortly
                 continue
-            be.advance()
+            guarded(be.advance)
             be.sync()
+            collect_failures()
             for idx in be.finished():
                 finish(idx)
         return [results[k] for k in sorted(results)]
 
 
 def summarize(results: List[Result], wall_s: float) -> dict:
-    lat = np.array([r.latency_s for r in results])
-    attempts = float(sum(r.L ** 3 * r.t_max for r in results))
+    """Latency and throughput over the requests answered with a result;
+    cancelled and failed ones are counted apart."""
+    ok = [r for r in results if r.status == "ok"]
+    lat = np.array([r.latency_s for r in ok]) if ok else np.zeros(1)
+    attempts = float(sum(r.L ** 3 * r.t_max for r in ok))
     return {
         "requests": len(results),
+        "cancelled": sum(r.status == "cancelled" for r in results),
+        "failed": sum(r.status == "failed" for r in results),
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
         "attempts_per_ns": attempts / (wall_s * 1e9),
