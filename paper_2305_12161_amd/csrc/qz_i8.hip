@@ -2,6 +2,8 @@
 // lattice index i = x + L*(y + L*z).  One launch per colour (the colour-p pass
 // reads only colour 1-p, so it updates in place without races), the bond count
 // of the state entering a sweep fused into its colour-0 pass.
+#include <algorithm>
+
 #include "qz_device.hpp"
 #include "qz_internal.hpp"
 
@@ -226,35 +228,98 @@ __global__ void __launch_bounds__(kThreads) k_i8_bonds(uint32_t L, const int8_t 
     block_add_u64(bz, acc3 + 2);
 }
 
-// Correlation sums: blockIdx.y = a*(L/2+1) + r for the pair (axis a, shift r),
-// and blockIdx.y = 3*(L/2+1) for the magnetisation; thread per column (x, y),
-// looping over z.
-__global__ void __launch_bounds__(kThreads) k_i8_corr(uint32_t L, const int8_t *s,
+// Correlation sums S_a(r) = sum_i s_i s_{i + r e_a}, r = 0..L/2, and
+// M = sum_i s_i.  A workgroup takes X lines along axis a (line position u,
+// transverse index v in [v0, v0 + X), the third coordinate o fixed) and
+// stages them in LDS, each padded with its own first bytes again (circular
+// continuation) so that a shifted read never wraps.  Work item (line, r-block
+// of 8): for every aligned word k of the line (4 sites u = 4k .. 4k+3) the 8
+// shifted words starting at byte 4k + r come from three words by byte
+// alignment, and a signed 4-way byte dot product accumulates each
+// separation: 8 dot products and 6 alignments per 32 products.  Per-block
+// sums meet in LDS (32-bit: at most X L per entry) and go to the global
+// 64-bit sums once per block.  Element (u, v, o) sits at
+//   x lines: u + L v + L^2 o;  y lines: L u + v + L^2 o;  z lines: L^2 u + v + L o.
+struct I8CorrGeom {
+    uint32_t L, R, X, Lp, nrb, ntile;   // Lp: staged bytes per line (multiple of 4)
+};
+
+__global__ void __launch_bounds__(kThreads) k_i8_corr(I8CorrGeom g, const int8_t *s,
                                                       unsigned long long *S)
 {
-    const uint32_t R = L / 2 + 1;
-    const uint32_t q = blockIdx.y;
-    const uint32_t col = blockIdx.x * kThreads + threadIdx.x;
+    extern __shared__ uint32_t i8c_sm[];
+    const uint32_t L = g.L, R = g.R, X = g.X, Lp = g.Lp;
+    int *sS = reinterpret_cast<int *>(i8c_sm);              // [R] this block's sums, then M
+    int8_t *buf = reinterpret_cast<int8_t *>(i8c_sm + R + 1);   // [X][Lp]
+    const uint32_t tile = blockIdx.x % g.ntile;
+    const uint32_t o = (blockIdx.x / g.ntile) % L;
+    const uint32_t a = blockIdx.x / (g.ntile * L);
+    const uint32_t v0 = tile * X;
+    const uint32_t nl = min(X, L - v0);                     // lines in this block
+    for (uint32_t k = threadIdx.x; k <= R; k += kThreads)
+        sS[k] = 0;
     const uint64_t LL = (uint64_t)L * L;
-    long long acc = 0;
-    if (col < L * L) {
-        const uint32_t x = col % L, y = col / L;
-        if (q == 3 * R) {
-            for (uint32_t z = 0; z < L; ++z)
-                acc += s[(uint64_t)z * LL + col];
+    // staging: the memory-contiguous coordinate runs fastest across threads
+    const uint32_t nst = nl * Lp;
+    for (uint32_t e = threadIdx.x; e < nst; e += kThreads) {
+        uint32_t u, vl;
+        if (a == 0) {
+            vl = e / Lp;
+            u = e % Lp;
         } else {
-            const uint32_t a = q / R, r = q % R;
-            const uint32_t xs = (a == 0) ? (x + r >= L ? x + r - L : x + r) : x;
-            const uint32_t ys = (a == 1) ? (y + r >= L ? y + r - L : y + r) : y;
-            const uint64_t other = (uint64_t)ys * L + xs;
-            const uint32_t dz = (a == 2) ? r : 0u;
-            for (uint32_t z = 0; z < L; ++z) {
-                const uint32_t zs = z + dz >= L ? z + dz - L : z + dz;
-                acc += (int)s[(uint64_t)z * LL + col] * (int)s[(uint64_t)zs * LL + other];
-            }
+            u = e / nl;
+            vl = e % nl;
         }
+        const uint32_t uu = u % L, v = v0 + vl;
+        const uint64_t off = a == 0 ? uu + (uint64_t)L * v + LL * o
+                           : a == 1 ? (uint64_t)L * uu + v + LL * o
+                                    : LL * uu + v + (uint64_t)L * o;
+        buf[(size_t)vl * Lp + u] = s[off];
     }
-    block_add_u64((unsigned long long)acc, S + q);
+    __syncthreads();
+    const uint32_t nk = (L + 3) / 4;                        // words of a line's sites
+    const uint32_t tail = L % 4;                            // sites in a partial last word
+    const uint32_t last_mask = tail ? (1u << (8 * tail)) - 1u : 0xFFFFFFFFu;
+    int m_acc = 0;
+    for (uint32_t item = threadIdx.x; item < nl * g.nrb; item += kThreads) {
+        const uint32_t vl = item / g.nrb, rb = item % g.nrb;
+        const uint32_t r0 = 8u * rb;
+        const uint32_t *lw = reinterpret_cast<const uint32_t *>(buf + (size_t)vl * Lp);
+        int acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        const uint32_t kb = r0 / 4;
+        uint32_t w0 = lw[kb], w1 = lw[kb + 1], w2 = lw[kb + 2];
+        for (uint32_t k = 0; k < nk; ++k) {
+            uint32_t av = lw[k];
+            if (k + 1 == nk)
+                av &= last_mask;                            // sites past L contribute nothing
+            const int ai = (int)av;
+            acc[0] = __builtin_amdgcn_sdot4(ai, (int)w0, acc[0], false);
+            acc[1] = __builtin_amdgcn_sdot4(ai, (int)__builtin_amdgcn_alignbyte(w1, w0, 1), acc[1], false);
+            acc[2] = __builtin_amdgcn_sdot4(ai, (int)__builtin_amdgcn_alignbyte(w1, w0, 2), acc[2], false);
+            acc[3] = __builtin_amdgcn_sdot4(ai, (int)__builtin_amdgcn_alignbyte(w1, w0, 3), acc[3], false);
+            acc[4] = __builtin_amdgcn_sdot4(ai, (int)w1, acc[4], false);
+            acc[5] = __builtin_amdgcn_sdot4(ai, (int)__builtin_amdgcn_alignbyte(w2, w1, 1), acc[5], false);
+            acc[6] = __builtin_amdgcn_sdot4(ai, (int)__builtin_amdgcn_alignbyte(w2, w1, 2), acc[6], false);
+            acc[7] = __builtin_amdgcn_sdot4(ai, (int)__builtin_amdgcn_alignbyte(w2, w1, 3), acc[7], false);
+            w0 = w1;
+            w1 = w2;
+            w2 = lw[kb + k + 3];
+            if (a == 0 && rb == 0)
+                m_acc = __builtin_amdgcn_sdot4(ai, 0x01010101, m_acc, false);
+        }
+#pragma unroll
+        for (int d = 0; d < 8; ++d)
+            if (r0 + d < R)
+                atomicAdd(sS + r0 + d, acc[d]);
+    }
+    if (a == 0 && m_acc != 0)
+        atomicAdd(sS + R, m_acc);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < R; k += kThreads)
+        if (sS[k] != 0)
+            atomicAdd(S + (size_t)a * R + k, (unsigned long long)(long long)sS[k]);
+    if (a == 0 && threadIdx.x == 0 && sS[R] != 0)
+        atomicAdd(S + 3 * (size_t)R, (unsigned long long)(long long)sS[R]);
 }
 
 __global__ void __launch_bounds__(kThreads) k_i8_check(uint64_t n, const int8_t *s,
@@ -337,9 +402,23 @@ hipError_t i8_corr(hipStream_t st, uint32_t L, const int8_t *s, long long *S, lo
 {
     // S and M are contiguous: M sits at S[3*(L/2+1)].
     (void)M;
-    const uint32_t R = L / 2 + 1;
-    hipLaunchKernelGGL(k_i8_corr, dim3((L * L + kThreads - 1) / kThreads, 3 * R + 1),
-                       dim3(kThreads), 0, st, L, s, reinterpret_cast<unsigned long long *>(S));
+    I8CorrGeom g;
+    g.L = L;
+    g.R = L / 2 + 1;
+    g.nrb = (g.R + 7) / 8;
+    // staged bytes per line: the line, then its continuation far enough for
+    // the largest r-block's three-word window to stay inside
+    g.Lp = ((L + 8 * g.nrb + 16) + 3) / 4 * 4;
+    uint32_t X = 40960 / g.Lp;
+    X = std::max(1u, std::min({X, 64u, L}));
+    g.X = X;
+    g.ntile = (L + X - 1) / X;
+    const size_t lds = (size_t)(g.R + 1) * 4 + (size_t)X * g.Lp;
+    const uint64_t blocks = 3ull * L * g.ntile;
+    if (blocks > 0x7FFFFFFFull)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_i8_corr, dim3((uint32_t)blocks), dim3(kThreads), lds, st, g, s,
+                       reinterpret_cast<unsigned long long *>(S));
     return hipGetLastError();
 }
 

@@ -363,6 +363,28 @@ def test_corr_matches_fft_L512(qz):
         assert np.array_equal(S[a], want), a
 
 
+@pytest.mark.parametrize("L", [4, 6, 10, 18, 34, 66, 130, 256])
+def test_i8_corr_random_states(qz, L):
+    """The int8 layout's correlation sums on uploaded random states (biased,
+    so that M is far from 0) against numpy's FFT autocorrelation per axis
+    (exact in double at these sizes): sizes with L % 4 == 2 end their lines
+    in a half word, and L = 256 runs the full block geometry."""
+    R = L // 2 + 1
+    for p_up, seed in ((0.5, 3), (0.8, 4)):
+        say("i8 corr", L, p_up)
+        st = wl.random_state(L, seed + L, p_up)
+        lat = qz.Lattice(L, 1, "i8")
+        lat.upload(st, 0)
+        S, M = lat.corr()
+        s = st.astype(np.float64)
+        assert M == int(s.sum())
+        for a, ax in enumerate((2, 1, 0)):   # x, y, z are array axes 2, 1, 0
+            f = np.fft.rfft(s, axis=ax)
+            ac = np.fft.irfft(f * np.conj(f), n=L, axis=ax)
+            want = np.rint(ac.sum(axis=tuple(k for k in range(3) if k != ax))[:R]).astype(np.int64)
+            assert np.array_equal(S[a], want), (a, L, p_up)
+
+
 @pytest.mark.parametrize("layout,L", [("i8", 6), ("i8", 16), ("i8", 34), ("bit", 64),
                                       ("bit", 128), ("bit", 192), ("bit", 256)])
 def test_bonds_and_corr_match_oracle(qz, orc, layout, L):
