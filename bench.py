@@ -591,6 +591,12 @@ def main():
             print(f"# {name} failed: {e}", file=sys.stderr, flush=True)
     if not args.no_batch:
         leg("batched", lambda: batched_workload(binding, torch, workloads))
+        if "value" in out.get("batched", {}):
+            # the batch against the single-lattice kernel at its best size
+            # (the L = 2048 sweeps above), beside the one-lattice-at-a-time
+            # comparison at the batch's own sizes
+            out["batched"]["batched_over_L2048_sweeps"] = round(
+                out["batched"]["value"] / out["sweep_only_attempts_per_ns"], 4)
     if not args.no_serve:
         rate = args.serve_rate if args.serve_rate else workloads.SERVE_RATE_PER_S
         leg("served", lambda: served_workload(binding, torch, workloads, args.serve_requests, rate))

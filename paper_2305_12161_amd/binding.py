@@ -87,6 +87,15 @@ def _stream_handle(stream):
     return stream, ctypes.c_void_p(stream.cuda_stream)
 
 
+def _counts(n, trace_every=0):
+    """Sweep count and trace cadence as non-negative integers: a negative value
+    would reach the library as a huge unsigned count."""
+    n, trace_every = int(n), int(trace_every)
+    if n < 0 or trace_every < 0:
+        raise ValueError("sweep counts and trace cadences must be non-negative")
+    return n, trace_every
+
+
 def _dev_buf(t, need: int):
     """Device pointer of a torch tensor that receives `need` 64-bit values, or
     None.  Refuses tensors the library would write past or misread."""
@@ -144,6 +153,7 @@ class Lattice:
         return int(v.value)
 
     def run(self, n: int, trace_every: int = 0) -> np.ndarray:
+        n, trace_every = _counts(n, trace_every)
         if trace_every:
             out = np.zeros(n // trace_every, dtype=np.uint64)
             _check(lib.qz_run(self._h, n, trace_every,
@@ -154,12 +164,14 @@ class Lattice:
 
     def run_device(self, n: int, trace_every: int, dev_trace) -> None:
         """Asynchronous run; dev_trace is a torch int64/uint64 device tensor."""
+        n, trace_every = _counts(n, trace_every)
         ptr = _dev_buf(dev_trace, n // trace_every if trace_every else 0)
         _check(lib.qz_run_device(self._h, n, trace_every, ptr))
 
     def run_traced(self, n: int, trace_every: int):
         """Run n sweeps; returns (B, flips) at every trace_every-th sweep: the bond
         count entering the sweep and the number of spins it flipped."""
+        n, trace_every = _counts(n, trace_every)
         if trace_every <= 0:
             raise ValueError("trace_every must be positive")
         B = np.zeros(n // trace_every, dtype=np.uint64)
@@ -170,6 +182,7 @@ class Lattice:
 
     def run_device_traced(self, n: int, trace_every: int, dev_B, dev_flips) -> None:
         """Asynchronous run with device traces of B and of the accepted flips."""
+        n, trace_every = _counts(n, trace_every)
         need = n // trace_every if trace_every else 0
         pb, pf = _dev_buf(dev_B, need), _dev_buf(dev_flips, need)
         _check(lib.qz_run_device_traced(self._h, n, trace_every, pb, pf))
@@ -178,6 +191,7 @@ class Lattice:
         """Run n sweeps; returns (B, flips) for the sweeps at the listed offsets
         (strictly increasing, each < n): the bond count entering the sweep and
         the number of spins it flipped."""
+        n, _ = _counts(n)
         P = ctypes.POINTER(ctypes.c_uint64)
         lst = np.ascontiguousarray(at, dtype=np.uint64)
         B = np.zeros(lst.size, dtype=np.uint64)
@@ -188,6 +202,7 @@ class Lattice:
 
     def run_device_at(self, n: int, at, dev_B, dev_flips) -> None:
         """Asynchronous run; device traces of B and of the flips at the listed sweeps."""
+        n, _ = _counts(n)
         P = ctypes.POINTER(ctypes.c_uint64)
         lst = np.ascontiguousarray(at, dtype=np.uint64)
         pb, pf = _dev_buf(dev_B, lst.size), _dev_buf(dev_flips, lst.size)
@@ -392,6 +407,7 @@ class Batch:
         cadence) returns an int64 array [slot, i] of B at the traced times
         reached in this run (-1 where a slot did not reach that time) and
         synchronises; otherwise the call is asynchronous and returns None."""
+        n, trace_every = _counts(n, trace_every)
         if trace_every:
             P = -(-n // trace_every)
             out = np.zeros(len(self.specs) * P, dtype=np.uint64)

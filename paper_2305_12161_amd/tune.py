@@ -165,12 +165,17 @@ def tune_batch(specs, sweeps: int = 10000, verbose: bool = True):
     sizes = sorted({L for L, _ in specs})
     chosen = {L: None for L in sizes}
     results = {}
-    warm = 200          # a multiple of every graph length tried; captures the graphs
+    # untimed first sweeps that capture the graphs: a multiple of every graph
+    # length tried, when the job is long enough to leave most of it timed
+    warm = 200 if sweeps >= 400 else 0
+    if sweeps <= warm:
+        raise ValueError("sweeps must be positive")
 
     def time_batch(tz, graph, onchip=0):
         b = binding.Batch(specs, tuning={"graph_sweeps": graph, "onchip": onchip,
                                          "tz": {str(L): v for L, v in tz.items() if v}})
-        b.run(warm)
+        if warm:
+            b.run(warm)
         b.sync()
         t0 = time.perf_counter()
         b.run(sweeps - warm)
@@ -201,6 +206,9 @@ def tune_batch(specs, sweeps: int = 10000, verbose: bool = True):
             if L not in results or ms < results[L][1]:
                 results[L] = (Tz, ms)
         chosen[L] = results[L][0]
+    for L in sizes:
+        if chosen[L] is None:            # side 64 on chip: its sub-tile shape stays the default
+            chosen[L] = 8 if L % 8 == 0 else 1
     best_graph = None
     for gs in (10, 25, 50, 100, 200):
         ms = time_batch(chosen, gs, onchip)
@@ -210,7 +218,7 @@ def tune_batch(specs, sweeps: int = 10000, verbose: bool = True):
             best_graph = (gs, ms)
     d = _load()
     for L in sizes:
-        d["batch"][str(L)] = {"Tz": chosen[L] or 8, "graph_sweeps": best_graph[0]}
+        d["batch"][str(L)] = {"Tz": chosen[L], "graph_sweeps": best_graph[0]}
         if L == 64:
             d["batch"][str(L)]["onchip"] = onchip
     _save(d)

@@ -117,3 +117,13 @@ def test_null_handle_calls(lib):
     lib.qz_run.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
     assert lib.qz_run(None, 1, 0, None) == -1
     assert lib.qz_destroy(None) == -1
+
+
+def test_binding_rejects_negative_counts():
+    """A negative sweep count or cadence would reach the library as a huge
+    unsigned count (a run that does not end): the binding refuses it."""
+    from paper_2305_12161_amd import binding
+    assert binding._counts(5, 2) == (5, 2)
+    for bad in ((-1, 0), (10, -5), (-180, 0)):
+        with pytest.raises(ValueError):
+            binding._counts(*bad)
