@@ -377,10 +377,23 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     lat = binding.Lattice(L, seed, "bit", stream=stream)
-    if args.tuning:
-        lat.set_tuning(*[int(v) for v in args.tuning.split(",")])
+    # tiles: given on the command line, else the autotuner's stored winners
+    # for this L (tune.py), else the library's defaults
+    tuning_source = "library defaults"
     if args.sweeps_per_pass:
         lat.set_pass(args.sweeps_per_pass)
+    if args.tuning:
+        lat.set_tuning(*[int(v) for v in args.tuning.split(",")])
+        tuning_source = "command line"
+    else:
+        from paper_2305_12161_amd import tune as tuner
+        stored1, stored2 = tuner.best_single(L), tuner.best_pass2(L)
+        if stored1:
+            lat.set_tuning(*stored1)
+        if stored2 and lat.pass_config()[0] == 2:
+            lat.set_pass(2, *stored2)
+        if stored1 or stored2:
+            tuning_source = "tuned.json"
     tune = lat.tuning()
     pcfg = lat.pass_config()
     per_launch = pcfg[0]   # sweeps carried by one launch of the dominant kernel
@@ -534,7 +547,7 @@ def main():
                         f"unsatisfied-bond count (fused) {bond_cadence}, axis C(r<=L/2) at the "
                         f"{len(corr_times)} of 40 log-spaced times in the timed window",
             "L": L, "layout": "bit", "seed": seed, "t_window": [W, W + K],
-            "tuning_V_Ty_Tz": list(tune), "sweeps_per_pass": pcfg[0],
+            "tuning_V_Ty_Tz": list(tune), "tuning_source": tuning_source, "sweeps_per_pass": pcfg[0],
             "pass2_tuning_V_Ty_Tz": list(pcfg[1:]), "parallelism": "single GPU",
         },
         "roofline": {

@@ -117,6 +117,7 @@ class GpuBackend:
             for slot, (L, _) in enumerate(specs):
                 self.batch.set_active(slot, False)
                 self.free_batch[L].append(slot)
+        self._tuned: Dict[int, Optional[tuple]] = {}   # side -> stored two-sweep tile
         self.single_budget = budget_bytes - self.batch_bytes
         if self.single_budget < 0:
             raise ValueError("batch slots exceed the memory budget")
@@ -176,6 +177,13 @@ class GpuBackend:
                                   stream=p["stream"])
         if self.layout_for(p["L"]) == "bit" and self.single_pass:
             lat.set_pass(self.single_pass)
+            # the autotuner's stored tile for this side, if it has one
+            if p["L"] not in self._tuned:
+                from . import tune
+                self._tuned[p["L"]] = tune.best_pass2(p["L"])
+            stored = self._tuned[p["L"]]
+            if stored is not None and self.single_pass == 2:
+                lat.set_pass(2, *stored)
         p["lat"] = lat
 
     def advance(self) -> None:
