@@ -710,3 +710,56 @@ def test_run_device_traced_matches_host(qz):
     assert np.array_equal(dB.cpu().numpy(), B)
     assert np.array_equal(dF.cpu().numpy(), F)
     assert np.array_equal(a.download(), b.download())
+
+
+@pytest.mark.parametrize("layout,L", [("i8", 4), ("i8", 6), ("bit", 64)])
+def test_zero_sweep_calls_change_nothing(qz, layout, L):
+    """Empty runs: zero sweeps with and without traces, an empty list of
+    traced sweeps, and an asynchronous zero-sweep run leave the state and
+    the time as they were and return empty traces."""
+    import torch
+    say("zero sweeps", layout, L)
+    lat = qz.Lattice(L, 5, layout)
+    lat.run(3)
+    s0, t0 = lat.download(), lat.t
+    assert lat.run(0).size == 0
+    assert lat.run(0, 1).size == 0
+    B, F = lat.run_at(0, [])
+    assert B.size == 0 and F.size == 0
+    dev = torch.full((2,), -7, dtype=torch.int64, device="cuda")
+    lat.run_device(0, 1, dev)
+    torch.cuda.synchronize()
+    assert dev.cpu().tolist() == [-7, -7]
+    assert lat.t == t0 and np.array_equal(lat.download(), s0)
+    # and the trajectory goes on as if nothing had been called
+    ref = qz.Lattice(L, 5, layout)
+    ref.run(3)
+    assert np.array_equal(lat.run(4, 2), ref.run(4, 2))
+    assert np.array_equal(lat.download(), ref.download())
+
+
+def test_batch_zero_sweeps_and_all_parked(qz):
+    """A batch advanced zero sweeps, or with every slot parked, keeps its
+    states and times; unparked, each slot goes on exactly as a lone run."""
+    specs = [(64, 71), (128, 72)]
+    b = qz.Batch(specs, trace_every=5, trace_cap=16)
+    b.run(10)
+    b.sync()
+    states = [b.download(i) for i in range(len(specs))]
+    b.run(0)
+    for i in range(len(specs)):
+        b.set_active(i, False)
+    b.run(20)
+    b.sync()
+    for i, (L, seed) in enumerate(specs):
+        assert b.time(i) == 10
+        assert np.array_equal(b.download(i), states[i])
+        b.set_active(i, True)
+    b.run(10)
+    b.sync()
+    for i, (L, seed) in enumerate(specs):
+        lone = qz.Lattice(L, seed, "bit")
+        tr = lone.run(20, 5)
+        assert b.time(i) == 20
+        assert np.array_equal(b.download(i), lone.download())
+        assert np.array_equal(b.trace(i, 10, 2), tr[2:4])
