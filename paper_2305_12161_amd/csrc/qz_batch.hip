@@ -174,11 +174,12 @@ __device__ __forceinline__ void batch_body(const BatchArgs &A)
         for (int v = 0; v < 4; ++v)
             r[v] = rb.w[v];
     };
+    // Step qi updates colour 0 of plane zq for qi = -1 .. nz and colour 1 of
+    // plane zm for qi = 1 .. nz; a step's words are drawn only where its
+    // update runs (the draw for step qi + 1 is made at step qi).
     uint32_t s0[4] = {0u, 0u, 0u, 0u}, s1[4] = {0u, 0u, 0u, 0u};   // next step's tie words
-    if (act) {
+    if (act)
         draw((z0 + L - 1) % L, 0u, s0);
-        draw((z0 + L - 2) % L, 1u, s1);
-    }
 
     // the step's plane zq and its neighbours, advanced with one wrap test per
     // step instead of divisions by L
@@ -201,9 +202,10 @@ __device__ __forceinline__ void batch_body(const BatchArgs &A)
             r0[v] = s0[v];
             r1[v] = s1[v];
         }
-        if (act) {
+        if (act && qi < (int)nz) {
             draw(z1, 0u, s0);
-            draw(zq, 1u, s1);
+            if (qi >= 0)
+                draw(zq, 1u, s1);
         }
         __syncthreads();
         if (act) {
