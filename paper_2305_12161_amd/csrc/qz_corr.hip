@@ -640,16 +640,22 @@ __device__ __forceinline__ uint32_t transpose32(uint32_t v, uint32_t lane)
 constexpr uint32_t kSwapIn = 520;      // words of a block in LDS: [slot][word][65 rows, padded]
 constexpr uint32_t kSwapOut = 514;     // words per zb in LDS: [row pair][slot][row parity], padded
 
+// Blocks zb held in LDS before they are written out: 16 (64-byte pieces of
+// the output rows) where W allows, else all W of them.
+__host__ __device__ inline uint32_t swap_span(uint32_t W) { return (W & 15u) == 0u ? 16u : W; }
+
 __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, const uint32_t *P0,
                                                     const uint32_t *P1, uint32_t *Q0, uint32_t *Q1)
 {
     // One workgroup of 256 threads per (y, group xg of four 64-column blocks,
     // one per wave): it builds the 256 rows (z' = x, y) of Q for x in
-    // [256 xg, 256 xg + 256) in LDS, block zb by block zb, and writes them
-    // out whole.
+    // [256 xg, 256 xg + 256) in LDS, F blocks zb at a time, and writes out
+    // each row's F words of those blocks (F = swap_span(W): with 64-byte
+    // pieces the LDS of three workgroups fits a CU).
     extern __shared__ uint32_t sm[];
-    uint32_t *out = sm;                   // [zb][128 row pairs][2 slots][2 rows]
-    uint32_t *in = sm + kSwapOut * W;     // [2 buffers][2 blocks][kSwapIn]
+    const uint32_t F = swap_span(W);
+    uint32_t *out = sm;                   // [F blocks][128 row pairs][2 slots][2 rows]
+    uint32_t *in = sm + kSwapOut * F;     // [2 buffers][2 blocks][kSwapIn]
     const uint32_t ngroups = W / 4;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // a y's groups share an XCD
     const uint32_t y = tile / ngroups, xg = tile % ngroups;
@@ -676,6 +682,7 @@ __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, con
     // this lane's row of a block: z = 2 zh + p
     const uint32_t zh = (lane & 3u) | ((lane >> 3) << 2), p = (lane >> 2) & 1u;
     const uint32_t rz = 2u * zh + p;
+    const uint32_t nq = F / 4;            // 16-byte quads of a row's piece
     for (uint32_t pp = 0; pp < npairs; ++pp) {
         // the pair's segments into this iteration's buffer; the other buffer
         // was last read before the previous barrier
@@ -692,30 +699,34 @@ __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, con
             pre[a] = pre[a + 1];
         pre[kAhead - 1] = fetch(min(pp + kAhead, npairs - 1u));
         __syncthreads();
+        const uint32_t zb0 = 2u * pp - (2u * pp) % F;      // first block of this piece
 #pragma unroll
         for (uint32_t hb = 0; hb < 2; ++hb) {
-            const uint32_t zb = 2u * pp + hb;
+            const uint32_t zl = 2u * pp + hb - zb0;
             const uint32_t *bb = ib + hb * kSwapIn;
             // wave wv: x block 4 xg + wv, word wv of each segment
             const uint32_t we = transpose32(bb[wv * 65u + rz], lane);          // q = 0
             const uint32_t wo = transpose32(bb[(4u + wv) * 65u + rz], lane);   // q = 1
             // rows z' = 64 wv + 2 zh + q of Q's group, slot p, word zb
             const uint32_t r2 = 32u * wv + zh;
-            *reinterpret_cast<uint2 *>(out + zb * kSwapOut + r2 * 4u + p * 2u) = make_uint2(we, wo);
+            *reinterpret_cast<uint2 *>(out + zl * kSwapOut + r2 * 4u + p * 2u) = make_uint2(we, wo);
         }
-    }
-    __syncthreads();
-    // rows z' = 256 xg + row: parity slot p' goes to colour (p' + y + z') & 1;
-    // item it: quad w4 of the words of (row, slot), 16 bytes to global memory
-    const uint32_t nq = W / 4;
-    for (uint32_t it = threadIdx.x; it < 512u * nq; it += blockDim.x) {
-        const uint32_t w4 = it % nq, rs = it / nq;
-        const uint32_t row = rs >> 1, slot = rs & 1u;
-        const uint32_t *src = out + (4u * w4) * kSwapOut + (row >> 1) * 4u + slot * 2u + (row & 1u);
-        const uint4 v = make_uint4(src[0], src[kSwapOut], src[2u * kSwapOut], src[3u * kSwapOut]);
-        const uint32_t zp = 256u * xg + row;
-        const uint32_t c = slot ^ ((y + zp) & 1u);
-        *reinterpret_cast<uint4 *>((c ? Q1 : Q0) + ((size_t)zp * L + y) * W + 4u * w4) = v;
+        if (2u * pp + 2u - zb0 < F)
+            continue;
+        // the piece is complete: rows z' = 256 xg + row, parity slot p' to
+        // colour (p' + y + z') & 1; item it: quad w4 of (row, slot)'s piece.
+        // The next pair's LDS writes come after its barrier, so no thread
+        // overwrites the piece before every thread has written it out.
+        __syncthreads();
+        for (uint32_t it = threadIdx.x; it < 512u * nq; it += blockDim.x) {
+            const uint32_t rs = it / nq, w4 = it - rs * nq;
+            const uint32_t row = rs >> 1, slot = rs & 1u;
+            const uint32_t *src = out + (4u * w4) * kSwapOut + (row >> 1) * 4u + slot * 2u + (row & 1u);
+            const uint4 v = make_uint4(src[0], src[kSwapOut], src[2u * kSwapOut], src[3u * kSwapOut]);
+            const uint32_t zp = 256u * xg + row;
+            const uint32_t c = slot ^ ((y + zp) & 1u);
+            *reinterpret_cast<uint4 *>((c ? Q1 : Q0) + ((size_t)zp * L + y) * W + zb0 + 4u * w4) = v;
+        }
     }
 }
 
@@ -836,8 +847,8 @@ hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32
         if (gram_x) {
             // x: the z axis of the lattice with x and z swapped (into Q)
             hipLaunchKernelGGL(k_bit_swap_xz, dim3(L * (W / 4)), dim3(256),
-                               (size_t)(kSwapOut * W + 4 * kSwapIn) * 4, st, L, W, P0, P1, Q0,
-                               Q1);
+                               (size_t)(kSwapOut * swap_span(W) + 4 * kSwapIn) * 4, st, L, W, P0,
+                               P1, Q0, Q1);
             hipLaunchKernelGGL((k_corr_gram<2, kGramNB>), grid_gram, dim3(256), 0, st, gg, Q0, Q1,
                                anti);
         }
