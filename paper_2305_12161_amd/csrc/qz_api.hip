@@ -209,6 +209,24 @@ struct TracePlan {
 int run_plan(qz_lattice *q, uint64_t n, const TracePlan &plan, unsigned long long *dev_trace,
              unsigned long long *dev_flips)
 {
+    if (q->layout == QZ_LAYOUT_I8 && qz::i8_onchip_ok(q->L) && plan.n_at == 0 &&
+        plan.every <= 0xFFFFFFFFull) {
+        // a small int8 lattice: all the sweeps on chip, in launches of whole
+        // multiples of the trace cadence
+        const uint64_t every = plan.every;
+        const uint64_t piece = every > 0 ? std::max<uint64_t>(every, 65536 / every * every) : 65536;
+        for (uint64_t k = 0; k < n;) {
+            const uint64_t m = std::min<uint64_t>(piece, n - k);
+            const uint64_t e = every > 0 ? k / every : 0;
+            QZ_HIP(q, qz::i8_onchip_run(q->st, q->L, q->seed, (uint32_t)q->t, (uint32_t)m, q->mixed,
+                                        i8_spins(q), (uint32_t)every,
+                                        dev_trace != nullptr ? dev_trace + e : nullptr,
+                                        dev_flips != nullptr ? dev_flips + e : nullptr));
+            q->t += m;
+            k += m;
+        }
+        return QZ_OK;
+    }
     const bool pairs = q->pass == 2 && q->layout == QZ_LAYOUT_BIT && q->dcb == 0;
     auto slot = [&](unsigned long long *base, int64_t e) -> unsigned long long * {
         return (base != nullptr && e >= 0) ? base + e : nullptr;

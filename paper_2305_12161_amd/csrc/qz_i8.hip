@@ -115,15 +115,87 @@ __global__ void __launch_bounds__(kThreads)
 // Sum of the four bytes of v (each at most 63).
 __device__ __forceinline__ uint32_t byte_sum(uint32_t v) { return (v * 0x01010101u) >> 24; }
 
-// Half-sweep for L % 16 == 0 on 16-byte chunks along x: thread per chunk of
-// one plane (blockIdx.y = z).  A site's spin becomes a bit per byte (1 where
-// it is -1); its six neighbour bits come from 16-byte loads of the rows y +-
-// 1 and planes z +- 1, and for x from the chunk itself shifted by one byte,
-// with one byte loaded at each end.  The anti-aligned count a (0..6) is then
-// a bytewise sum of six XORs, four sites per 32-bit word; a >= 4 flips, a ==
-// 3 flips on the site's tie bit.  The chunk's 8 sites of colour p have
-// consecutive colour indices j0 .. j0 + 7, i.e. one byte of one Philox
-// output word.
+// One 16-byte chunk along x (sites x0 .. x0+15 of row (y, z), L % 16 == 0)
+// of a colour-p half-sweep, in place.  A site's spin becomes a bit per byte
+// (1 where it is -1); its six neighbour bits come from 16-byte loads of the
+// rows y +- 1 and planes z +- 1, and for x from the chunk itself shifted by
+// one byte, with one byte loaded at each end.  The anti-aligned count a
+// (0..6) is then a bytewise sum of six XORs, four sites per 32-bit word; a >=
+// 4 flips, a == 3 flips on the site's tie bit.  The chunk's 8 sites of colour
+// p have consecutive colour indices j0 .. j0 + 7, i.e. one byte of one Philox
+// output word.  The lattice is reached through `ld16(offset)`, `ld1(offset)`
+// and `st16(offset, value)`, so that the same update runs on global memory and
+// on a lattice held in LDS.  Adds the chunk's anti-aligned counts over the
+// colour-p sites to asum and its flips to fsum.
+template <class Off, class LD16, class LD1, class ST16>
+__device__ __forceinline__ void i8_chunk(uint32_t L, uint32_t p, uint32_t y, uint32_t z,
+                                         uint32_t x0, uint32_t t, uint32_t k0, uint32_t k1,
+                                         LD16 ld16, LD1 ld1, ST16 st16, uint32_t &asum,
+                                         uint32_t &fsum)
+{
+    const Off LL = (Off)L * L;
+    const Off rb = (Off)z * LL + (Off)y * L;
+    const uint4 vme = ld16(rb + x0);
+    const uint4 vym = ld16((Off)z * LL + (Off)wrap_dn(y, L) * L + x0);
+    const uint4 vyp = ld16((Off)z * LL + (Off)wrap_up(y, L) * L + x0);
+    const uint4 vzm = ld16((Off)wrap_dn(z, L) * LL + (Off)y * L + x0);
+    const uint4 vzp = ld16((Off)wrap_up(z, L) * LL + (Off)y * L + x0);
+    const uint32_t lbit = ((uint32_t)(uint8_t)ld1(rb + (x0 == 0 ? L - 1 : x0 - 1)) >> 7) & 1u;
+    const uint32_t rbit = ((uint32_t)(uint8_t)ld1(rb + (x0 + 16 == L ? 0 : x0 + 16)) >> 7) & 1u;
+    constexpr uint32_t kOnes = 0x01010101u;
+    const uint32_t me[4] = {vme.x, vme.y, vme.z, vme.w};
+    const uint32_t ym[4] = {vym.x, vym.y, vym.z, vym.w};
+    const uint32_t yp[4] = {vyp.x, vyp.y, vyp.z, vyp.w};
+    const uint32_t zm[4] = {vzm.x, vzm.y, vzm.z, vzm.w};
+    const uint32_t zp[4] = {vzp.x, vzp.y, vzp.z, vzp.w};
+    uint32_t u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        u[k] = (me[k] >> 7) & kOnes;
+    // bytes of colour p: those whose offset k in the chunk has the parity
+    // (p + y + z) & 1 (x0 is even); as 0x01 flags per byte
+    const uint32_t kpar = (p + y + z) & 1u;
+    const uint32_t cm = kpar ? 0x01000100u : 0x00010001u;
+    const Off j0 = (Off)z * L * (L >> 1) + (Off)y * (L >> 1) + (x0 >> 1);
+    uint32_t ge4[4], eq3[4], ties = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t xl = (u[k] << 8) | (k == 0 ? lbit : u[k - 1] >> 24);
+        const uint32_t xr = (u[k] >> 8) | ((k == 3 ? rbit : u[k + 1]) << 24);
+        const uint32_t a = (u[k] ^ xl) + (u[k] ^ xr) + (u[k] ^ ((ym[k] >> 7) & kOnes)) +
+                           (u[k] ^ ((yp[k] >> 7) & kOnes)) + (u[k] ^ ((zm[k] >> 7) & kOnes)) +
+                           (u[k] ^ ((zp[k] >> 7) & kOnes));
+        asum += byte_sum(a & (cm * 7u));
+        ge4[k] = (a >> 2) & cm;                          // a <= 6: bit 2 set iff a >= 4
+        eq3[k] = a & (a >> 1) & ~(a >> 2) & cm;          // a == 3
+        ties |= eq3[k];
+    }
+    uint32_t r[4] = {0u, 0u, 0u, 0u};
+    if (ties) {
+        const Words4 w = philox10((uint32_t)(j0 >> 7), t, p, 0u, k0, k1);
+        const uint32_t sel = (uint32_t)(j0 >> 5) & 3u;     // selected, not indexed (no scratch)
+        const uint32_t word = sel == 0u ? w.w[0] : sel == 1u ? w.w[1] : sel == 2u ? w.w[2] : w.w[3];
+        const uint32_t bits = (word >> (j0 & 31)) & 0xFFu;
+        // site m (j0 + m) is byte 2m + kpar of the chunk
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            r[k] = (((bits >> (2 * k)) & 1u) << (8 * kpar)) |
+                   (((bits >> (2 * k + 1)) & 1u) << (8 * (2 + kpar)));
+    }
+    uint32_t out[4], any = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t f = ge4[k] | (eq3[k] & r[k]);
+        fsum += byte_sum(f);
+        out[k] = me[k] ^ (f * 0xFEu);                    // +1 (0x01) <-> -1 (0xFF)
+        any |= f;
+    }
+    if (any)
+        st16(rb + x0, make_uint4(out[0], out[1], out[2], out[3]));
+}
+
+// Half-sweep for L % 16 == 0: thread per 16-byte chunk of one plane
+// (blockIdx.y = z), global memory.
 __global__ void __launch_bounds__(kThreads)
     k_i8_half16(uint32_t L, uint32_t k0, uint32_t k1, uint32_t t, uint32_t which, uint32_t mixed,
                 int8_t *s, unsigned long long *bond_acc, unsigned long long *flip_acc)
@@ -133,73 +205,85 @@ __global__ void __launch_bounds__(kThreads)
     const uint32_t q = blockIdx.x * kThreads + threadIdx.x;   // chunk within the plane
     uint32_t asum = 0, fsum = 0;
     if (q < L * C) {
-        const uint32_t cx = q % C, y = q / C, x0 = cx << 4;
-        const uint64_t LL = (uint64_t)L * L;
-        const uint64_t rb = (uint64_t)z * LL + (uint64_t)y * L;
-        const uint4 vme = *reinterpret_cast<const uint4 *>(s + rb + x0);
-        const uint4 vym =
-            *reinterpret_cast<const uint4 *>(s + (uint64_t)z * LL + (uint64_t)wrap_dn(y, L) * L + x0);
-        const uint4 vyp =
-            *reinterpret_cast<const uint4 *>(s + (uint64_t)z * LL + (uint64_t)wrap_up(y, L) * L + x0);
-        const uint4 vzm =
-            *reinterpret_cast<const uint4 *>(s + (uint64_t)wrap_dn(z, L) * LL + (uint64_t)y * L + x0);
-        const uint4 vzp =
-            *reinterpret_cast<const uint4 *>(s + (uint64_t)wrap_up(z, L) * LL + (uint64_t)y * L + x0);
-        const uint32_t lbit = ((uint32_t)(uint8_t)s[rb + (x0 == 0 ? L - 1 : x0 - 1)] >> 7) & 1u;
-        const uint32_t rbit = ((uint32_t)(uint8_t)s[rb + (x0 + 16 == L ? 0 : x0 + 16)] >> 7) & 1u;
-        constexpr uint32_t kOnes = 0x01010101u;
-        const uint32_t me[4] = {vme.x, vme.y, vme.z, vme.w};
-        const uint32_t ym[4] = {vym.x, vym.y, vym.z, vym.w};
-        const uint32_t yp[4] = {vyp.x, vyp.y, vyp.z, vyp.w};
-        const uint32_t zm[4] = {vzm.x, vzm.y, vzm.z, vzm.w};
-        const uint32_t zp[4] = {vzp.x, vzp.y, vzp.z, vzp.w};
-        uint32_t u[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            u[k] = (me[k] >> 7) & kOnes;
-        // bytes of colour p: those whose offset k in the chunk has the parity
-        // (p + y + z) & 1 (x0 is even); as 0x01 flags per byte
-        const uint32_t kpar = (p + y + z) & 1u;
-        const uint32_t cm = kpar ? 0x01000100u : 0x00010001u;
-        const uint64_t j0 = (uint64_t)z * L * (L >> 1) + (uint64_t)y * (L >> 1) + (x0 >> 1);
-        uint32_t ge4[4], eq3[4], ties = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t xl = (u[k] << 8) | (k == 0 ? lbit : u[k - 1] >> 24);
-            const uint32_t xr = (u[k] >> 8) | ((k == 3 ? rbit : u[k + 1]) << 24);
-            const uint32_t a = (u[k] ^ xl) + (u[k] ^ xr) + (u[k] ^ ((ym[k] >> 7) & kOnes)) +
-                               (u[k] ^ ((yp[k] >> 7) & kOnes)) + (u[k] ^ ((zm[k] >> 7) & kOnes)) +
-                               (u[k] ^ ((zp[k] >> 7) & kOnes));
-            asum += byte_sum(a & (cm * 7u));
-            ge4[k] = (a >> 2) & cm;                          // a <= 6: bit 2 set iff a >= 4
-            eq3[k] = a & (a >> 1) & ~(a >> 2) & cm;          // a == 3
-            ties |= eq3[k];
-        }
-        uint32_t r[4] = {0u, 0u, 0u, 0u};
-        if (ties) {
-            const Words4 w = philox10((uint32_t)(j0 >> 7), t, p, 0u, k0, k1);
-            const uint32_t bits = (w.w[(j0 >> 5) & 3] >> (j0 & 31)) & 0xFFu;
-            // site m (j0 + m) is byte 2m + kpar of the chunk
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                r[k] = (((bits >> (2 * k)) & 1u) << (8 * kpar)) |
-                       (((bits >> (2 * k + 1)) & 1u) << (8 * (2 + kpar)));
-        }
-        uint32_t out[4], any = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t f = ge4[k] | (eq3[k] & r[k]);
-            fsum += byte_sum(f);
-            out[k] = me[k] ^ (f * 0xFEu);                    // +1 (0x01) <-> -1 (0xFF)
-            any |= f;
-        }
-        if (any)
-            *reinterpret_cast<uint4 *>(s + rb + x0) = make_uint4(out[0], out[1], out[2], out[3]);
+        const uint32_t cx = q % C, y = q / C;
+        i8_chunk<uint64_t>(
+            L, p, y, z, cx << 4, t, k0, k1,
+            [&](uint64_t o) { return *reinterpret_cast<const uint4 *>(s + o); },
+            [&](uint64_t o) { return s[o]; },
+            [&](uint64_t o, uint4 v) { *reinterpret_cast<uint4 *>(s + o) = v; }, asum, fsum);
     }
     if (bond_acc != nullptr)
         block_add_u64(asum, bond_acc);
     if (flip_acc != nullptr)
         block_add_u64(fsum, flip_acc);
+}
+
+// n sweeps of a small lattice (L = 16 or 32, at most 32 KiB) in one launch
+// of one workgroup holding the whole lattice in LDS: per
+// half-sweep every thread updates its chunks in place (a colour-p update
+// reads only colour 1 - p), then a barrier; the lattice goes back to global
+// memory at the end.  Sweep t0 + k with k % every == 0 (every > 0) adds its
+// entering bond count to dev_B[k / every] and the spins it flips to
+// dev_F[k / every] (either pointer may be null).
+constexpr uint32_t kI8OnchipThreads = 1024;
+
+__global__ void __launch_bounds__(kI8OnchipThreads)
+    k_i8_onchip(uint32_t L, uint32_t k0, uint32_t k1, uint32_t t0, uint32_t n, uint32_t mixed,
+                int8_t *s, uint32_t every, unsigned long long *dev_B, unsigned long long *dev_F)
+{
+    extern __shared__ uint4 i8o_sm[];
+    __shared__ unsigned long long red[2][kI8OnchipThreads / 64];
+    int8_t *lat = reinterpret_cast<int8_t *>(i8o_sm);
+    const uint32_t N = L * L * L, tid = threadIdx.x;
+    for (uint32_t i = tid; i < N / 16; i += kI8OnchipThreads)
+        i8o_sm[i] = reinterpret_cast<const uint4 *>(s)[i];
+    __syncthreads();
+    const uint32_t C = L >> 4, nchunks = L * L * C;
+    auto ld16 = [&](uint32_t o) { return *reinterpret_cast<const uint4 *>(lat + o); };
+    auto ld1 = [&](uint32_t o) { return lat[o]; };
+    auto st16 = [&](uint32_t o, uint4 v) { *reinterpret_cast<uint4 *>(lat + o) = v; };
+    // L is 16 or 32: chunk q = cx + C (y + L z) by shifts
+    const uint32_t lc = C == 1u ? 0u : 1u, ll = L == 16u ? 4u : 5u;
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint32_t t = t0 + k;
+        const bool traced = every != 0u && k % every == 0u;
+        uint32_t asum = 0, fsum = 0;
+        for (uint32_t which = 0; which < 2; ++which) {
+            const uint32_t p = half_colour(which, mixed, t, k0, k1);
+            uint32_t a = 0;
+#pragma unroll 1
+            for (uint32_t q = tid; q < nchunks; q += kI8OnchipThreads) {
+                const uint32_t row = q >> lc;
+                i8_chunk<uint32_t>(L, p, row & (L - 1u), row >> ll, (q & (C - 1u)) << 4, t, k0, k1,
+                                   ld16, ld1, st16, a, fsum);
+            }
+            if (which == 0)
+                asum = a;
+            __syncthreads();
+        }
+        if (traced && (dev_B != nullptr || dev_F != nullptr)) {
+            const unsigned long long wb = wave_sum_u64(asum), wf = wave_sum_u64(fsum);
+            if ((tid & 63u) == 0u) {
+                red[0][tid >> 6] = wb;
+                red[1][tid >> 6] = wf;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                unsigned long long b = 0, f = 0;
+                for (uint32_t w = 0; w < kI8OnchipThreads / 64; ++w) {
+                    b += red[0][w];
+                    f += red[1][w];
+                }
+                if (dev_B != nullptr)
+                    dev_B[k / every] += b;
+                if (dev_F != nullptr)
+                    dev_F[k / every] += f;
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = tid; i < N / 16; i += kI8OnchipThreads)
+        reinterpret_cast<uint4 *>(s)[i] = i8o_sm[i];
 }
 
 // Per-axis unsatisfied bonds: [s_i != s_{i+e_x}], [.. e_y], [.. e_z]; thread
@@ -388,6 +472,22 @@ hipError_t i8_half_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, 
         hipLaunchKernelGGL(k_i8_half, grid, dim3(kThreads), 0, st, L, k0, k1, t, (uint32_t)which,
                            mixed ? 1u : 0u, s, bond_acc, flip_acc);
     }
+    return hipGetLastError();
+}
+
+bool i8_onchip_ok(uint32_t L) { return L == 16 || L == 32; }
+
+hipError_t i8_onchip_run(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t0, uint32_t n,
+                         bool mixed, int8_t *s, uint32_t every, unsigned long long *dev_B,
+                         unsigned long long *dev_F)
+{
+    if (!i8_onchip_ok(L))
+        return hipErrorInvalidValue;
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_i8_onchip, dim3(1), dim3(kI8OnchipThreads), (size_t)L * L * L, st, L,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), t0, n, mixed ? 1u : 0u, s, every,
+                       dev_B, dev_F);
     return hipGetLastError();
 }
 

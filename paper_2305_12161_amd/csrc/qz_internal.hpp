@@ -47,6 +47,14 @@ hipError_t i8_init(hipStream_t st, uint32_t L, uint64_t seed, int8_t *s);
 // mixed cycle), which = 1: the second.
 // bond_acc / flip_acc (nullable): bond count of the state entering the pass,
 // accepted flips of the pass.
+// Small lattices (L = 16 or 32): n sweeps from time t0 in one
+// launch of one workgroup with the lattice in LDS; sweep t0 + k with
+// k % every == 0 (every > 0) adds its entering bond count to dev_B[k / every]
+// and its flips to dev_F[k / every] (either may be null).
+bool i8_onchip_ok(uint32_t L);
+hipError_t i8_onchip_run(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t0, uint32_t n,
+                         bool mixed, int8_t *s, uint32_t every, unsigned long long *dev_B,
+                         unsigned long long *dev_F);
 hipError_t i8_half_sweep(hipStream_t st, uint32_t L, uint64_t seed, uint32_t t, int which,
                          bool mixed, int8_t *s, unsigned long long *bond_acc,
                          unsigned long long *flip_acc);

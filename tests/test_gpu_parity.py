@@ -763,3 +763,23 @@ def test_batch_zero_sweeps_and_all_parked(qz):
         assert b.time(i) == 20
         assert np.array_equal(b.download(i), lone.download())
         assert np.array_equal(b.trace(i, 10, 2), tr[2:4])
+
+
+@pytest.mark.parametrize("L,mixed", [(16, False), (32, True)])
+def test_i8_onchip_long_run_in_pieces(qz, orc, L, mixed):
+    """Small int8 lattices run on chip in launches of up to 65536 sweeps (whole
+    multiples of the trace cadence): a run across a launch boundary, traced
+    and untraced, equals the oracle's."""
+    say("i8 on chip", L, mixed)
+    seed = 70 + L
+    lat = qz.Lattice(L, seed, "i8")
+    lat.set_cycle(mixed)
+    n, every = 70_000, 7_000
+    tr = lat.run(n, every)
+    s = orc.init(L, seed)
+    want = orc.run(s, seed, 0, n, every, mixed=mixed)
+    assert np.array_equal(tr.astype(np.int64), want)
+    assert np.array_equal(lat.download(), s)
+    lat.run(3)
+    orc.run(s, seed, n, 3, mixed=mixed)
+    assert np.array_equal(lat.download(), s)
