@@ -87,7 +87,7 @@ SERVE_TMAX = (1_000, 10_000)
 # MI355X sustained on this stream, measured once and frozen here.
 SERVE_BUDGET_BYTES = 512 << 20
 SERVE_BATCH_SLOTS = {64: 8, 128: 8, 192: 8, 256: 8}
-SERVE_RATE_PER_S = 35.3   # 0.8 x 44.15 requests/s, the first 300 requests all queued at t = 0
+SERVE_RATE_PER_S = 52.5   # 0.8 x 65.7 requests/s, the first 300 requests all queued at t = 0
 
 
 def request_stream(n: int = 2000, rate_per_s: float = 100.0, master_seed: int = 5,
