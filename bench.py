@@ -89,8 +89,8 @@ def plain_rate(binding, torch, L, n):
 
 def batched_workload(binding, torch, workloads):
     """512 x L64 + 64 x L128 + 8 x L256 replicas, 1e4 MCS, B every 10 MCS each."""
-    specs = [(r.L, r.seed) for r in workloads.batch_config4()]
-    t_max = workloads.batch_config4()[0].t_max
+    specs = [(r.L, r.seed) for r in workloads.batch_mix_584()]
+    t_max = workloads.batch_mix_584()[0].t_max
     warm = binding.Batch(specs[:2] + specs[-1:], trace_every=10, trace_cap=1024)
     warm.run(64)
     warm.sync()
@@ -269,7 +269,7 @@ def int8_workloads(binding, torch, workloads):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / (2 * n)        # two half-sweep launches per sweep
 
-    for cfg in (workloads.CONFIG1, workloads.CONFIG2):
+    for cfg in (workloads.RUN_I8_L32, workloads.RUN_I8_L256):
         L, N = cfg.L, cfg.L ** 3
         lat = binding.Lattice(L, cfg.seed, "i8", stream=st)
         torch.cuda.synchronize()
@@ -360,7 +360,7 @@ def main():
     from paper_2305_12161_amd import binding, workloads
 
     L, seed = args.L, args.seed
-    t_max = workloads.CONFIG3.t_max
+    t_max = workloads.RUN_BIT_L2048.t_max
     W = args.warmup
     K = args.steps if args.steps is not None else max(1, t_max - W)
     corr_times = [] if args.no_corr else [t for t in workloads.log_times(t_max) if W < t <= W + K]

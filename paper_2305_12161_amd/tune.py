@@ -2,7 +2,7 @@
 keeps the fastest.  Results never depend on the tuning, only speed does.
 
     python -m paper_2305_12161_amd.tune --L 2048            # single lattice, both passes
-    python -m paper_2305_12161_amd.tune --batch-config4     # batched replicas
+    python -m paper_2305_12161_amd.tune --batch-mix-584     # batched replicas
 
 Winners are written to tuned.json next to this file; `best_single(L)`,
 `best_pass2(L)` and `best_batch(L)` read them back (None when a size was never
@@ -228,7 +228,7 @@ def tune_batch(specs, sweeps: int = 10000, verbose: bool = True):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--L", type=int, nargs="*", default=[])
-    ap.add_argument("--batch-config4", action="store_true")
+    ap.add_argument("--batch-mix-584", action="store_true")
     ap.add_argument("--out", type=str, default="",
                     help="write the winners to this file instead of tuned.json next to tune.py")
     args = ap.parse_args()
@@ -238,9 +238,9 @@ def main():
     for L in args.L:
         print(json.dumps({"L": L, "best_one_sweep": tune_single(L)}), flush=True)
         print(json.dumps({"L": L, "best_two_sweep": tune_pass2(L)}), flush=True)
-    if args.batch_config4:
+    if args.batch_mix_584:
         from . import workloads
-        specs = [(r.L, r.seed) for r in workloads.batch_config4()]
+        specs = [(r.L, r.seed) for r in workloads.batch_mix_584()]
         print(json.dumps({"batch_best": tune_batch(specs)}), flush=True)
 
 

@@ -46,11 +46,11 @@ class LatticeRun:
     corr_times: tuple = ()  # times at which the axis correlation is taken
 
 
-CONFIG1 = LatticeRun("L32_i8_1e3", 32, "i8", 1, 1000, trace_every=10)
-CONFIG2 = LatticeRun("L256_i8_1e4", 256, "i8", 2, 10_000, trace_every=0,
-                     corr_times=tuple(log_times(10_000)))
-CONFIG3 = LatticeRun("L2048_bit_1e5", 2048, "bit", 3, 100_000, trace_every=0,
-                     corr_times=tuple(log_times(100_000)))
+RUN_I8_L32 = LatticeRun("L32_i8_1e3", 32, "i8", 1, 1000, trace_every=10)
+RUN_I8_L256 = LatticeRun("L256_i8_1e4", 256, "i8", 2, 10_000, trace_every=0,
+                         corr_times=tuple(log_times(10_000)))
+RUN_BIT_L2048 = LatticeRun("L2048_bit_1e5", 2048, "bit", 3, 100_000, trace_every=0,
+                           corr_times=tuple(log_times(100_000)))
 
 
 @dataclass(frozen=True)
@@ -60,7 +60,7 @@ class ReplicaSpec:
     t_max: int
 
 
-def batch_config4() -> List[ReplicaSpec]:
+def batch_mix_584() -> List[ReplicaSpec]:
     """512 replicas at L=64, 64 at L=128 and 8 at L=256, seeds 0x40000000 + r, 1e4 MCS."""
     specs: List[ReplicaSpec] = []
     r = 0

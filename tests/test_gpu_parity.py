@@ -51,11 +51,11 @@ def test_init_matches_oracle(qz, orc, layout, L):
 
 
 # --------------------------------------------------------------------------
-# dynamics: config 1 in full, small and ragged sizes, both layouts
+# dynamics: the L=32 int8 run in full, small and ragged sizes, both layouts
 # --------------------------------------------------------------------------
-def test_config1_full_run(qz, orc):
-    c = wl.CONFIG1
-    say("config1", c)
+def test_i8_L32_full_run(qz, orc):
+    c = wl.RUN_I8_L32
+    say("i8 L=32", c)
     lat = qz.Lattice(c.L, c.seed, "i8")
     tr = lat.run(c.t_max, c.trace_every)
     s, want = oracle_run(orc, c.L, c.seed, c.t_max, c.trace_every)

@@ -89,8 +89,8 @@ def host_axis_sum(t, axis, r, slab=128):
 # --------------------------------------------------------------------------
 # L = 256, int8, seed 2, 1e4 MCS: the whole trajectory against the oracle
 # --------------------------------------------------------------------------
-def test_config2_trajectory_matches_oracle(qz, orc):
-    c = wl.CONFIG2
+def test_i8_L256_trajectory_matches_oracle(qz, orc):
+    c = wl.RUN_I8_L256
     N = c.L ** 3
     lat = qz.Lattice(c.L, c.seed, "i8")
     s = orc.init(c.L, c.seed)
@@ -103,7 +103,7 @@ def test_config2_trajectory_matches_oracle(qz, orc):
         Bo = orc.bonds(s)
         S, M = lat.corr()
         So, Mo = orc.corr(s)
-        say("config2 t =", tc, "B =", int(B.sum()), "M =", M)
+        say("i8 L=256 t =", tc, "B =", int(B.sum()), "M =", M)
         assert np.array_equal(B, Bo), tc
         assert M == Mo, tc
         assert np.array_equal(S, So), tc
@@ -115,19 +115,19 @@ def test_config2_trajectory_matches_oracle(qz, orc):
 # --------------------------------------------------------------------------
 # L = 2048, 1-bit, seed 3, two sweeps per pass: late windows, recounts
 # --------------------------------------------------------------------------
-def test_config3_late_replays_and_recounts(qz, orc):
+def test_L2048_late_replays_and_recounts(qz, orc):
     import torch
-    c = wl.CONFIG3
+    c = wl.RUN_BIT_L2048
     L, seed, N = c.L, c.seed, c.L ** 3
     lat = qz.Lattice(L, seed, "bit")
     assert lat.pass_config()[0] == 2
-    say("config3 late: pass", lat.pass_config())
+    say("L=2048 late: pass", lat.pass_config())
     rng = np.random.default_rng(2048)
     W, T = 160, 8
     for t0 in (1_000, 10_000, c.t_max - T):
         lat.run(t0 - lat.t)
         o = [int(v) for v in rng.integers(0, L, size=3)]
-        say("config3 replay at", t0, o)
+        say("L=2048 replay at", t0, o)
         full = t0 == 10_000
         if full:
             s = lat.download()
@@ -140,7 +140,7 @@ def test_config3_late_replays_and_recounts(qz, orc):
             assert B_entering == int(Bh.sum())
     assert lat.t == c.t_max
     # the final state: host recount, and the correlation sums
-    say("config3 final download")
+    say("L=2048 final download")
     s = lat.download()
     Bh = orc.bonds(s)
     assert np.array_equal(lat.bonds(), Bh)
@@ -156,14 +156,14 @@ def test_config3_late_replays_and_recounts(qz, orc):
         assert fold == sq[a], a
     for a in range(3):
         for r in (2, 257, L // 2):
-            say("config3 direct S", a, r)
+            say("L=2048 direct S", a, r)
             assert int(S[a, r]) == host_axis_sum(ts, a, r), (a, r)
 
 
-def test_config3_mixed_cycle_replay_t1e4(qz, orc):
+def test_L2048_mixed_cycle_replay_t1e4(qz, orc):
     """The mixed cycle at L = 2048 (pairs of sweeps of either order share a
     pass) replayed by the oracle's mixed-cycle window at t0 = 1e4."""
-    c = wl.CONFIG3
+    c = wl.RUN_BIT_L2048
     L, seed = c.L, c.seed
     lat = qz.Lattice(L, seed, "bit")
     lat.set_cycle(True)
@@ -175,11 +175,11 @@ def test_config3_mixed_cycle_replay_t1e4(qz, orc):
     rng = np.random.default_rng(4096)
     for _ in range(2):
         o = [int(v) for v in rng.integers(0, L, size=3)]
-        say("config3 mixed replay at", lat.t, o)
+        say("L=2048 mixed replay at", lat.t, o)
         replay(orc, lat, seed, o, 160, 8, mixed=True)
 
 
-def test_config3_same_tile_full_run_L256(qz, orc):
+def test_L2048_tile_full_run_L256(qz, orc):
     """The two-sweep tile of the L = 2048 default, read from an L = 2048 handle,
     on a full L = 256 run against the oracle."""
     big = qz.Lattice(2048, 3, "bit")

@@ -46,9 +46,9 @@ def check_identities(lat, S, M, N):
     assert abs(M) <= N and (M - N) % 2 == 0
 
 
-def test_config2_full_run(qz, orc):
+def test_i8_L256_full_run(qz, orc):
     """L=256 int8, seed 2, 1e4 MCS with C(r) at the 40 log-spaced times."""
-    c = wl.CONFIG2
+    c = wl.RUN_I8_L256
     N = c.L ** 3
     lat = qz.Lattice(c.L, c.seed, "i8")
     for t in c.corr_times:
@@ -64,20 +64,20 @@ def test_config2_full_run(qz, orc):
     assert M == Mo and np.array_equal(S, So)
 
 
-def test_config2_window_replays(qz, orc):
+def test_i8_L256_window_replays(qz, orc):
     """The same trajectory, replayed by the oracle in windows at early, middle and late times."""
-    c = wl.CONFIG2
+    c = wl.RUN_I8_L256
     lat = qz.Lattice(c.L, c.seed, "i8")
     rng = np.random.default_rng(2)
     for t0 in (1, 1000, 9990):
         lat.run(t0 - lat.t)
         o = [int(v) for v in rng.integers(0, c.L, size=3)]
-        print("config2 replay at", t0, o, flush=True)
+        print("i8 L=256 replay at", t0, o, flush=True)
         assert replay(orc, lat, c.L, c.seed, o, 64 + 4 * 5, 5)
 
 
-def test_config2_trace_and_recount(qz, orc):
-    c = wl.CONFIG2
+def test_i8_L256_trace_and_recount(qz, orc):
+    c = wl.RUN_I8_L256
     lat = qz.Lattice(c.L, c.seed, "i8")
     tr = lat.run(300, 10)
     s = lat.download()
@@ -89,13 +89,13 @@ def test_config2_trace_and_recount(qz, orc):
 
 
 @pytest.mark.parametrize("sweeps", [1, 2])
-def test_config3_window_replays_L2048(qz, orc, sweeps):
+def test_L2048_window_replays(qz, orc, sweeps):
     """L=2048 bit, seed 3, with the default tunings bench.py times (one and two
     sweeps per pass); replayed windows."""
-    c = wl.CONFIG3
+    c = wl.RUN_BIT_L2048
     lat = qz.Lattice(c.L, c.seed, "bit")
     lat.set_pass(sweeps)
-    print("config3 tuning", lat.tuning(), lat.pass_config(), flush=True)
+    print("L=2048 tuning", lat.tuning(), lat.pass_config(), flush=True)
     # the start itself, at a few windows, against the oracle's start
     for o in ((0, 0, 0), (2000, 1000, 5), (1024, 2047, 2047)):
         assert np.array_equal(lat.window(o, 48), orc.init_window(c.L, c.seed, o, 48))
@@ -103,7 +103,7 @@ def test_config3_window_replays_L2048(qz, orc, sweeps):
     for t0 in (0, 60, 200):
         lat.run(t0 - lat.t)
         o = [int(v) for v in rng.integers(0, c.L, size=3)]
-        print("config3 replay at", t0, o, flush=True)
+        print("L=2048 replay at", t0, o, flush=True)
         assert replay(orc, lat, c.L, c.seed, o, 128 + 4 * 8, 8)
     S, M = lat.corr()
     check_identities(lat, S, M, c.L ** 3)
@@ -114,16 +114,16 @@ def test_config3_window_replays_L2048(qz, orc, sweeps):
     assert lat_t == 218 and int(tr[0]) >= int(B.sum())  # energy never rises
 
 
-def test_config3_two_sweep_pass_L2048(qz, orc):
+def test_L2048_two_sweep_pass(qz, orc):
     """L=2048, seed 3, with two sweeps per pass: identical to the one-sweep pass
     (bond trace and state), and replayed windows against the oracle."""
-    c = wl.CONFIG3
+    c = wl.RUN_BIT_L2048
     one = qz.Lattice(c.L, c.seed, "bit")
     one.set_pass(1)
     two = qz.Lattice(c.L, c.seed, "bit")
     two.set_pass(2)
     assert one.pass_config()[0] == 1 and two.pass_config()[0] == 2
-    print("config3 two-sweep", two.pass_config(), flush=True)
+    print("L=2048 two-sweep", two.pass_config(), flush=True)
     tr1 = one.run(24, 3)
     tr2 = two.run(24, 3)
     assert np.array_equal(tr1, tr2)
@@ -132,7 +132,7 @@ def test_config3_two_sweep_pass_L2048(qz, orc):
     del one
     rng = np.random.default_rng(33)
     o = [int(v) for v in rng.integers(0, c.L, size=3)]
-    print("config3 two-sweep replay", o, flush=True)
+    print("L=2048 two-sweep replay", o, flush=True)
     assert replay(orc, two, c.L, c.seed, o, 128 + 4 * 10, 10)
     S, M = two.corr()
     check_identities(two, S, M, c.L ** 3)
@@ -216,19 +216,19 @@ def test_physics_band_ell_L256(qz):
     assert 0.7 * band["mean_ell_checkerboard"] < mean < 1.3 * band["mean_ell_checkerboard"]
 
 
-def test_config4_batch_all_replicas(qz, orc):
+def test_batch_584_all_replicas(qz, orc):
     """The 584-replica batch (512 x L64 + 64 x L128 + 8 x L256, seeds
     0x40000000 + r, B every 10 MCS): after 10^3 MCS every replica equals the
     same (L, seed) run alone on the GPU; after 10^4 MCS 16 L64 and 2 L128
     replicas equal the oracle's full runs, and one L256 replica equals the
     oracle at 10^3 MCS and in a window replay at 10^4 MCS."""
-    specs = [(r.L, r.seed) for r in wl.batch_config4()]
+    specs = [(r.L, r.seed) for r in wl.batch_mix_584()]
     every, t1, t2 = 10, 1000, 10_000
     b = qz.Batch(specs, trace_every=every, trace_cap=t2 // every + 8)
     b.set_tuning(64, 0, 100)
     b.run(t1)
     b.sync()
-    print("config4 batch at t=1000: checking", len(specs), "replicas", flush=True)
+    print("584-replica batch at t=1000: checking", len(specs), "replicas", flush=True)
     at_t1 = {}
     for slot, (L, seed) in enumerate(specs):
         lat = qz.Lattice(L, seed, "bit")
@@ -241,7 +241,7 @@ def test_config4_batch_all_replicas(qz, orc):
         del lat
     b.run(t2 - t1)
     b.sync()
-    print("config4 batch at t=1e4: oracle comparisons", flush=True)
+    print("584-replica batch at t=1e4: oracle comparisons", flush=True)
     picks = [k * 32 for k in range(16)] + [512, 575]          # 16 L64, 2 L128
     for slot in picks:
         L, seed = specs[slot]

@@ -310,7 +310,7 @@ def test_served_cancel_mid_flight_gpu():
 
 
 @pytest.mark.gpu
-def test_served_config5_stream_prefix(orc):
+def test_served_stream_prefix(orc):
     """The first 120 requests of the served stream (L uniform in {64, 96, 128,
     192, 256, 384, 512}, t_max in {1e3, 1e4}, seeds 0x50000000 + idx), all
     queued at once on the configured memory budget and batch slots: every
