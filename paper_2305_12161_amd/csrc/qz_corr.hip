@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(kBlock) k_corr_x(uint32_t L, uint32_t W, const
 
 // ---------------------------------------------------------------------------
 // Axis sums on the matrix cores (y and z directly, x through the copy with x
-// and z swapped, below).  For axis a, row u is the plane of sites
+// and y swapped, below).  For axis a, row u is the plane of sites
 // at coordinate u along a, and column k one of the L^2 lines along a; with
 // b = 1 for up spins, the Gram matrix G[u][u'] = sum_k b(u,k) b(u',k) gives
 //   T(r) = sum_u G[u][(u + r) mod L]   (up-up pairs at separation r),
@@ -577,21 +577,22 @@ __global__ void k_corr_gram_finish(unsigned long long *tb, uint32_t R, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Swap the x and z axes of a 1-bit lattice into Q: Q holds the lattice s' with
-// s'(x', y, z') = s(z', y, x'), in the same colour-separated layout (the
-// colour x + y + z is unchanged), so the z-axis sums of Q are the x-axis sums
-// of P and the x axis can run on the matrix cores too.
+// Swap the x and y axes of a 1-bit lattice into Q: Q holds the lattice s' with
+// s'(x', y', z) = s(y', x', z), in the same colour-separated layout (the
+// colour x + y + z is unchanged), so the y-axis sums of Q are the x-axis sums
+// of P and the x axis runs on the matrix cores too, with the row order of the
+// y axis (rows of one z-plane, adjacent in memory).
 //
-// A block of 64 z by 64 x sites splits by the parities of z and x into four
-// 32 x 32 bit matrices: with z = 2 zh + p and x = 2 xh + q, the word of the
-// x-parity slot q in row z holds bits xh of M_pq[zh].  The word of Q's row
-// z' = x, slot p (the parity of x' = z), holds bit zh of the transpose of
-// M_pq.  A wave holds the 64 rows z of a block, one per lane, with p at lane
-// bit 2 and the five bits of zh at lane bits 0, 1, 3, 4, 5, and transposes
-// its two words (q = 0, 1) in five steps; step j exchanges with the lane that
-// differs in the lane bit of zh's bit j (lane xor 1, 2, 8, 16, 32: quad
-// permutes, a row rotation and the two lane-half swaps, all without LDS)
-// and moves j x j bit blocks with a rotate and a bit select.
+// A block of 64 y by 64 x sites of one z-plane splits by the parities of y
+// and x into four 32 x 32 bit matrices: with y = 2 yh + p and x = 2 xh + q,
+// the word of the x-parity slot q in row y holds bits xh of M_pq[yh].  The
+// word of Q's row y' = x, slot p (the parity of x' = y), holds bit yh of the
+// transpose of M_pq.  A wave holds the 64 rows y of a block, one per lane,
+// with p at lane bit 2 and the five bits of yh at lane bits 0, 1, 3, 4, 5,
+// and transposes its two words (q = 0, 1) in five steps; step j exchanges
+// with the lane that differs in the lane bit of yh's bit j (lane xor 1, 2, 8,
+// 16, 32: quad permutes, a row rotation and the two lane-half swaps, all
+// without LDS) and moves j x j bit blocks with a rotate and a bit select.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t xor_lane(uint32_t v, int lx)
 {
@@ -612,7 +613,7 @@ __device__ __forceinline__ uint32_t xor_lane(uint32_t v, int lx)
 }
 
 // One transposition step on the 32-bit row v of this lane: bits k with
-// (k & j) != 0 of the lane whose zh bit j is clear (a) trade places with bits
+// (k & j) != 0 of the lane whose yh bit j is clear (a) trade places with bits
 // k - j of its partner (b).  a keeps its bits in m and takes the partner's
 // rotated left by j elsewhere; b keeps the bits outside m and takes the
 // partner's rotated right by j in m.
@@ -638,83 +639,99 @@ __device__ __forceinline__ uint32_t transpose32(uint32_t v, uint32_t lane)
 }
 
 constexpr uint32_t kSwapIn = 520;      // words of a block in LDS: [slot][word][65 rows, padded]
-constexpr uint32_t kSwapOut = 514;     // words per zb in LDS: [row pair][slot][row parity], padded
+constexpr uint32_t kSwapOut = 514;     // words per yb in LDS: [row pair][slot][row parity], padded
 
-// Blocks zb held in LDS before they are written out: 16 (64-byte pieces of
+// Blocks yb held in LDS before they are written out: 16 (64-byte pieces of
 // the output rows) where W allows, else all W of them.
 __host__ __device__ inline uint32_t swap_span(uint32_t W) { return (W & 15u) == 0u ? 16u : W; }
 
-__global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, const uint32_t *P0,
+// P16: W is a multiple of 16, so pieces are 16 blocks and a piece is
+// complete after every kAhead = 8 pairs, at the same step of the unrolled
+// pair loop: the stores then sit at one place in the loop, and only the first
+// load after them waits for all memory operations in flight.
+template <bool P16>
+__global__ void __launch_bounds__(256) k_bit_swap_xy(uint32_t L, uint32_t W, const uint32_t *P0,
                                                     const uint32_t *P1, uint32_t *Q0, uint32_t *Q1)
 {
-    // One workgroup of 256 threads per (y, group xg of four 64-column blocks,
-    // one per wave): it builds the 256 rows (z' = x, y) of Q for x in
-    // [256 xg, 256 xg + 256) in LDS, F blocks zb at a time, and writes out
+    // One workgroup of 256 threads per (z, group xg of four 64-column blocks,
+    // one per wave): it builds the 256 rows (y' = x, z) of Q for x in
+    // [256 xg, 256 xg + 256) in LDS, F blocks yb at a time, and writes out
     // each row's F words of those blocks (F = swap_span(W): with 64-byte
     // pieces the LDS of three workgroups fits a CU).
     extern __shared__ uint32_t sm[];
-    const uint32_t F = swap_span(W);
+    const uint32_t F = P16 ? 16u : swap_span(W);
     uint32_t *out = sm;                   // [F blocks][128 row pairs][2 slots][2 rows]
     uint32_t *in = sm + kSwapOut * F;     // [2 buffers][2 blocks][kSwapIn]
     const uint32_t ngroups = W / 4;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // a y's groups share an XCD
-    const uint32_t y = tile / ngroups, xg = tile % ngroups;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);   // a z's groups share an XCD
+    const uint32_t z = tile / ngroups, xg = tile % ngroups;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     // Words 4 xg .. 4 xg + 3 of row (z, y) of one colour plane are one
-    // 16-byte segment; block zb is the 128 segments of rows z = 64 zb + r,
+    // 16-byte segment; block yb is the 128 segments of rows y = 64 yb + r,
     // both parity slots (slot 0 = even x).  Blocks come in pairs, one per half
     // of the workgroup (thread t: segment t & 127 of block 2 pp + t / 128),
     // and kAhead pairs are loaded ahead, so that many 16-byte loads per lane
-    // are in flight.
+    // are in flight.  The row y = 64 (2 pp + half) + sr has the parity of sr,
+    // so a thread reads one colour plane, 128 rows further on per pair.
     const uint32_t seg = threadIdx.x & 127u, half = threadIdx.x >> 7;
     const uint32_t sr = seg >> 1, sslot = seg & 1u;
+    const uint32_t c0 = sslot ^ ((z + sr) & 1u);   // colour holding the parity slot
+    const uint32_t *seg0 = (c0 ? P1 : P0) + ((size_t)z * L + 64u * half + sr) * W + 4u * xg;
+    const size_t pstride = (size_t)128u * W;
     auto fetch = [&](uint32_t pp) -> uint4 {
-        const uint32_t z = 64u * (2u * pp + half) + sr;
-        const uint32_t c = sslot ^ ((y + z) & 1u);   // colour holding the parity slot
-        return *reinterpret_cast<const uint4 *>((c ? P1 : P0) + ((size_t)z * L + y) * W + 4u * xg);
+        return *reinterpret_cast<const uint4 *>(seg0 + pp * pstride);
     };
+    // The pair loop is unrolled by kAhead, so that each prefetch buffer keeps
+    // its registers: shifting the buffers down every pair made the compiler
+    // wait for the load it had just issued before the copy.
     constexpr uint32_t kAhead = 8;
     const uint32_t npairs = W / 2;
     uint4 pre[kAhead];
+    // issued in the order they are used, so that each wait below is for the
+    // oldest loads only
 #pragma unroll
-    for (uint32_t a = 0; a < kAhead; ++a)
+    for (uint32_t a = 0; a < kAhead; ++a) {
         pre[a] = fetch(min(a, npairs - 1u));
-    // this lane's row of a block: z = 2 zh + p
-    const uint32_t zh = (lane & 3u) | ((lane >> 3) << 2), p = (lane >> 2) & 1u;
-    const uint32_t rz = 2u * zh + p;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // this lane's row of a block: y = 2 yh + p
+    const uint32_t yh = (lane & 3u) | ((lane >> 3) << 2), p = (lane >> 2) & 1u;
+    const uint32_t ry = 2u * yh + p;
     const uint32_t nq = F / 4;            // 16-byte quads of a row's piece
-    for (uint32_t pp = 0; pp < npairs; ++pp) {
+    for (uint32_t p0 = 0; p0 < npairs; p0 += kAhead)
+#pragma unroll
+    for (uint32_t a = 0; a < kAhead; ++a) {
+        const uint32_t pp = p0 + a;
+        if (!P16 && pp >= npairs)   // with P16, npairs is a multiple of kAhead
+            break;
         // the pair's segments into this iteration's buffer; the other buffer
         // was last read before the previous barrier
         uint32_t *ib = in + (pp & 1u) * (2u * kSwapIn);
         {
             uint32_t *d = ib + half * kSwapIn + sslot * 4u * 65u + sr;
-            d[0] = pre[0].x;
-            d[65] = pre[0].y;
-            d[130] = pre[0].z;
-            d[195] = pre[0].w;
+            d[0] = pre[a].x;
+            d[65] = pre[a].y;
+            d[130] = pre[a].z;
+            d[195] = pre[a].w;
         }
-#pragma unroll
-        for (uint32_t a = 0; a + 1 < kAhead; ++a)
-            pre[a] = pre[a + 1];
-        pre[kAhead - 1] = fetch(min(pp + kAhead, npairs - 1u));
+        pre[a] = fetch(min(pp + kAhead, npairs - 1u));
         __syncthreads();
-        const uint32_t zb0 = 2u * pp - (2u * pp) % F;      // first block of this piece
+        const uint32_t yb0 = 2u * pp - (2u * pp) % F;      // first block of this piece
 #pragma unroll
         for (uint32_t hb = 0; hb < 2; ++hb) {
-            const uint32_t zl = 2u * pp + hb - zb0;
+            const uint32_t yl = 2u * pp + hb - yb0;
             const uint32_t *bb = ib + hb * kSwapIn;
             // wave wv: x block 4 xg + wv, word wv of each segment
-            const uint32_t we = transpose32(bb[wv * 65u + rz], lane);          // q = 0
-            const uint32_t wo = transpose32(bb[(4u + wv) * 65u + rz], lane);   // q = 1
-            // rows z' = 64 wv + 2 zh + q of Q's group, slot p, word zb
-            const uint32_t r2 = 32u * wv + zh;
-            *reinterpret_cast<uint2 *>(out + zl * kSwapOut + r2 * 4u + p * 2u) = make_uint2(we, wo);
+            const uint32_t we = transpose32(bb[wv * 65u + ry], lane);          // q = 0
+            const uint32_t wo = transpose32(bb[(4u + wv) * 65u + ry], lane);   // q = 1
+            // rows y' = 64 wv + 2 yh + q of Q's group, slot p, word yb
+            const uint32_t r2 = 32u * wv + yh;
+            *reinterpret_cast<uint2 *>(out + yl * kSwapOut + r2 * 4u + p * 2u) = make_uint2(we, wo);
         }
-        if (2u * pp + 2u - zb0 < F)
+        if (P16 ? a + 1 < kAhead : 2u * pp + 2u - yb0 < F)
             continue;
-        // the piece is complete: rows z' = 256 xg + row, parity slot p' to
-        // colour (p' + y + z') & 1; item it: quad w4 of (row, slot)'s piece.
+        // the piece is complete: rows y' = 256 xg + row, parity slot p' to
+        // colour (p' + y' + z) & 1; item it: quad w4 of (row, slot)'s piece.
         // The next pair's LDS writes come after its barrier, so no thread
         // overwrites the piece before every thread has written it out.
         __syncthreads();
@@ -723,9 +740,9 @@ __global__ void __launch_bounds__(256) k_bit_swap_xz(uint32_t L, uint32_t W, con
             const uint32_t row = rs >> 1, slot = rs & 1u;
             const uint32_t *src = out + (4u * w4) * kSwapOut + (row >> 1) * 4u + slot * 2u + (row & 1u);
             const uint4 v = make_uint4(src[0], src[kSwapOut], src[2u * kSwapOut], src[3u * kSwapOut]);
-            const uint32_t zp = 256u * xg + row;
-            const uint32_t c = slot ^ ((y + zp) & 1u);
-            *reinterpret_cast<uint4 *>((c ? Q1 : Q0) + ((size_t)zp * L + y) * W + zb0 + 4u * w4) = v;
+            const uint32_t yp = 256u * xg + row;
+            const uint32_t c = slot ^ ((yp + z) & 1u);
+            *reinterpret_cast<uint4 *>((c ? Q1 : Q0) + ((size_t)z * L + yp) * W + yb0 + 4u * w4) = v;
         }
     }
 }
@@ -845,11 +862,15 @@ hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32
         const GramGeom gg = gram_geom(L, kGramNB);
         const dim3 grid_gram((gg.ntile * gg.nsplit + 3) / 4);
         if (gram_x) {
-            // x: the z axis of the lattice with x and z swapped (into Q)
-            hipLaunchKernelGGL(k_bit_swap_xz, dim3(L * (W / 4)), dim3(256),
-                               (size_t)(kSwapOut * swap_span(W) + 4 * kSwapIn) * 4, st, L, W, P0,
-                               P1, Q0, Q1);
-            hipLaunchKernelGGL((k_corr_gram<2, kGramNB>), grid_gram, dim3(256), 0, st, gg, Q0, Q1,
+            // x: the y axis of the lattice with x and y swapped (into Q)
+            const size_t lds = (size_t)(kSwapOut * swap_span(W) + 4 * kSwapIn) * 4;
+            if ((W & 15u) == 0u)
+                hipLaunchKernelGGL(k_bit_swap_xy<true>, dim3(L * (W / 4)), dim3(256), lds, st, L,
+                                   W, P0, P1, Q0, Q1);
+            else
+                hipLaunchKernelGGL(k_bit_swap_xy<false>, dim3(L * (W / 4)), dim3(256), lds, st, L,
+                                   W, P0, P1, Q0, Q1);
+            hipLaunchKernelGGL((k_corr_gram<1, kGramNB>), grid_gram, dim3(256), 0, st, gg, Q0, Q1,
                                anti);
         }
         hipLaunchKernelGGL((k_corr_gram<1, kGramNB>), grid_gram, dim3(256), 0, st, gg, P0, P1,
