@@ -48,16 +48,32 @@ __device__ __forceinline__ void batch_body(const BatchArgs &A)
         // a replica that has reached its t_max is skipped like a parked one
         act = R.active != 0u && (R.t_max == 0u || R.t + A.step < R.t_max);
     }
-    const uint64_t t64 = act ? R.t + A.step : 0;
+    uint64_t t64 = act ? R.t + A.step : 0;
+    uint32_t rd = act ? ((R.cur ^ A.step) & 1u) : 0u;
+    uint32_t k0 = act ? (uint32_t)R.seed : 0u, k1 = act ? (uint32_t)(R.seed >> 32) : 0u;
+    uint32_t *base = act ? R.base : nullptr;
+    unsigned long long *trace = act ? R.trace : nullptr;
+    if constexpr (WK == 2 || WK == 4) {
+        // Q is a multiple of 64 here, so a wave lies in one sub-tile: the
+        // replica, its time and key and the first plane are the same in all
+        // its lanes, and in scalar registers the Philox key schedule, the
+        // plane steps and the plane addresses leave the vector unit
+        act = wave_u32(act ? 1u : 0u) != 0u;
+        t64 = wave_u64(t64);
+        rd = wave_u32(rd);
+        k0 = wave_u32(k0);
+        k1 = wave_u32(k1);
+        base = wave_ptr(base);
+        trace = wave_ptr(trace);
+        T.z0 = wave_u32(T.z0);
+    }
     const uint32_t t = (uint32_t)t64;
-    const uint32_t rd = act ? ((R.cur ^ A.step) & 1u) : 0u;
     const size_t pw_all = (size_t)L * PW;                // words of one colour plane set
-    const uint32_t *S0 = act ? R.base + (2 * rd + 0) * pw_all : nullptr;
-    const uint32_t *S1 = act ? R.base + (2 * rd + 1) * pw_all : nullptr;
-    uint32_t *D0 = act ? R.base + (2 * (1 - rd) + 0) * pw_all : nullptr;
-    uint32_t *D1 = act ? R.base + (2 * (1 - rd) + 1) * pw_all : nullptr;
-    const bool counting = act && A.every != 0u && R.trace != nullptr && (t64 % A.every) == 0u;
-    const uint32_t k0 = act ? (uint32_t)R.seed : 0u, k1 = act ? (uint32_t)(R.seed >> 32) : 0u;
+    const uint32_t *S0 = act ? base + (2 * rd + 0) * pw_all : nullptr;
+    const uint32_t *S1 = act ? base + (2 * rd + 1) * pw_all : nullptr;
+    uint32_t *D0 = act ? base + (2 * (1 - rd) + 0) * pw_all : nullptr;
+    uint32_t *D1 = act ? base + (2 * (1 - rd) + 1) * pw_all : nullptr;
+    const bool counting = act && A.every != 0u && trace != nullptr && (t64 % A.every) == 0u;
 
     // word geometry of this lane's quad within a plane
     const uint32_t g0 = 4 * lane;
@@ -243,7 +259,7 @@ __device__ __forceinline__ void batch_body(const BatchArgs &A)
     __syncthreads();
     if (counting && lane == 0 && sacc[sub]) {
         const uint32_t slot = (uint32_t)((t64 / A.every) % A.cap);
-        atomicAdd(R.trace + slot, (unsigned long long)sacc[sub]);
+        atomicAdd(trace + slot, (unsigned long long)sacc[sub]);
     }
 }
 
