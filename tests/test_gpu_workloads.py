@@ -216,6 +216,41 @@ def test_physics_band_ell_L256(qz):
     assert 0.7 * band["mean_ell_checkerboard"] < mean < 1.3 * band["mean_ell_checkerboard"]
 
 
+def test_physics_band_porod_L256(qz):
+    """Loose band, not parity: Porod's law on the GPU's structure factor.
+
+    The paper's collapsed S(k, t) decays as k^-(d+1) = k^-4 at large k l
+    (Results, structure-factor discussion).  Two L=256 lattices at the time of
+    the ell band above (l about 20), S(k) from the FFT route averaged over
+    both: its log-log slope over k l in [3, 12] (shells of |k| in units of
+    2 pi / L) lies within 20 % of -4."""
+    from paper_2305_12161_amd import measure
+    with open(os.path.join(GOLDEN, "paper_physics_bands.json")) as f:
+        bands = json.load(f)
+    tb = bands["ell_L256_t4000_rescaled"]
+    porod = bands["porod_exponent"]
+    t = int(round(tb["rescaled_time"] / tb["checkerboard_time_factor"]))
+    L = 256
+    N = L ** 3
+    sks, ells = [], []
+    for r in range(2):
+        lat = qz.Lattice(L, 0x4000_0000 + 640 + r, "bit")
+        lat.run(t)
+        S, M = lat.corr()
+        ells.append(measure.crossing_length(S, M, N))
+        _, Sk, _, nk, _ = lat.fft_corr()
+        sks.append(Sk)
+        del lat
+    ell = float(np.mean(ells))
+    Sk = np.mean(sks, axis=0)
+    k = 2 * np.pi * np.arange(len(Sk)) / L
+    sel = (nk > 0) & (k * ell >= 3) & (k * ell <= 12)
+    slope = float(np.polyfit(np.log(k[sel]), np.log(Sk[sel]), 1)[0])
+    print("Porod: t", t, "ell", ells, "shells", int(sel.sum()), "slope", slope, flush=True)
+    assert sel.sum() >= 8
+    assert abs(slope + porod["value"]) < 0.2 * porod["value"]
+
+
 def test_batch_584_all_replicas(qz, orc):
     """The 584-replica batch (512 x L64 + 64 x L128 + 8 x L256, seeds
     0x40000000 + r, B every 10 MCS): after 10^3 MCS every replica equals the
