@@ -78,6 +78,27 @@ def test_i8_small_sizes(qz, orc, L):
             assert np.array_equal(lat.download(), s)
 
 
+@pytest.mark.parametrize("L", [272, 320])
+def test_i8_chunked_sizes_above_256(qz, orc, L):
+    """The int8 half-sweep of 16-byte chunks at sides above 256 that are not
+    multiples of 64 (L = 272: 17 chunks per row, 320: 20), whose planes do not
+    fill whole workgroups of chunks.  Traces, the full lattice and its bonds
+    equal the oracle's, in both cycles."""
+    for mixed in (False, True):
+        seed = 7000 + L + (1 if mixed else 0)
+        say("i8 chunked", L, "mixed" if mixed else "01")
+        lat = qz.Lattice(L, seed, "i8")
+        lat.set_cycle(mixed)
+        s = orc.init(L, seed)
+        for chunk in (1, 5):
+            tr = lat.run(chunk, 1)
+            want = orc.run(s, seed, lat.t - chunk, chunk, 1, mixed=mixed)
+            assert np.array_equal(tr.astype(np.int64), want), (L, mixed, chunk)
+        assert np.array_equal(lat.download(), s)
+        assert np.array_equal(lat.bonds(), orc.bonds(s))
+        del lat
+
+
 @pytest.mark.parametrize("L", [64, 128, 192, 256])
 def test_bit_default_tuning(qz, orc, L):
     seed = 1000 + L
