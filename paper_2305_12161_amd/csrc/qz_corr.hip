@@ -404,7 +404,9 @@ __global__ void __launch_bounds__(256, 4 / NB) k_corr_gram(GramGeom g, const uin
     __shared__ uint32_t dsum[4][256];   // per wave: the tile's diagonals d - dbase
     const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint32_t i = lane & 31u, h = lane >> 5;
-    const uint32_t item = blockIdx.x * 4u + wv;
+    // workgroups of one XCD take consecutive items (tiles of one chunk that
+    // share row blocks), so that its L2 serves their common rows
+    const uint32_t item = xcd_tile(blockIdx.x, gridDim.x) * 4u + wv;
     if (item >= g.ntile * g.nsplit)      // whole wave
         return;
     uint32_t *ds = dsum[wv];
@@ -860,7 +862,8 @@ hipError_t bit_corr(hipStream_t st, uint32_t L, const uint32_t *P0, const uint32
     }
     if (gram) {
         const GramGeom gg = gram_geom(L, kGramNB);
-        const dim3 grid_gram((gg.ntile * gg.nsplit + 3) / 4);
+        // a multiple of 8 workgroups (whole XCD shares; the extra waves exit)
+        const dim3 grid_gram(((gg.ntile * gg.nsplit + 3) / 4 + 7) / 8 * 8);
         if (gram_x) {
             // x: the y axis of the lattice with x and y swapped (into Q)
             const size_t lds = (size_t)(kSwapOut * swap_span(W) + 4 * kSwapIn) * 4;
