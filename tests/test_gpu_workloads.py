@@ -251,6 +251,47 @@ def test_physics_band_porod_L256(qz):
     assert abs(slope + porod["value"]) < 0.2 * porod["value"]
 
 
+def test_physics_band_cycle_time_factors_L512(qz):
+    """Loose bands, not parity: the paper's time factors order the methods.
+
+    The 01 checkerboard and the 01 double checkerboard share a factor (1.75):
+    at equal raw time their mean ell_C agree within 5 %.  The mixed double
+    checkerboard's factor is lower (1.45), i.e. slower dynamics: the ratio of
+    the mean ell_C, 01 over mixed, lies in [1.0, 1.2].  Six L=512 lattices of
+    each, cubes of side 16, at the raw time of the ell band above.  Measured:
+    0.987 and 1.16 (the factors with a growth exponent of 0.3 - 0.5 alone
+    would put the second near 1.06 - 1.10; a mixed cycle also repeats a
+    colour at half of its sweep boundaries, where the repeated half-sweep
+    can change only ties)."""
+    from paper_2305_12161_amd import measure
+    with open(os.path.join(GOLDEN, "paper_physics_bands.json")) as f:
+        bands = json.load(f)
+    tb = bands["ell_L256_t4000_rescaled"]
+    tf = bands["time_factors"]
+    assert tf["checkerboard_01"] == tf["double_checkerboard_01"]
+    assert tf["double_checkerboard_01"] > tf["double_checkerboard_mixed"]
+    t = int(round(tb["rescaled_time"] / tb["checkerboard_time_factor"]))
+    L = 512
+    N = L ** 3
+    ell = {}
+    for name, B, mixed in (("cb01", 0, False), ("dcb01", 16, False), ("dcb_mixed", 16, True)):
+        vals = []
+        for r in range(6):
+            lat = qz.Lattice(L, 0x4000_0000 + 800 + r, "bit")
+            if B:
+                lat.set_double_checkerboard(B)
+            lat.set_cycle(mixed)
+            lat.run(t)
+            vals.append(measure.crossing_length(*lat.corr(), N))
+            del lat
+        ell[name] = float(np.mean(vals))
+    same = ell["cb01"] / ell["dcb01"]
+    ratio = ell["dcb01"] / ell["dcb_mixed"]
+    print("cycles: t", t, "mean ell_C", ell, "01 cb/dcb", same, "dcb 01/mixed", ratio, flush=True)
+    assert abs(same - 1.0) < 0.05
+    assert 1.0 < ratio < 1.2
+
+
 def test_batch_584_all_replicas(qz, orc):
     """The 584-replica batch (512 x L64 + 64 x L128 + 8 x L256, seeds
     0x40000000 + r, B every 10 MCS): after 10^3 MCS every replica equals the
