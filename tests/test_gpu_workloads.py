@@ -251,6 +251,35 @@ def test_physics_band_porod_L256(qz):
     assert abs(slope + porod["value"]) < 0.2 * porod["value"]
 
 
+def test_physics_band_early_exponent_L512(qz):
+    """Loose band, not parity: the early growth exponent.
+
+    The paper finds ell(t) growing at early times with an instantaneous
+    exponent compatible with 0.35 - 0.40, and cites 0.43 measured at L = 512
+    as agreeing with its own data there (Results, discussion of the
+    instantaneous exponent).  Four L=512 lattices, the mean ell_C at t = 64,
+    128, ..., 1024 (ell well below L, no finite-size effect): the slope of ln
+    ell against ln t lies in [0.30, 0.50]."""
+    from paper_2305_12161_amd import measure
+    with open(os.path.join(GOLDEN, "paper_physics_bands.json")) as f:
+        lo, hi = json.load(f)["early_alpha"]["value_range"]
+    L = 512
+    N = L ** 3
+    times = [64, 128, 256, 512, 1024]
+    ells = np.zeros((4, len(times)))
+    for r in range(4):
+        lat = qz.Lattice(L, 0x4000_0000 + 900 + r, "bit")
+        for k, t in enumerate(times):
+            lat.run(t - lat.t)
+            ells[r, k] = measure.crossing_length(*lat.corr(), N)
+        del lat
+    mean = ells.mean(axis=0)
+    alpha = float(np.polyfit(np.log(times), np.log(mean), 1)[0])
+    print("early exponent: t", times, "mean ell_C", mean.tolist(), "alpha", alpha,
+          "paper", lo, "-", hi, flush=True)
+    assert 0.30 < alpha < 0.50
+
+
 def test_physics_band_cycle_time_factors_L512(qz):
     """Loose bands, not parity: the paper's time factors order the methods.
 
