@@ -649,8 +649,9 @@ __host__ __device__ inline uint32_t swap_span(uint32_t W) { return (W & 15u) == 
 
 // P16: W is a multiple of 16, so pieces are 16 blocks and a piece is
 // complete after every kAhead = 8 pairs, at the same step of the unrolled
-// pair loop: the stores then sit at one place in the loop, and only the first
-// load after them waits for all memory operations in flight.
+// pair loop.  With the stores at one place in the loop (and no early exit)
+// each step waits only for its own oldest load; with a flush the compiler
+// cannot place, every step waited for everything in flight.
 template <bool P16>
 __global__ void __launch_bounds__(256) k_bit_swap_xy(uint32_t L, uint32_t W, const uint32_t *P0,
                                                     const uint32_t *P1, uint32_t *Q0, uint32_t *Q1)
