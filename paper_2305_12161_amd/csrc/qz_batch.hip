@@ -20,6 +20,23 @@ namespace {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// A value the caller knows to be the same in every active lane of the wave,
+// read from the first one into a scalar register (so that the arithmetic on
+// it runs on the scalar unit).
+__device__ __forceinline__ uint32_t wave_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint64_t wave_u64(uint64_t v)
+{
+    return ((uint64_t)wave_u32((uint32_t)(v >> 32)) << 32) | wave_u32((uint32_t)v);
+}
+template <class T>
+__device__ __forceinline__ T *wave_ptr(T *p)
+{
+    return reinterpret_cast<T *>(wave_u64(reinterpret_cast<uintptr_t>(p)));
+}
+
 // The body of one workgroup's sweep.  WK = words per colour row when the
 // rows are 1, 2 or 4 words long (L = 64, 128, 256): a lane's quad then holds
 // whole rows, so its x-neighbour words are its own and its y-neighbour words

@@ -142,23 +142,6 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
     return v;
 }
 
-// A value the caller knows to be the same in every active lane of the wave,
-// read from the first one into a scalar register (so that the arithmetic on
-// it runs on the scalar unit).
-__device__ __forceinline__ uint32_t wave_u32(uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
-__device__ __forceinline__ uint64_t wave_u64(uint64_t v)
-{
-    return ((uint64_t)wave_u32((uint32_t)(v >> 32)) << 32) | wave_u32((uint32_t)v);
-}
-template <class T>
-__device__ __forceinline__ T *wave_ptr(T *p)
-{
-    return reinterpret_cast<T *>(wave_u64(reinterpret_cast<uintptr_t>(p)));
-}
-
 // Map a linear block id to a tile so that consecutive tiles stay on one XCD.
 // Workgroups are dealt round-robin over the 8 XCDs; tile = xcd*(n/8) + k.
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nblocks)
